@@ -1,0 +1,22 @@
+"""FP64 CPU oracle for the anelastic pressure projection.
+
+TEST INFRASTRUCTURE ONLY. This package is the plain, slow reference that the
+HIP path is checked against. Only the tests, the smoke check and the bench's
+CPU-baseline leg may import it; the product path never does.
+
+Parity pinned: every function here is checked against brute force, a library
+closed form, manufactured solutions, continuum convergence and invariants in
+tests/test_oracle_pins.py.
+"""
+from .projection import (  # noqa: F401
+    vertical_grid,
+    divergence,
+    gradient,
+    tridiag_coefficients,
+    modified_wavenumbers,
+    forward_spectrum,
+    solve_columns,
+    inverse_spectrum,
+    project,
+    weighted_energy,
+)

@@ -1,0 +1,427 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+The paper (Sec. 4) says only that the pressure solve is a forward horizontal
+FFT, a vertical ODE per wavenumber and a backward FFT; it prints no equation,
+worked example or value. The oracle is therefore pinned against:
+
+  P-brute  dense matrices of D and G assembled cell by cell from the
+           C-grid definitions (code separate from the spectral oracle) and a
+           dense gauge-constrained solve, on tiny grids;
+  P-DCT    uniform dz and constant rho0: the operator is diagonalised by
+           DFT x DFT x DCT-II, solved with scipy's dct;
+  P-mfg    manufactured solutions (known p plus a discretely divergence-free
+           part built from a streamfunction);
+  P-inv    invariants (divergence-free output, gauge, per-level means, energy
+           identity, idempotence, linearity, lid);
+  P-conv   second-order convergence to a continuum closed form;
+  P-2D     nz = 1 reduces to the textbook periodic Poisson solve;
+  P-col    nx = ny = 1 reduces to a cumulative sum in z (plus a hand-derived
+           golden fixture).
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.fft as sfft
+
+import oracle
+import oracle.projection as op
+import synth
+from tests.helpers import relerr
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ----------------------------------------------------------------------------
+# Dense assembly from the definitions (independent of oracle/)
+# ----------------------------------------------------------------------------
+def _face_density(dz, rho0):
+    # rho0 on the face between cells k and k+1, linear in z: the weights are
+    # the distances to the two centres, dz_{k+1}/2 and dz_k/2.
+    return (dz[1:] * rho0[:-1] + dz[:-1] * rho0[1:]) / (dz[:-1] + dz[1:])
+
+
+def dense_operators(g):
+    nx, ny, nz = g.nx, g.ny, g.nz
+    N = nx * ny * nz
+    cell = lambda k, j, i: (k * ny + (j % ny)) * nx + (i % nx)
+    rw = _face_density(g.dz, g.rho0)
+    dzc = 0.5 * (g.dz[:-1] + g.dz[1:])
+    D = np.zeros((N, 3 * N))
+    G = np.zeros((3 * N, N))
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                r = cell(k, j, i)
+                D[r, cell(k, j, i)] += g.rho0[k] / g.dx
+                D[r, cell(k, j, i - 1)] -= g.rho0[k] / g.dx
+                D[r, N + cell(k, j, i)] += g.rho0[k] / g.dy
+                D[r, N + cell(k, j - 1, i)] -= g.rho0[k] / g.dy
+                if k <= nz - 2:
+                    D[r, 2 * N + cell(k, j, i)] += rw[k] / g.dz[k]
+                if k >= 1:
+                    D[r, 2 * N + cell(k - 1, j, i)] -= rw[k - 1] / g.dz[k]
+                G[cell(k, j, i), cell(k, j, i + 1)] += 1.0 / g.dx
+                G[cell(k, j, i), cell(k, j, i)] -= 1.0 / g.dx
+                G[N + cell(k, j, i), cell(k, j + 1, i)] += 1.0 / g.dy
+                G[N + cell(k, j, i), cell(k, j, i)] -= 1.0 / g.dy
+                if k <= nz - 2:
+                    G[2 * N + cell(k, j, i), cell(k + 1, j, i)] += 1.0 / dzc[k]
+                    G[2 * N + cell(k, j, i), cell(k, j, i)] -= 1.0 / dzc[k]
+    return D, G
+
+
+def dense_project(g, u, v, w):
+    """Gauge-constrained dense solve: [L 1; g^T 0][p; mu] = [b; 0] with
+    L = D G and g the cell volumes dz_k (so sum dz p = 0)."""
+    N = g.points
+    D, G = dense_operators(g)
+    L = D @ G
+    ustar = np.concatenate([u.ravel(), v.ravel(), w.ravel()])
+    b = D @ ustar
+    vol = np.repeat(g.dz, g.nx * g.ny)
+    K = np.zeros((N + 1, N + 1))
+    K[:N, :N] = L
+    K[:N, N] = 1.0
+    K[N, :N] = vol
+    sol = np.linalg.solve(K, np.concatenate([b, [0.0]]))
+    p = sol[:N]
+    uo = ustar - G @ p
+    shp = (g.nz, g.ny, g.nx)
+    wo = uo[2 * N:].reshape(shp).copy()
+    wo[-1] = 0.0
+    return uo[:N].reshape(shp), uo[N:2 * N].reshape(shp), wo, p.reshape(shp), b.reshape(shp)
+
+
+BRUTE_GRIDS = [(4, 4, 3), (5, 3, 4), (6, 4, 5), (8, 8, 6), (1, 1, 4), (4, 4, 1),
+               (3, 2, 2), (9, 6, 3), (2, 3, 5)]
+
+
+def brute_error(nx, ny, nz, seed):
+    rng = np.random.default_rng(seed)
+    g = synth.random_grid(rng, nx, ny, nz, stretch=(1.0, 1.3))
+    u, v, w = synth.random_fields(rng, g)
+    ref = dense_project(g, u, v, w)
+    out = oracle.project(u, v, w, g.dx, g.dy, g.dz, g.rho0)
+    # velocities relative to the input scale (an output field can be ~0, e.g.
+    # w on a single column); p relative to itself
+    vscale = max(np.max(np.abs(u)), np.max(np.abs(v)), np.max(np.abs(w)))
+    errs = [np.max(np.abs(out[t] - ref[t])) / vscale for t in range(3)]
+    return max(errs + [relerr(out[3], ref[3])])
+
+
+@pytest.mark.parametrize("shape", BRUTE_GRIDS)
+def test_brute_force_dense_solve(shape):
+    assert brute_error(*shape, seed=sum(shape)) <= 1e-12
+
+
+def test_brute_force_divergence_matches_dense():
+    rng = np.random.default_rng(7)
+    g = synth.random_grid(rng, 5, 4, 6)
+    u, v, w = synth.random_fields(rng, g)
+    D, _ = dense_operators(g)
+    b_ref = (D @ np.concatenate([u.ravel(), v.ravel(), w.ravel()])).reshape(u.shape)
+    assert relerr(oracle.divergence(u, v, w, g.dx, g.dy, g.dz, g.rho0), b_ref) <= 1e-14
+
+
+# ----------------------------------------------------------------------------
+# Library closed form: uniform dz, constant rho0 -> DFT x DFT x DCT-II
+# ----------------------------------------------------------------------------
+def dct_solve(b, dx, dy, dz, rho):
+    nz, ny, nx = b.shape
+    m = np.arange(nx // 2 + 1)
+    n = np.arange(ny)
+    q = np.arange(nz)
+    ev = ((4 / dx ** 2) * np.sin(np.pi * m / nx) ** 2)[None, None, :] \
+        + ((4 / dy ** 2) * np.sin(np.pi * n / ny) ** 2)[None, :, None] \
+        + ((4 / dz ** 2) * np.sin(np.pi * q / (2 * nz)) ** 2)[:, None, None]
+    spec = sfft.dct(np.fft.rfft2(b, axes=(1, 2)), type=2, axis=0, norm="ortho")
+    ev[0, 0, 0] = 1.0
+    spec = -spec / (rho * ev)
+    spec[0, 0, 0] = 0.0
+    return np.fft.irfft2(sfft.idct(spec, type=2, axis=0, norm="ortho"), s=(ny, nx), axes=(1, 2))
+
+
+def test_dct_closed_form_at_c0():
+    wl = synth.make_workload("c0")
+    m = wl.members[0]
+    g = m.grid
+    out = oracle.project(m.u, m.v, m.w, g.dx, g.dy, g.dz, g.rho0, intermediates=True)
+    p_ref = dct_solve(out["b"], g.dx, g.dy, 20.0, 1.0)
+    assert relerr(out["p"], p_ref) <= 1e-12
+
+
+def test_dct_closed_form_constant_rho():
+    rng = np.random.default_rng(11)
+    g = synth.Grid(12, 18, 10, 30.0, 45.0, np.full(10, 7.0), np.full(10, 1.7))
+    u, v, w = synth.random_fields(rng, g)
+    out = oracle.project(u, v, w, g.dx, g.dy, g.dz, g.rho0, intermediates=True)
+    assert relerr(out["p"], dct_solve(out["b"], g.dx, g.dy, 7.0, 1.7)) <= 1e-12
+
+
+# ----------------------------------------------------------------------------
+# Manufactured solutions
+# ----------------------------------------------------------------------------
+def manufactured(g, m0, n0, seed, mean_mode=False):
+    rng = np.random.default_rng(seed)
+    zw = np.concatenate([[0.0], np.cumsum(g.dz)])
+    zc = 0.5 * (zw[:-1] + zw[1:])
+    H = zw[-1]
+    prof = np.cos(2.3 * zc / H) + 0.4 * (zc / H) ** 2 - 0.1
+    if mean_mode:
+        prof = prof - np.sum(g.dz * prof) / H
+        p_true = np.broadcast_to(prof[:, None, None], (g.nz, g.ny, g.nx)).copy()
+    else:
+        cx = np.cos(2 * np.pi * m0 * (np.arange(g.nx) + 0.5) / g.nx)
+        cy = np.cos(2 * np.pi * n0 * (np.arange(g.ny) + 0.5) / g.ny)
+        p_true = prof[:, None, None] * np.outer(cy, cx)[None]
+    dzc = zc[1:] - zc[:-1]
+    gx = (np.roll(p_true, -1, 2) - p_true) / g.dx
+    gy = (np.roll(p_true, -1, 1) - p_true) / g.dy
+    gz = np.zeros_like(p_true)
+    gz[:-1] = np.diff(p_true, axis=0) / dzc[:, None, None]
+    psi = rng.standard_normal((g.nz, g.ny, g.nx))        # at cell corners
+    us = (psi - np.roll(psi, 1, 1)) / g.dy
+    vs = -(psi - np.roll(psi, 1, 2)) / g.dx
+    return p_true, us, vs, gx + us, gy + vs, gz
+
+
+@pytest.mark.parametrize("m0,n0", [(1, 0), (3, 2), (0, 5)])
+def test_manufactured_c1_vertical_grid(m0, n0):
+    base = synth.make_grid("c1")
+    g = synth.Grid(32, 24, base.nz, 40.0, 30.0, base.dz, base.rho0)
+    p_true, us, vs, u, v, w = manufactured(g, m0, n0, seed=m0 * 10 + n0)
+    uo, vo, wo, p = oracle.project(u, v, w, g.dx, g.dy, g.dz, g.rho0)
+    assert relerr(p, p_true) <= 1e-12
+    assert relerr(uo, us) <= 1e-12 and relerr(vo, vs) <= 1e-12
+    assert np.max(np.abs(wo)) <= 1e-12 * np.max(np.abs(w))
+
+
+def test_manufactured_mean_mode():
+    base = synth.make_grid("c1")
+    g = synth.Grid(16, 16, base.nz, 25.0, 25.0, base.dz, base.rho0)
+    p_true, us, vs, u, v, w = manufactured(g, 0, 0, seed=3, mean_mode=True)
+    uo, vo, wo, p = oracle.project(u, v, w, g.dx, g.dy, g.dz, g.rho0)
+    assert relerr(p, p_true) <= 1e-12
+    assert relerr(uo, us) <= 1e-12
+    assert np.max(np.abs(wo)) <= 1e-12 * np.max(np.abs(w))
+
+
+def test_manufactured_c4_worst_conditioned_column():
+    # c4's vertical grid (5 m -> 100 m over 160 levels) and horizontal
+    # length (2048 x 25 m), coarsely sampled in x and y: the (1, 0) and (0, 1)
+    # columns have the same smallest lambda as at full size.
+    base = synth.make_grid("c4")
+    g = synth.Grid(32, 32, base.nz, 2048 * 25.0 / 32, 2048 * 25.0 / 32, base.dz, base.rho0)
+    for (m0, n0) in [(1, 0), (1, 1)]:
+        p_true, us, vs, u, v, w = manufactured(g, m0, n0, seed=5)
+        uo, vo, wo, p = oracle.project(u, v, w, g.dx, g.dy, g.dz, g.rho0)
+        assert relerr(p, p_true) <= 1e-10
+        assert relerr(uo, us) <= 1e-10
+
+
+# ----------------------------------------------------------------------------
+# Invariants
+# ----------------------------------------------------------------------------
+def _inv_case(name):
+    if name == "c0":
+        m = synth.make_workload("c0").members[0]
+        return m.grid, m.u, m.v, m.w
+    if name == "c1":
+        m = synth.make_workload("c1").members[0]
+        return m.grid, m.u, m.v, m.w
+    rng = np.random.default_rng(99)
+    g = synth.random_grid(rng, 27, 12, 9, stretch=(1.0, 1.2))
+    return (g,) + synth.random_fields(rng, g)
+
+
+@pytest.mark.parametrize("case", ["c0", "c1", "odd"])
+def test_invariants(case):
+    g, u, v, w = _inv_case(case)
+    uo, vo, wo, p = oracle.project(u, v, w, g.dx, g.dy, g.dz, g.rho0)
+    div = oracle.divergence(uo, vo, wo, g.dx, g.dy, g.dz, g.rho0)
+    assert np.max(np.abs(div)) <= 1e-12
+    # gauge: dz-weighted volume sum of p is zero
+    assert abs(np.sum(g.dz[:, None, None] * p)) <= 1e-12 * np.sum(g.dz[:, None, None] * np.abs(p))
+    # horizontal mean of w vanishes on every face; means of u and v unchanged
+    assert np.max(np.abs(wo.mean(axis=(1, 2)))) <= 1e-13 * np.max(np.abs(w))
+    assert np.allclose(uo.mean(axis=(1, 2)), u.mean(axis=(1, 2)), rtol=0, atol=1e-13 * np.abs(u).max())
+    assert np.allclose(vo.mean(axis=(1, 2)), v.mean(axis=(1, 2)), rtol=0, atol=1e-13 * np.abs(v).max())
+    assert np.all(wo[-1] == 0.0)
+    # energy identity E(u*) = E(u) + E(u* - u): the projection is orthogonal
+    e_in = oracle.weighted_energy(u, v, w, g.dz, g.rho0)
+    e_out = oracle.weighted_energy(uo, vo, wo, g.dz, g.rho0)
+    e_gp = oracle.weighted_energy(u - uo, v - vo, w - wo, g.dz, g.rho0)
+    assert abs(e_in - e_out - e_gp) <= 1e-12 * e_in
+
+
+def test_idempotence_and_linearity():
+    g, u, v, w = _inv_case("odd")
+    a = oracle.project(u, v, w, g.dx, g.dy, g.dz, g.rho0)
+    b = oracle.project(a[0], a[1], a[2], g.dx, g.dy, g.dz, g.rho0)
+    assert np.max(np.abs(b[3])) <= 1e-12 * np.max(np.abs(a[3]))
+    for t in range(3):
+        assert relerr(b[t], a[t]) <= 1e-13
+    rng = np.random.default_rng(5)
+    u2, v2, w2 = synth.random_fields(rng, g)
+    c = oracle.project(u2, v2, w2, g.dx, g.dy, g.dz, g.rho0)
+    d = oracle.project(2.0 * u - 3.0 * u2, 2.0 * v - 3.0 * v2, 2.0 * w - 3.0 * w2,
+                       g.dx, g.dy, g.dz, g.rho0)
+    for t in range(4):
+        assert relerr(d[t], 2.0 * a[t] - 3.0 * c[t]) <= 1e-12
+
+
+# ----------------------------------------------------------------------------
+# Continuum convergence (second order)
+# ----------------------------------------------------------------------------
+def _continuum_errors(stretched):
+    L, H = 1000.0, 1000.0
+    kx, ky = 2 * np.pi / L, 4 * np.pi / L
+    errs = []
+    for n in (8, 16, 32, 64):
+        nx = ny = 2 * n
+        nz = n
+        xi = np.linspace(0.0, 1.0, nz + 1)
+        zw = H * (xi + 0.3 * xi * (1 - xi)) if stretched else H * xi
+        dz = np.diff(zw)
+        zc = 0.5 * (zw[:-1] + zw[1:])
+        dx = L / nx
+        xc = (np.arange(nx) + 0.5) * dx
+        xf = xc + 0.5 * dx
+        yc, yf = xc, xf
+        P = lambda x, y, z: np.cos(kx * x)[None, None, :] * np.cos(ky * y)[None, :, None] \
+            * np.cos(np.pi * z / H)[:, None, None]
+        p_ex = P(xc, yc, zc)
+        u = (-kx * np.sin(kx * xf))[None, None, :] * np.cos(ky * yc)[None, :, None] * np.cos(np.pi * zc / H)[:, None, None]
+        v = np.cos(kx * xc)[None, None, :] * (-ky * np.sin(ky * yf))[None, :, None] * np.cos(np.pi * zc / H)[:, None, None]
+        w = np.cos(kx * xc)[None, None, :] * np.cos(ky * yc)[None, :, None] \
+            * (-np.pi / H * np.sin(np.pi * zw[1:] / H))[:, None, None]
+        w[-1] = 0.0
+        _, _, _, p = oracle.project(u, v, w, dx, dx, dz, np.ones(nz))
+        errs.append(np.max(np.abs(p - p_ex)))
+    return errs
+
+
+@pytest.mark.parametrize("stretched", [False, True])
+def test_second_order_convergence(stretched):
+    errs = _continuum_errors(stretched)
+    rates = [errs[i] / errs[i + 1] for i in range(len(errs) - 1)]
+    assert min(rates) >= 3.5, (errs, rates)
+
+
+# ----------------------------------------------------------------------------
+# Reductions to textbook cases
+# ----------------------------------------------------------------------------
+def test_nz1_is_2d_poisson():
+    rng = np.random.default_rng(21)
+    g = synth.Grid(24, 18, 1, 20.0, 35.0, np.array([13.0]), np.array([0.8]))
+    u, v, w = synth.random_fields(rng, g)
+    out = oracle.project(u, v, w, g.dx, g.dy, g.dz, g.rho0, intermediates=True)
+    bh = np.fft.fft2(out["b"][0])
+    kx = np.fft.fftfreq(g.nx) * g.nx
+    ky = np.fft.fftfreq(g.ny) * g.ny
+    lam = (4 / g.dx ** 2) * np.sin(np.pi * kx / g.nx)[None, :] ** 2 \
+        + (4 / g.dy ** 2) * np.sin(np.pi * ky / g.ny)[:, None] ** 2
+    lam[0, 0] = 1.0
+    ph = -bh / (0.8 * lam)
+    ph[0, 0] = 0.0
+    assert relerr(out["p"][0], np.fft.ifft2(ph).real) <= 1e-13
+
+
+def test_single_column_cumulative_sum():
+    # nx = ny = 1: D(u) = 0 forces every interior flux to 0, so w -> 0, u and
+    # v are untouched and p_{k+1} - p_k = dzc_k w*_k, then the gauge.
+    rng = np.random.default_rng(4)
+    g = synth.random_grid(rng, 1, 1, 9)
+    u, v, w = synth.random_fields(rng, g)
+    uo, vo, wo, p = oracle.project(u, v, w, g.dx, g.dy, g.dz, g.rho0)
+    zc = np.concatenate([[0.0], np.cumsum(g.dz)])[:-1] + 0.5 * g.dz
+    pc = np.concatenate([[0.0], np.cumsum(np.diff(zc) * w[:-1, 0, 0])])
+    pc -= np.sum(g.dz * pc) / g.dz.sum()
+    assert relerr(p[:, 0, 0], pc) <= 1e-14
+    assert np.array_equal(uo, u) and np.array_equal(vo, v)
+    assert np.max(np.abs(wo)) <= 1e-14 * np.max(np.abs(w))
+
+
+def _read_golden(name):
+    vals = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                key, rest = line.split("=", 1)
+                vals[key.strip()] = np.array([float(t) for t in rest.split()])
+    return vals
+
+
+def test_golden_single_column():
+    gd = _read_golden("single_column_nz3.txt")
+    dz, rho0, w = gd["dz"], gd["rho0"], gd["w"]
+    shape = (3, 1, 1)
+    uo, vo, wo, p = oracle.project(np.zeros(shape), np.zeros(shape), w.reshape(shape),
+                                   7.0, 9.0, dz, rho0)
+    assert np.allclose(p.ravel(), gd["p"], rtol=0, atol=1e-14)
+    assert np.allclose(wo.ravel(), 0.0, atol=1e-15)
+
+
+# ----------------------------------------------------------------------------
+# The pins catch plausible mistakes planted in the oracle (CPU only)
+# ----------------------------------------------------------------------------
+def _spectral_k2(nx, ny, dx, dy):
+    m = np.arange(nx // 2 + 1)
+    n = np.fft.fftfreq(ny) * ny
+    return (2 * np.pi * m / (nx * dx)) ** 2, (2 * np.pi * n / (ny * dy)) ** 2
+
+
+def _swapped_coeffs(dz, rho0):
+    a, c = _ORIG["tridiag_coefficients"](dz, rho0)
+    return c, a
+
+
+def _plain_mean_rhow(dz, rho0):
+    vg = _ORIG["vertical_grid"](dz, rho0)
+    vg["rhow"] = 0.5 * (vg["rho0"][:-1] + vg["rho0"][1:])
+    return vg
+
+
+def _no_rho_div(u, v, w, dx, dy, dz, rho0):
+    b = _ORIG["divergence"](u, v, w, dx, dy, dz, rho0)
+    hor = (u - np.roll(u, 1, 2)) / dx + (v - np.roll(v, 1, 1)) / dy
+    return b - (np.asarray(rho0)[:, None, None] - 1.0) * hor
+
+
+def _flipped_grad(p, dx, dy, dz):
+    gx, gy, gz = _ORIG["gradient"](p, dx, dy, dz)
+    return gx, gy, -gz
+
+
+def _unnormalised_inverse(P, nx, ny, workers=None):
+    return _ORIG["inverse_spectrum"](P, nx, ny, workers) * 2.0
+
+
+def _no_gauge(B0, dz, rho0):
+    P = _ORIG["solve_mean_column"](B0, dz, rho0)
+    return P + 0.37
+
+
+_ORIG = {k: getattr(op, k) for k in ("modified_wavenumbers", "tridiag_coefficients",
+                                     "vertical_grid", "divergence", "gradient",
+                                     "inverse_spectrum", "solve_mean_column")}
+
+MUTANTS = {
+    "spectral_k2": ("modified_wavenumbers", _spectral_k2),
+    "swapped_a_c": ("tridiag_coefficients", _swapped_coeffs),
+    "midpoint_face_density": ("vertical_grid", _plain_mean_rhow),
+    "rho_dropped_horizontal": ("divergence", _no_rho_div),
+    "flipped_vertical_gradient": ("gradient", _flipped_grad),
+    "wrong_inverse_scale": ("inverse_spectrum", _unnormalised_inverse),
+    "gauge_missing": ("solve_mean_column", _no_gauge),
+}
+
+
+@pytest.mark.parametrize("mutant", sorted(MUTANTS))
+def test_pins_catch_planted_mistake(mutant, monkeypatch):
+    name, fn = MUTANTS[mutant]
+    monkeypatch.setattr(op, name, fn)
+    worst = max(brute_error(6, 4, 5, seed=1), brute_error(5, 3, 4, seed=2))
+    assert worst > 1e-6, f"planted mistake {mutant} went unnoticed ({worst})"
