@@ -1,0 +1,193 @@
+/*
+ * monc.h -- C ABI of the MI355X (gfx950) anelastic pressure projection.
+ *
+ * The operation is the pressure solve of a cloud-resolving model's dynamical
+ * core: the paper ("A highly scalable Met Office NERC Cloud model", Sec. 4,
+ * "Performance and scaling", the paragraph on the FFT pressure solver)
+ * describes it as a forward FFT over the periodic horizontal, a vertical ODE
+ * per horizontal wavenumber solved in Fourier space, and a backward FFT; the
+ * single-precision solver variant is discussed in the same section and a
+ * mixed-precision solver with a double-precision restart and self-tuning in
+ * Sec. 5 ("Conclusions and further work").
+ *
+ * Discrete problem solved (Arakawa C-grid, second-order finite volume):
+ *   arrays are C-order (nz, ny, nx), x fastest, periodic in x and y;
+ *   p[k,j,i] at the cell centre, u at the east face x=(i+1)dx, v at the north
+ *   face y=(j+1)dy, w[k] at the top face of cell k (w[nz-1] is the rigid lid,
+ *   and the bottom lid w=0 at z=0 is implicit);
+ *   dz[k] is the thickness of layer k, dzc_k = (dz_k + dz_{k+1})/2, rho0[k]
+ *   the reference density at cell centres, interpolated linearly in z to the
+ *   faces (rhow_k);
+ *   D(u) = rho0_k[(u_i-u_{i-1})/dx + (v_j-v_{j-1})/dy]
+ *          + (rhow_k w_k - rhow_{k-1} w_{k-1})/dz_k        (zero flux at lids)
+ *   G(p) = ((p_{i+1}-p_i)/dx, (p_{j+1}-p_j)/dy, (p_{k+1}-p_k)/dzc_k)
+ *   find p with D(G p) = D(u*) and sum_k dz_k sum_ij p = 0 (gauge), then
+ *   u = u* - G p (dt folded into p) and w[nz-1] = 0.
+ * Horizontally this is diagonal in the discrete Fourier basis with the
+ * modified wavenumbers (4/dx^2)sin^2(pi m/nx) + (4/dy^2)sin^2(pi n/ny); per
+ * wavenumber it leaves one real tridiagonal system in z (complex right-hand
+ * side), solved in FP64 on every path.
+ *
+ * Thread safety: all functions may be called from several host threads; a
+ * plan (and a batch) must not be used by two calls that overlap in time
+ * (one workspace per plan). Every enqueueing call is asynchronous on the
+ * given stream and never synchronises the host.
+ */
+#ifndef MONC_H
+#define MONC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct monc_plan monc_plan;   /* opaque; owns its device workspace */
+
+/* precision of a plan */
+enum {
+  MONC_FP64 = 0,   /* double storage and arithmetic everywhere */
+  MONC_MIXED = 1   /* float storage; FP32 stencils and FFTs; FP64 tridiagonal
+                      and mean mode; one FP64 iterative-refinement step */
+};
+
+/* status codes */
+enum {
+  MONC_OK = 0,
+  MONC_EINVAL = -1,        /* bad argument (null/misaligned/aliased pointer,
+                              bad size, mixed dtypes in a batch, ...)        */
+  MONC_EUNSUPPORTED = -2,  /* valid but unsupported (e.g. a size above the
+                              kernel limits)                                 */
+  MONC_ENOMEM = -3,        /* device allocation failed                       */
+  MONC_EHIP = -4           /* a HIP runtime call or launch failed            */
+};
+
+/* Limits of this build: nx, ny in [1, 8192] with no prime factor above 3
+ * (FFT radices 2, 3, 4, 8); nz in [1, 1024]; batches of 1..256 members. */
+#define MONC_MAX_N 8192
+#define MONC_MAX_NZ 1024
+#define MONC_MAX_BATCH 256
+
+/*
+ * Create a plan on the current HIP device.
+ *   nx, ny, nz : grid size;
+ *   dx, dy     : horizontal spacings [m], finite and > 0;
+ *   dz[nz]     : layer thicknesses [m], finite and > 0 (host pointer);
+ *   rho0[nz]   : reference density at layer centres, finite and > 0 (host);
+ *   dtype      : MONC_FP64 or MONC_MIXED.
+ * dz and rho0 are copied; the caller keeps ownership. All argument checks
+ * run on the host before any HIP call. Returns NULL on failure and sets the
+ * message read by monc_last_error().
+ */
+monc_plan* monc_plan_create(int nx, int ny, int nz, double dx, double dy,
+                            const double* dz, const double* rho0, int dtype);
+
+/* Release a plan and its device memory (NULL is ignored). The caller must
+ * make sure no enqueued work still uses the plan. */
+void monc_plan_destroy(monc_plan* plan);
+
+/*
+ * Project one field in place.
+ *   u, v, w : device arrays (nz, ny, nx) of double (MONC_FP64) or float
+ *             (MONC_MIXED), updated in place; w[nz-1] is ignored on input and
+ *             written as 0;
+ *   p       : device array (nz, ny, nx), output only, gauge sum dz*p = 0;
+ *   stream  : a hipStream_t (NULL = the default stream).
+ * All four pointers must be non-null, 16-byte aligned and non-overlapping.
+ * The mixed path returns p = p1 + delta rounded to float, and u = u* -
+ * G(p1) - G(delta) evaluated in FP64 before rounding, so differencing the
+ * returned float p does not reproduce u to full accuracy.
+ * Returns MONC_OK, MONC_EINVAL or MONC_EHIP.
+ */
+int monc_project(monc_plan* plan, void* u, void* v, void* w, void* p, void* stream);
+
+/*
+ * Project `count` independent members in one go. plans[i] is member i's
+ * plan; u[i], v[i], w[i], p[i] are its arrays as in monc_project. All plans
+ * must share one dtype and one device. The whole batch is validated before
+ * anything is enqueued (all or nothing). The first call for a given set of
+ * plans and pointers builds a schedule (grouped per-phase launches covering
+ * every member) and captures it in a HIP graph; later calls with the same
+ * plans and pointers replay the graph, others re-capture.
+ */
+int monc_project_batched(monc_plan* const* plans, int count,
+                         void* const* u, void* const* v, void* const* w,
+                         void* const* p, void* stream);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* monc_last_error(void);
+
+/* ---------------------------------------------------------------------
+ * Introspection, tuning, profiling and stage-wise access (used by tests
+ * and the benchmark; not needed for ordinary use).
+ * ------------------------------------------------------------------- */
+
+/* Geometry of the spectral workspace: complex values are stored (nz, ny,
+ * row) with row = *row_len >= nx/2+1 (padded); *elem_bytes is 16 (FP64) or
+ * 8 (MIXED). Returns the number of complex elements, or 0 for NULL plan. */
+size_t monc_spectral_layout(const monc_plan* plan, int* row_len, int* elem_bytes);
+
+/* Stage-wise execution on caller buffers (all device pointers, sizes as in
+ * monc_project; `spec` holds monc_spectral_layout() complex elements):
+ *   MONC_STAGE_FORWARD  bufs = {u, v, w, spec}: spec = unnormalised real 2-D
+ *                       FFT per level of D(u) (m = 0..nx/2 of each row);
+ *   MONC_STAGE_SOLVE    bufs = {spec}: in place, each wavenumber column
+ *                       replaced by its tridiagonal solution times 1/(nx ny)
+ *                       (the (0,0) column with the gauge);
+ *   MONC_STAGE_INVERSE  bufs = {spec, p}: p = inverse real 2-D FFT without
+ *                       extra scaling (imaginary parts of self-conjugate bins
+ *                       ignored); spec is overwritten;
+ *   MONC_STAGE_GRADIENT bufs = {p, u, v, w}: u -= G p (in place), w lid = 0;
+ *   MONC_STAGE_RESIDUAL bufs = {u, v, w, p, spec} (MIXED only): spec = FFT of
+ *                       the FP64 residual D(u) - D(G p) rounded to float.
+ * Returns MONC_OK, MONC_EINVAL or MONC_EHIP. */
+enum {
+  MONC_STAGE_FORWARD = 1,
+  MONC_STAGE_SOLVE = 2,
+  MONC_STAGE_INVERSE = 3,
+  MONC_STAGE_GRADIENT = 4,
+  MONC_STAGE_RESIDUAL = 5
+};
+int monc_debug_stage(monc_plan* plan, int stage, void* const* bufs, int nbufs, void* stream);
+
+/* Kernel identifiers used by the profiler. */
+enum {
+  MONC_K_DIV_FFTX = 0,    /* divergence fused with the x-direction r2c FFT  */
+  MONC_K_FFTY_FWD = 1,    /* y-direction c2c forward FFT                    */
+  MONC_K_TRIDIAG = 2,     /* FP64 tridiagonal solve per wavenumber column   */
+  MONC_K_FFTY_INV = 3,    /* y-direction c2c inverse FFT                    */
+  MONC_K_IFFTX = 4,       /* x-direction c2r inverse FFT (writes p)         */
+  MONC_K_GRAD = 5,        /* pressure-gradient correction (FP64 path)       */
+  MONC_K_RESID_FFTX = 6,  /* FP64 residual fused with the x r2c FFT (MIXED) */
+  MONC_K_GRAD_FINAL = 7,  /* p1 + delta and FP64 gradient correction (MIXED)*/
+  MONC_K_COUNT = 8
+};
+const char* monc_kernel_name(int kernel_id);
+
+/* Per-kernel timing with HIP events recorded on the launch stream around
+ * every launch of the kernels in `mask` (bit i = kernel id i); 0 disables.
+ * Applies to monc_project/monc_project_batched calls on this plan (for a
+ * batch, the first member's plan controls it). */
+int monc_profile_enable(monc_plan* plan, unsigned mask);
+/* Wait for the recorded events, add their durations per kernel into
+ * ms[MONC_K_COUNT] and launches[MONC_K_COUNT], and clear the record. */
+int monc_profile_read(monc_plan* plan, double* ms, int* launches);
+
+/* Autotune the tile parameters of a plan (FFT elements per thread, y-FFT
+ * columns per workgroup, tridiagonal lanes per column) by timing the
+ * candidates on scratch buffers on `stream`; the choice is stored in the plan
+ * and in the JSON cache named by the MONC_TUNE_CACHE environment variable
+ * (if set). Synchronises the stream. Returns MONC_OK or an error. */
+int monc_autotune(monc_plan* plan, void* stream);
+
+/* Current tile parameters of a plan: out[0] = x-FFT elements per thread,
+ * out[1] = y-FFT elements per thread, out[2] = y-FFT columns per workgroup,
+ * out[3] = tridiagonal lanes per column. */
+int monc_plan_params(const monc_plan* plan, int* out4);
+/* Set them (values are checked; 0 keeps the current value). */
+int monc_plan_set_params(monc_plan* plan, const int* in4);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MONC_H */

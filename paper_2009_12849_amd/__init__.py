@@ -1,0 +1,209 @@
+"""Python binding of libmonc.so, the MI355X anelastic pressure projection.
+
+Argument marshalling only: every step of the projection runs in the HIP
+kernels of the library. PyTorch supplies device memory and streams; tensors
+must be contiguous CUDA (HIP) tensors of the plan's dtype (float64 for
+"f64", float32 for "mixed") and shape (nz, ny, nx).
+
+The library must have been built in-tree (``python -m
+paper_2009_12849_amd.build``); nothing here falls back to another
+implementation when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+__all__ = ["Plan", "project_batched", "lib", "last_error", "MoncError",
+           "FP64", "MIXED", "STAGE_FORWARD", "STAGE_SOLVE", "STAGE_INVERSE",
+           "STAGE_GRADIENT", "STAGE_RESIDUAL", "KERNELS"]
+
+FP64, MIXED = 0, 1
+OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP = 0, -1, -2, -3, -4
+STAGE_FORWARD, STAGE_SOLVE, STAGE_INVERSE, STAGE_GRADIENT, STAGE_RESIDUAL = 1, 2, 3, 4, 5
+KERNELS = ["div_fftx", "ffty_fwd", "tridiag", "ffty_inv", "ifftx", "grad",
+           "resid_fftx", "grad_final"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmonc.so")
+_lib = None
+
+
+class MoncError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"monc error {code}: {msg}")
+        self.code = code
+
+
+def lib() -> ctypes.CDLL:
+    """Load libmonc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2009_12849_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, ip, dp = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double)
+    L.monc_plan_create.restype = vp
+    L.monc_plan_create.argtypes = [ip, ip, ip, ctypes.c_double, ctypes.c_double, dp, dp, ip]
+    L.monc_plan_destroy.restype = None
+    L.monc_plan_destroy.argtypes = [vp]
+    L.monc_project.restype = ip
+    L.monc_project.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.monc_project_batched.restype = ip
+    L.monc_project_batched.argtypes = [ctypes.POINTER(vp), ip] + [ctypes.POINTER(vp)] * 4 + [vp]
+    L.monc_last_error.restype = ctypes.c_char_p
+    L.monc_last_error.argtypes = []
+    L.monc_spectral_layout.restype = ctypes.c_size_t
+    L.monc_spectral_layout.argtypes = [vp, ctypes.POINTER(ip), ctypes.POINTER(ip)]
+    L.monc_debug_stage.restype = ip
+    L.monc_debug_stage.argtypes = [vp, ip, ctypes.POINTER(vp), ip, vp]
+    L.monc_kernel_name.restype = ctypes.c_char_p
+    L.monc_kernel_name.argtypes = [ip]
+    L.monc_profile_enable.restype = ip
+    L.monc_profile_enable.argtypes = [vp, ctypes.c_uint]
+    L.monc_profile_read.restype = ip
+    L.monc_profile_read.argtypes = [vp, dp, ctypes.POINTER(ip)]
+    L.monc_autotune.restype = ip
+    L.monc_autotune.argtypes = [vp, vp]
+    L.monc_plan_params.restype = ip
+    L.monc_plan_params.argtypes = [vp, ctypes.POINTER(ip)]
+    L.monc_plan_set_params.restype = ip
+    L.monc_plan_set_params.argtypes = [vp, ctypes.POINTER(ip)]
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().monc_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise MoncError(rc, last_error())
+
+
+def _dtype_code(dtype) -> int:
+    if dtype in ("f64", "fp64", FP64):
+        return FP64
+    if dtype in ("mixed", MIXED):
+        return MIXED
+    raise ValueError(f"unknown dtype {dtype!r}")
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+class Plan:
+    """Projection plan for one grid (see include/monc.h)."""
+
+    def __init__(self, nx: int, ny: int, nz: int, dx: float, dy: float,
+                 dz: Sequence[float], rho0: Sequence[float], dtype="f64"):
+        L = lib()
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.dtype = _dtype_code(dtype)
+        dzv = np.ascontiguousarray(dz, dtype=np.float64)
+        rv = np.ascontiguousarray(rho0, dtype=np.float64)
+        if dzv.shape != (self.nz,) or rv.shape != (self.nz,):
+            raise ValueError("dz and rho0 must have nz entries")
+        dptr = ctypes.POINTER(ctypes.c_double)
+        h = L.monc_plan_create(self.nx, self.ny, self.nz, float(dx), float(dy),
+                               dzv.ctypes.data_as(dptr), rv.ctypes.data_as(dptr), self.dtype)
+        if not h:
+            raise MoncError(EINVAL, last_error())
+        self._h = ctypes.c_void_p(h)
+
+    @classmethod
+    def from_grid(cls, grid, dtype="f64") -> "Plan":
+        return cls(grid.nx, grid.ny, grid.nz, grid.dx, grid.dy, grid.dz, grid.rho0, dtype)
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    @property
+    def torch_dtype(self):
+        import torch
+        return torch.float64 if self.dtype == FP64 else torch.float32
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().monc_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _field(self, t, name):
+        if t.dtype != self.torch_dtype or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous CUDA tensor of {self.torch_dtype}")
+        if tuple(t.shape) != (self.nz, self.ny, self.nx):
+            raise ValueError(f"{name} must have shape (nz, ny, nx) = {(self.nz, self.ny, self.nx)}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def project(self, u, v, w, p, stream=None):
+        """In-place projection of u, v, w; p receives the pressure."""
+        args = [self._field(t, n) for t, n in ((u, "u"), (v, "v"), (w, "w"), (p, "p"))]
+        _check(lib().monc_project(self._h, *args, ctypes.c_void_p(_stream_handle(stream))))
+
+    # -- introspection / stages / profiling / tuning ---------------------
+    def spectral_layout(self):
+        row, eb = ctypes.c_int(), ctypes.c_int()
+        n = lib().monc_spectral_layout(self._h, ctypes.byref(row), ctypes.byref(eb))
+        return int(n), row.value, eb.value
+
+    def spectral_buffer(self):
+        """A zeroed device tensor with the spectral layout (nz, ny, row)."""
+        import torch
+        n, row, eb = self.spectral_layout()
+        dt = torch.complex128 if self.dtype == FP64 else torch.complex64
+        return torch.zeros((self.nz, self.ny, row), dtype=dt, device="cuda")
+
+    def debug_stage(self, stage: int, bufs, stream=None):
+        arr = (ctypes.c_void_p * len(bufs))(*[ctypes.c_void_p(b.data_ptr()) for b in bufs])
+        _check(lib().monc_debug_stage(self._h, stage, arr, len(bufs), ctypes.c_void_p(_stream_handle(stream))))
+
+    def profile_enable(self, mask: int):
+        _check(lib().monc_profile_enable(self._h, mask))
+
+    def profile_read(self):
+        ms = (ctypes.c_double * len(KERNELS))()
+        cnt = (ctypes.c_int * len(KERNELS))()
+        _check(lib().monc_profile_read(self._h, ms, cnt))
+        return {KERNELS[i]: (ms[i], cnt[i]) for i in range(len(KERNELS)) if cnt[i]}
+
+    def autotune(self, stream=None):
+        _check(lib().monc_autotune(self._h, ctypes.c_void_p(_stream_handle(stream))))
+
+    @property
+    def params(self):
+        out = (ctypes.c_int * 4)()
+        _check(lib().monc_plan_params(self._h, out))
+        return list(out)
+
+    @params.setter
+    def params(self, vals):
+        arr = (ctypes.c_int * 4)(*[int(x) for x in vals])
+        _check(lib().monc_plan_set_params(self._h, arr))
+
+
+def project_batched(plans: Sequence[Plan], us, vs, ws, ps, stream=None):
+    """Project every member in one graph launch (see include/monc.h)."""
+    n = len(plans)
+    VP = ctypes.c_void_p * n
+    hs = VP(*[pl.handle for pl in plans])
+    fields = []
+    for name, ts in (("u", us), ("v", vs), ("w", ws), ("p", ps)):
+        fields.append(VP(*[pl._field(t, f"{name}[{i}]") for i, (pl, t) in enumerate(zip(plans, ts))]))
+    _check(lib().monc_project_batched(hs, n, *fields, ctypes.c_void_p(_stream_handle(stream))))

@@ -1,0 +1,963 @@
+// C ABI of the projection library: plans, the single and batched projection,
+// stage-wise access, per-kernel profiling and the autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/monc.h"
+#include "kernels.h"
+#include "monc_types.h"
+#include "plan_math.h"
+
+using namespace monc;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) return fail(MONC_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// profiler: HIP event pairs around the launches of selected kernels
+// ---------------------------------------------------------------------------
+struct Profiler {
+  unsigned mask = 0;
+  struct Rec {
+    int id;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  std::mutex mu;
+
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  ~Profiler() {
+    for (auto& r : recs) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+static std::atomic<unsigned long long> g_plan_ids{1};
+static std::once_flag g_attr_once;
+
+struct monc_plan {
+  unsigned long long id = 0;
+  unsigned long long version = 0;  // bumped when tile parameters change
+  int nx = 0, ny = 0, nz = 0, dtype = 0, device = 0;
+  double dx = 0, dy = 0;
+  std::vector<double> dz, rho0;
+  int ex = 8, ey = 8, ymt = 0, triP = 0;  // tile parameters
+  MemberDesc h{};                          // host copy with device pointers
+  MemberDesc* d_desc = nullptr;            // device copy
+  void* d_tables = nullptr;
+  void* d_spec = nullptr;
+  double* d_wbuf = nullptr;
+  size_t spec_elems = 0;
+  Profiler prof;
+};
+
+static size_t elem_bytes(int dtype) { return dtype == MONC_FP64 ? 8 : 4; }
+static size_t cplx_bytes(int dtype) { return 2 * elem_bytes(dtype); }
+
+static int pow2_floor(int x) {
+  int p = 1;
+  while (p * 2 <= x) p *= 2;
+  return p;
+}
+
+// Rows per lane of the tridiagonal kernel for nz rows on P lanes: the
+// smallest compiled row count (2..8, 12, 16) that covers them, 0 if none.
+static int tri_rows(int nz, int P) {
+  const int s = std::max(2, (nz + P - 1) / P);
+  if (s <= 8) return s;
+  if (s <= 12) return 12;
+  if (s <= kTriSmax) return kTriSmax;
+  return 0;
+}
+
+// Derive FFT plans and tile parameters from (ex, ey, ymt, triP); 0 = default.
+static int configure_tiles(monc_plan* pl, int ex, int ey, int ymt, int triP) {
+  MemberDesc& h = pl->h;
+  FftPlan fx{}, fy{};
+  if (!radix_plan(pl->nx, fx) || !radix_plan(pl->ny, fy))
+    return fail(MONC_EUNSUPPORTED, "no radix plan for nx=%d ny=%d", pl->nx, pl->ny);
+  if (ex <= 0) ex = pl->ex;
+  if (ey <= 0) ey = pl->ey;
+  if (ex > kGenericElems || ey > kGenericElems)
+    return fail(MONC_EINVAL, "elements per thread must be <= %d (got %d, %d)", kGenericElems, ex, ey);
+  if (!fft_threads(fx, ex) || !fft_threads(fy, ey))
+    return fail(MONC_EUNSUPPORTED, "FFT of nx=%d or ny=%d needs more than 1024 threads", pl->nx, pl->ny);
+  const size_t cb = cplx_bytes(pl->dtype);
+  // y-FFT columns per workgroup: 128-byte rows by default, bounded by the
+  // workgroup size (1024) and 64 KB of LDS
+  const int mt_cap = std::max(1, std::min(1024 / fy.nt, (int)(65536 / (pl->ny * cb))));
+  if (ymt <= 0) ymt = pl->ymt > 0 ? pl->ymt : (int)(128 / cb);
+  if (ymt > 64) return fail(MONC_EINVAL, "y-FFT columns per workgroup must be <= 64 (got %d)", ymt);
+  ymt = std::max(1, std::min(ymt, mt_cap));
+  const int nxh = pl->nx / 2 + 1;
+  ymt = std::min(ymt, pow2_floor(nxh) * 2);
+  // tridiagonal lanes per column: default = fewest lanes with <= 8 rows each
+  if (triP <= 0) triP = pl->triP;
+  if (triP <= 0) {
+    triP = 1;
+    while ((pl->nz + triP - 1) / triP > 8 && triP < kTriPmax) triP *= 2;
+  }
+  if (triP & (triP - 1) || triP > kTriPmax)
+    return fail(MONC_EINVAL, "tridiagonal lanes per column must be a power of 2 <= %d (got %d)", kTriPmax, triP);
+  const int s = tri_rows(pl->nz, triP);
+  if (s == 0)
+    return fail(MONC_EINVAL, "%d lanes leave %d rows per lane (max %d)", triP, (pl->nz + triP - 1) / triP, kTriSmax);
+  pl->ex = ex;
+  pl->ey = ey;
+  pl->ymt = ymt;
+  pl->triP = triP;
+  h.fx = fx;
+  h.fy = fy;
+  h.ymt = ymt;
+  h.triP = triP;
+  h.tris = s;
+  h.tricw = 256 / triP;
+  return MONC_OK;
+}
+
+static int upload_desc(monc_plan* pl) {
+  HIP_TRY(hipMemcpy(pl->d_desc, &pl->h, sizeof(MemberDesc), hipMemcpyHostToDevice));
+  return MONC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// tuning cache (flat JSON object: "arch:nx,ny,nz:dtype" -> [ex, ey, ymt, triP])
+// ---------------------------------------------------------------------------
+static std::mutex g_cache_mu;
+
+static std::string cache_key(const monc_plan* pl) {
+  char buf[128];
+  std::snprintf(buf, sizeof buf, "gfx950:%d,%d,%d:%s", pl->nx, pl->ny, pl->nz,
+                pl->dtype == MONC_FP64 ? "fp64" : "mixed");
+  return buf;
+}
+
+static std::map<std::string, std::vector<int>> read_cache(const char* path) {
+  std::map<std::string, std::vector<int>> out;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return out;
+  std::string s;
+  char buf[4096];
+  size_t n;
+  while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) s.append(buf, n);
+  std::fclose(f);
+  size_t pos = 0;
+  while ((pos = s.find('"', pos)) != std::string::npos) {
+    const size_t end = s.find('"', pos + 1);
+    if (end == std::string::npos) break;
+    std::string key = s.substr(pos + 1, end - pos - 1);
+    const size_t lb = s.find('[', end), rb = s.find(']', end);
+    if (lb == std::string::npos || rb == std::string::npos || rb < lb) break;
+    std::vector<int> vals;
+    const char* p = s.c_str() + lb + 1;
+    while (p < s.c_str() + rb) {
+      char* q = nullptr;
+      long v = std::strtol(p, &q, 10);
+      if (q == p) { ++p; continue; }
+      vals.push_back((int)v);
+      p = q;
+    }
+    out[key] = vals;
+    pos = rb + 1;
+  }
+  return out;
+}
+
+static void write_cache(const char* path, const std::map<std::string, std::vector<int>>& m) {
+  std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return;
+  std::fprintf(f, "{\n");
+  size_t i = 0;
+  for (auto& kv : m) {
+    std::fprintf(f, "  \"%s\": [", kv.first.c_str());
+    for (size_t j = 0; j < kv.second.size(); ++j) std::fprintf(f, "%s%d", j ? ", " : "", kv.second[j]);
+    std::fprintf(f, "]%s\n", ++i < m.size() ? "," : "");
+  }
+  std::fprintf(f, "}\n");
+  std::fclose(f);
+  std::rename(tmp.c_str(), path);
+}
+
+// ---------------------------------------------------------------------------
+// plan creation
+// ---------------------------------------------------------------------------
+extern "C" monc_plan* monc_plan_create(int nx, int ny, int nz, double dx, double dy, const double* dz,
+                                       const double* rho0, int dtype) {
+  std::string err;
+  const int rc = check_plan_args(nx, ny, nz, dx, dy, dz, rho0, dtype, err);
+  if (rc != MONC_OK) {
+    g_err = err;
+    return nullptr;
+  }
+  auto pl = std::make_unique<monc_plan>();
+  pl->id = g_plan_ids.fetch_add(1);
+  pl->nx = nx;
+  pl->ny = ny;
+  pl->nz = nz;
+  pl->dx = dx;
+  pl->dy = dy;
+  pl->dtype = dtype;
+  pl->dz.assign(dz, dz + nz);
+  pl->rho0.assign(rho0, rho0 + nz);
+  MemberDesc& h = pl->h;
+  h.nx = nx;
+  h.ny = ny;
+  h.nz = nz;
+  h.nxh = nx / 2 + 1;
+  h.nxp = (h.nxh + 7) / 8 * 8;
+  h.dtype = dtype;
+  h.nrow = (long long)nz * ny;
+  h.plane = (long long)ny * h.nxp;
+  h.rdx = 1.0 / dx;
+  h.rdy = 1.0 / dy;
+  h.inv_nxny = 1.0 / ((double)nx * (double)ny);
+  h.rdxf = (float)h.rdx;
+  h.rdyf = (float)h.rdy;
+  // tile parameters (cached tuning first)
+  int ex = 0, ey = 0, ymt = 0, triP = 0;
+  if (const char* path = std::getenv("MONC_TUNE_CACHE")) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto m = read_cache(path);
+    auto it = m.find(cache_key(pl.get()));
+    if (it != m.end() && it->second.size() == 4) {
+      ex = it->second[0];
+      ey = it->second[1];
+      ymt = it->second[2];
+      triP = it->second[3];
+    }
+  }
+  if (configure_tiles(pl.get(), ex, ey, ymt, triP) != MONC_OK &&
+      configure_tiles(pl.get(), 8, 8, 0, 0) != MONC_OK)
+    return nullptr;
+
+  // host tables
+  VerticalTables vt = vertical_tables(nz, dz, rho0);
+  h.rH = vt.rH;
+  std::vector<double> lamx = modified_wavenumbers(nx, h.nxh, dx);
+  std::vector<double> lamy = modified_wavenumbers(ny, ny, dy);
+  std::vector<double> twx = twiddles(nx), twy = twiddles(ny);
+
+  // one device blob for the tables: 7 FP64 vertical, 3 FP32 vertical,
+  // lamx, lamy, twiddles in the storage precision
+  const size_t eb = elem_bytes(dtype);
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  size_t off = 0;
+  const size_t o_v64 = off; off += al(7 * (size_t)nz * 8);
+  const size_t o_v32 = off; off += al(3 * (size_t)nz * 4);
+  const size_t o_lx = off; off += al((size_t)h.nxh * 8);
+  const size_t o_ly = off; off += al((size_t)ny * 8);
+  const size_t o_tx = off; off += al((size_t)nx * 2 * eb);
+  const size_t o_ty = off; off += al((size_t)ny * 2 * eb);
+  const size_t tables_bytes = off;
+  std::vector<unsigned char> blob(tables_bytes, 0);
+  double* v64 = reinterpret_cast<double*>(blob.data() + o_v64);
+  const std::vector<double>* cols[7] = {&vt.rho0, &vt.rhow, &vt.rdz, &vt.rdzc, &vt.dz, &vt.ta, &vt.tc};
+  for (int t = 0; t < 7; ++t) std::memcpy(v64 + (size_t)t * nz, cols[t]->data(), (size_t)nz * 8);
+  float* v32 = reinterpret_cast<float*>(blob.data() + o_v32);
+  for (int k = 0; k < nz; ++k) {
+    v32[k] = (float)vt.rho0[k];
+    v32[nz + k] = (float)vt.rhow[k];
+    v32[2 * nz + k] = (float)vt.rdz[k];
+  }
+  std::memcpy(blob.data() + o_lx, lamx.data(), lamx.size() * 8);
+  std::memcpy(blob.data() + o_ly, lamy.data(), lamy.size() * 8);
+  auto put_tw = [&](size_t o, const std::vector<double>& tw) {
+    if (dtype == MONC_FP64) {
+      std::memcpy(blob.data() + o, tw.data(), tw.size() * 8);
+    } else {
+      float* f = reinterpret_cast<float*>(blob.data() + o);
+      for (size_t i = 0; i < tw.size(); ++i) f[i] = (float)tw[i];
+    }
+  };
+  put_tw(o_tx, twx);
+  put_tw(o_ty, twy);
+
+  // device side
+  std::call_once(g_attr_once, [] { init_kernel_attributes(); });
+  if (hipGetDevice(&pl->device) != hipSuccess) {
+    fail(MONC_EHIP, "hipGetDevice failed (no usable HIP device)");
+    return nullptr;
+  }
+  pl->spec_elems = (size_t)nz * ny * h.nxp;
+  auto release = [&]() {
+    if (pl->d_tables) (void)hipFree(pl->d_tables);
+    if (pl->d_spec) (void)hipFree(pl->d_spec);
+    if (pl->d_wbuf) (void)hipFree(pl->d_wbuf);
+    if (pl->d_desc) (void)hipFree(pl->d_desc);
+  };
+  if (hipMalloc(&pl->d_tables, tables_bytes) != hipSuccess ||
+      hipMalloc(&pl->d_spec, pl->spec_elems * cplx_bytes(dtype)) != hipSuccess ||
+      hipMalloc((void**)&pl->d_desc, sizeof(MemberDesc)) != hipSuccess ||
+      (dtype == MONC_MIXED &&
+       hipMalloc((void**)&pl->d_wbuf, (size_t)nx * ny * nz * sizeof(double)) != hipSuccess)) {
+    (void)hipGetLastError();
+    release();
+    fail(MONC_ENOMEM, "device allocation failed for a %dx%dx%d plan", nx, ny, nz);
+    return nullptr;
+  }
+  if (hipMemcpy(pl->d_tables, blob.data(), tables_bytes, hipMemcpyHostToDevice) != hipSuccess) {
+    release();
+    fail(MONC_EHIP, "table upload failed");
+    return nullptr;
+  }
+  unsigned char* base = reinterpret_cast<unsigned char*>(pl->d_tables);
+  const double* d64 = reinterpret_cast<const double*>(base + o_v64);
+  h.rho0 = d64;
+  h.rhow = d64 + nz;
+  h.rdz = d64 + 2 * (size_t)nz;
+  h.rdzc = d64 + 3 * (size_t)nz;
+  h.dz = d64 + 4 * (size_t)nz;
+  h.ta = d64 + 5 * (size_t)nz;
+  h.tc = d64 + 6 * (size_t)nz;
+  const float* d32 = reinterpret_cast<const float*>(base + o_v32);
+  h.rho0f = d32;
+  h.rhowf = d32 + nz;
+  h.rdzf = d32 + 2 * (size_t)nz;
+  h.lamx = reinterpret_cast<const double*>(base + o_lx);
+  h.lamy = reinterpret_cast<const double*>(base + o_ly);
+  h.twx = base + o_tx;
+  h.twy = base + o_ty;
+  h.spec = pl->d_spec;
+  h.wbuf = pl->d_wbuf;
+  if (upload_desc(pl.get()) != MONC_OK) {
+    release();
+    return nullptr;
+  }
+  g_err.clear();
+  return pl.release();
+}
+
+static void drop_batch_cache_for(unsigned long long plan_id);
+
+extern "C" void monc_plan_destroy(monc_plan* pl) {
+  if (!pl) return;
+  drop_batch_cache_for(pl->id);
+  if (pl->d_tables) (void)hipFree(pl->d_tables);
+  if (pl->d_spec) (void)hipFree(pl->d_spec);
+  if (pl->d_wbuf) (void)hipFree(pl->d_wbuf);
+  if (pl->d_desc) (void)hipFree(pl->d_desc);
+  delete pl;
+}
+
+extern "C" const char* monc_last_error(void) { return g_err.c_str(); }
+
+extern "C" size_t monc_spectral_layout(const monc_plan* pl, int* row_len, int* eb) {
+  if (!pl) return 0;
+  if (row_len) *row_len = pl->h.nxp;
+  if (eb) *eb = (int)cplx_bytes(pl->dtype);
+  return pl->spec_elems;
+}
+
+extern "C" const char* monc_kernel_name(int id) {
+  static const char* names[MONC_K_COUNT] = {"div_fftx", "ffty_fwd",  "tridiag",    "ffty_inv",
+                                            "ifftx",    "grad",      "resid_fftx", "grad_final"};
+  if (id < 0 || id >= MONC_K_COUNT) return "";
+  return names[id];
+}
+
+// ---------------------------------------------------------------------------
+// grouped launches
+// ---------------------------------------------------------------------------
+struct GroupMember {
+  const MemberDesc* h;  // host copy
+  const MemberDesc* d;  // device copy
+  IoPtrs io;
+};
+
+struct Group {
+  std::vector<GroupMember> mem;
+  bool fp64 = true;
+};
+
+enum Phase { PH_XFWD, PH_RESID, PH_YFWD, PH_TRI, PH_YINV, PH_XINV, PH_XINV_CORR, PH_GRAD, PH_GRAD_MIXED };
+
+static int phase_kernel_id(Phase ph) {
+  switch (ph) {
+    case PH_XFWD: return MONC_K_DIV_FFTX;
+    case PH_RESID: return MONC_K_RESID_FFTX;
+    case PH_YFWD: return MONC_K_FFTY_FWD;
+    case PH_TRI: return MONC_K_TRIDIAG;
+    case PH_YINV: return MONC_K_FFTY_INV;
+    case PH_XINV: case PH_XINV_CORR: return MONC_K_IFFTX;
+    case PH_GRAD: return MONC_K_GRAD;
+    case PH_GRAD_MIXED: return MONC_K_GRAD_FINAL;
+  }
+  return 0;
+}
+
+static bool is_xphase(Phase ph) { return ph == PH_XFWD || ph == PH_RESID || ph == PH_XINV || ph == PH_XINV_CORR; }
+static bool is_yphase(Phase ph) { return ph == PH_YFWD || ph == PH_YINV; }
+
+// Launch shape of one member in one phase. Members whose shapes agree share
+// a launch; `variant` identifies the kernel instance (compile-time length or
+// the runtime-length kernel) and `block` its workgroup size.
+struct Shape {
+  int variant = 0;   // compile-time length, or 0 for the runtime-length kernel
+  int block = 256;
+  size_t lds = 0;
+  long long blocks = 0;
+};
+
+static size_t xpad_len_host(int n, size_t cb) { return (size_t)n + (size_t)(n >> (cb == 16 ? 3 : 4)) + 1; }
+
+static Shape member_shape(const MemberDesc& d, Phase ph, bool fp64) {
+  const size_t cb = fp64 ? 16 : 8;
+  Shape s;
+  if (is_xphase(ph)) {
+    const long long pairs = (d.nrow + 1) / 2;
+    if (ct_supported(d.nx)) {
+      const int nt = ct_threads_host(d.nx);
+      const int ipw = std::max(1, 256 / nt);
+      s.variant = d.nx;
+      s.block = ipw * nt;
+      s.lds = (size_t)ipw * xpad_len_host(d.nx, cb) * cb;
+      s.blocks = (pairs + ipw - 1) / ipw;
+    } else {
+      s.block = std::max(256, (d.fx.nt + 63) / 64 * 64);
+      const int ipw = s.block / d.fx.nt;
+      s.lds = (size_t)ipw * d.nx * cb;
+      s.blocks = (pairs + ipw - 1) / ipw;
+    }
+  } else if (is_yphase(ph)) {
+    if (ct_supported(d.ny)) {
+      const int nt = ct_threads_host(d.ny);
+      const int mt = std::max(1, std::min(d.ymt, 1024 / nt));
+      s.variant = d.ny;
+      s.block = mt * nt;
+      s.lds = (size_t)d.ny * mt * cb;
+      s.blocks = (long long)d.nz * ((d.nxh + mt - 1) / mt);
+    } else {
+      s.block = std::max(64, (d.ymt * d.fy.nt + 63) / 64 * 64);
+      s.lds = (size_t)d.ny * d.ymt * cb;
+      s.blocks = (long long)d.nz * ((d.nxh + d.ymt - 1) / d.ymt);
+    }
+  } else if (ph == PH_TRI) {
+    s.variant = d.tris;
+    s.lds = (size_t)256 * (d.tris + 1) * 16;
+    s.blocks = ((long long)d.ny * d.nxh + d.tricw - 1) / d.tricw;
+  } else {
+    const long long nh = (long long)d.nx * d.ny;
+    s.blocks = ((nh + 255) / 256) * ((d.nz + kGradChunk - 1) / kGradChunk);
+  }
+  return s;
+}
+
+static int launch_one(const Group& g, const std::vector<int>& idx, Phase ph, const Shape& sh, void* stream,
+                      Profiler* prof) {
+  LaunchArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.nmem = (int)idx.size();
+  long long blocks = 0;
+  size_t lds = 0;
+  int block = sh.block;
+  for (size_t t = 0; t < idx.size(); ++t) {
+    const GroupMember& m = g.mem[idx[t]];
+    const Shape s = member_shape(*m.h, ph, g.fp64);
+    a.mem[t] = m.d;
+    a.io[t] = m.io;
+    a.block_start[t] = (int)blocks;
+    blocks += s.blocks;
+    lds = std::max(lds, s.lds);
+    block = std::max(block, s.block);
+    if (blocks > (1LL << 31) - 1) return fail(MONC_EUNSUPPORTED, "grid too large");
+  }
+  a.block_start[idx.size()] = (int)blocks;
+  if (block > 1024) return fail(MONC_EUNSUPPORTED, "launch needs %d threads per workgroup", block);
+  if (lds > 160 * 1024) return fail(MONC_EUNSUPPORTED, "phase needs %zu bytes of LDS", lds);
+  if (blocks == 0) return MONC_OK;
+  const int grid = (int)blocks;
+  const int kid = phase_kernel_id(ph);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const bool timed = prof && (prof->mask >> kid & 1u);
+  if (timed) {
+    std::lock_guard<std::mutex> lk(prof->mu);
+    e0 = prof->get();
+    e1 = prof->get();
+    if (e0) (void)hipEventRecord(e0, (hipStream_t)stream);
+  }
+  const int v = sh.variant;
+  switch (ph) {
+    case PH_XFWD: launch_xfwd(a, grid, block, lds, g.fp64, 0, v, stream); break;
+    case PH_RESID: launch_xfwd(a, grid, block, lds, false, 1, v, stream); break;
+    case PH_YFWD: launch_ffty(a, grid, block, lds, g.fp64, false, v, stream); break;
+    case PH_YINV: launch_ffty(a, grid, block, lds, g.fp64, true, v, stream); break;
+    case PH_TRI: launch_tridiag(a, grid, lds, g.fp64, v, stream); break;
+    case PH_XINV: launch_xinv(a, grid, block, lds, g.fp64, 0, v, stream); break;
+    case PH_XINV_CORR: launch_xinv(a, grid, block, lds, false, 1, v, stream); break;
+    case PH_GRAD: launch_grad(a, grid, g.fp64, 0, stream); break;
+    case PH_GRAD_MIXED: launch_grad(a, grid, false, 1, stream); break;
+  }
+  hipError_t le = hipGetLastError();
+  if (timed) {
+    std::lock_guard<std::mutex> lk(prof->mu);
+    if (e1) (void)hipEventRecord(e1, (hipStream_t)stream);
+    if (e0 && e1) prof->recs.push_back({kid, e0, e1});
+  }
+  if (le != hipSuccess) return fail(MONC_EHIP, "launch of %s failed: %s", monc_kernel_name(kid), hipGetErrorString(le));
+  return MONC_OK;
+}
+
+// One phase for every member of the group: members are partitioned by kernel
+// instance and workgroup size, and each partition (up to kMaxLaunchMembers
+// members) is one launch.
+static int launch_phase(const Group& g, Phase ph, void* stream, Profiler* prof) {
+  std::vector<std::pair<std::pair<int, int>, std::vector<int>>> parts;
+  std::vector<Shape> shapes;
+  for (int i = 0; i < (int)g.mem.size(); ++i) {
+    const Shape s = member_shape(*g.mem[i].h, ph, g.fp64);
+    // the compile-time kernels need blockDim to match each member exactly
+    const std::pair<int, int> key{s.variant, s.variant ? s.block : 0};
+    size_t pi = 0;
+    while (pi < parts.size() && (parts[pi].first != key || parts[pi].second.size() >= (size_t)kMaxLaunchMembers)) ++pi;
+    if (pi == parts.size()) {
+      parts.push_back({key, {}});
+      shapes.push_back(s);
+    }
+    parts[pi].second.push_back(i);
+  }
+  for (size_t pi = 0; pi < parts.size(); ++pi) {
+    const int rc = launch_one(g, parts[pi].second, ph, shapes[pi], stream, prof);
+    if (rc != MONC_OK) return rc;
+  }
+  return MONC_OK;
+}
+
+static int run_phases(const std::vector<Group>& groups, const std::vector<Phase>& phases, void* stream,
+                      Profiler* prof) {
+  for (Phase ph : phases)
+    for (const auto& g : groups) {
+      const int rc = launch_phase(g, ph, stream, prof);
+      if (rc != MONC_OK) return rc;
+    }
+  return MONC_OK;
+}
+
+static const std::vector<Phase>& full_sequence(bool fp64) {
+  static const std::vector<Phase> f64 = {PH_XFWD, PH_YFWD, PH_TRI, PH_YINV, PH_XINV, PH_GRAD};
+  static const std::vector<Phase> mixed = {PH_XFWD, PH_YFWD, PH_TRI, PH_YINV, PH_XINV, PH_RESID,
+                                           PH_YFWD, PH_TRI,  PH_YINV, PH_XINV_CORR, PH_GRAD_MIXED};
+  return fp64 ? f64 : mixed;
+}
+
+// ---------------------------------------------------------------------------
+// pointer checks
+// ---------------------------------------------------------------------------
+static int check_fields(const monc_plan* pl, void* const* ptrs, int n, const char* what) {
+  const size_t bytes = (size_t)pl->nx * pl->ny * pl->nz * elem_bytes(pl->dtype);
+  for (int i = 0; i < n; ++i) {
+    if (!ptrs[i]) return fail(MONC_EINVAL, "%s: pointer %d is null", what, i);
+    if (reinterpret_cast<uintptr_t>(ptrs[i]) % 16 != 0)
+      return fail(MONC_EINVAL, "%s: pointer %d is not 16-byte aligned", what, i);
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j) {
+      const uintptr_t a = reinterpret_cast<uintptr_t>(ptrs[i]), b = reinterpret_cast<uintptr_t>(ptrs[j]);
+      if (a < b + bytes && b < a + bytes) return fail(MONC_EINVAL, "%s: arrays %d and %d overlap", what, i, j);
+    }
+  return MONC_OK;
+}
+
+static int check_device(const monc_plan* pl) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(MONC_EHIP, "hipGetDevice failed");
+  if (dev != pl->device)
+    return fail(MONC_EINVAL, "plan was created on device %d but device %d is current", pl->device, dev);
+  return MONC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// single projection
+// ---------------------------------------------------------------------------
+extern "C" int monc_project(monc_plan* pl, void* u, void* v, void* w, void* p, void* stream) {
+  if (!pl) return fail(MONC_EINVAL, "plan is null");
+  void* ptrs[4] = {u, v, w, p};
+  int rc = check_fields(pl, ptrs, 4, "monc_project");
+  if (rc != MONC_OK) return rc;
+  rc = check_device(pl);
+  if (rc != MONC_OK) return rc;
+  Group g;
+  g.fp64 = pl->dtype == MONC_FP64;
+  g.mem.push_back({&pl->h, pl->d_desc, IoPtrs{u, v, w, p, pl->d_spec}});
+  std::vector<Group> groups{g};
+  return run_phases(groups, full_sequence(g.fp64), stream, pl->prof.mask ? &pl->prof : nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// stage-wise access
+// ---------------------------------------------------------------------------
+extern "C" int monc_debug_stage(monc_plan* pl, int stage, void* const* bufs, int nbufs, void* stream) {
+  if (!pl) return fail(MONC_EINVAL, "plan is null");
+  if (!bufs) return fail(MONC_EINVAL, "bufs is null");
+  int rc = check_device(pl);
+  if (rc != MONC_OK) return rc;
+  const bool fp64 = pl->dtype == MONC_FP64;
+  auto need = [&](int n) { return nbufs == n ? MONC_OK : fail(MONC_EINVAL, "stage %d takes %d buffers (got %d)", stage, n, nbufs); };
+  for (int i = 0; i < nbufs; ++i)
+    if (!bufs[i] || reinterpret_cast<uintptr_t>(bufs[i]) % 16) return fail(MONC_EINVAL, "buffer %d is null or misaligned", i);
+  IoPtrs io{nullptr, nullptr, nullptr, nullptr, nullptr};
+  std::vector<Phase> seq;
+  switch (stage) {
+    case MONC_STAGE_FORWARD:
+      if ((rc = need(4))) return rc;
+      io = IoPtrs{bufs[0], bufs[1], bufs[2], nullptr, bufs[3]};
+      seq = {PH_XFWD, PH_YFWD};
+      break;
+    case MONC_STAGE_SOLVE:
+      if ((rc = need(1))) return rc;
+      io.spec = bufs[0];
+      seq = {PH_TRI};
+      break;
+    case MONC_STAGE_INVERSE:
+      if ((rc = need(2))) return rc;
+      io.spec = bufs[0];
+      io.p = bufs[1];
+      seq = {PH_YINV, PH_XINV};
+      break;
+    case MONC_STAGE_GRADIENT:
+      if ((rc = need(4))) return rc;
+      if (!fp64) return fail(MONC_EINVAL, "the gradient stage takes an FP64 pressure (FP64 plans only)");
+      io = IoPtrs{bufs[1], bufs[2], bufs[3], bufs[0], nullptr};
+      seq = {PH_GRAD};
+      break;
+    case MONC_STAGE_RESIDUAL:
+      if ((rc = need(5))) return rc;
+      if (fp64) return fail(MONC_EINVAL, "the residual stage exists on MIXED plans only");
+      io = IoPtrs{bufs[0], bufs[1], bufs[2], bufs[3], bufs[4]};
+      seq = {PH_RESID, PH_YFWD};
+      break;
+    default:
+      return fail(MONC_EINVAL, "unknown stage %d", stage);
+  }
+  Group g;
+  g.fp64 = fp64;
+  g.mem.push_back({&pl->h, pl->d_desc, io});
+  return run_phases({g}, seq, stream, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// batched projection: grouped launches captured in a HIP graph
+// ---------------------------------------------------------------------------
+struct BatchEntry {
+  std::vector<unsigned long long> key;
+  std::vector<unsigned long long> plan_ids;
+  MemberDesc* d_array = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  unsigned long long last_use = 0;
+  ~BatchEntry() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (d_array) (void)hipFree(d_array);
+  }
+};
+
+static std::mutex g_batch_mu;
+static std::vector<std::unique_ptr<BatchEntry>> g_batches;
+static unsigned long long g_batch_clock = 0;
+static const size_t kBatchCacheSize = 8;
+
+static void drop_batch_cache_for(unsigned long long plan_id) {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  g_batches.erase(std::remove_if(g_batches.begin(), g_batches.end(),
+                                 [&](const std::unique_ptr<BatchEntry>& e) {
+                                   return std::find(e->plan_ids.begin(), e->plan_ids.end(), plan_id) !=
+                                          e->plan_ids.end();
+                                 }),
+                  g_batches.end());
+}
+
+// Members ordered by size (largest first) so the big members' workgroups
+// start first and the small ones fill the tail.
+static std::vector<int> batch_order(monc_plan* const* plans, int count) {
+  std::vector<int> ord(count);
+  for (int i = 0; i < count; ++i) ord[i] = i;
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+    const long long pa = (long long)plans[a]->nx * plans[a]->ny * plans[a]->nz;
+    const long long pb = (long long)plans[b]->nx * plans[b]->ny * plans[b]->nz;
+    return pa > pb;
+  });
+  return ord;
+}
+
+static int build_groups(monc_plan* const* plans, int count, void* const* u, void* const* v, void* const* w,
+                        void* const* p, const MemberDesc* d_array, const std::vector<int>& ord,
+                        std::vector<Group>& groups) {
+  groups.clear();
+  Group g;
+  g.fp64 = plans[0]->dtype == MONC_FP64;
+  for (int t = 0; t < count; ++t) {
+    const int i = ord[t];
+    g.mem.push_back({&plans[i]->h, d_array + t, IoPtrs{u[i], v[i], w[i], p[i], plans[i]->d_spec}});
+  }
+  groups.push_back(std::move(g));
+  return MONC_OK;
+}
+
+extern "C" int monc_project_batched(monc_plan* const* plans, int count, void* const* u, void* const* v,
+                                    void* const* w, void* const* p, void* stream) {
+  if (!plans || !u || !v || !w || !p) return fail(MONC_EINVAL, "null argument array");
+  if (count < 1 || count > MONC_MAX_BATCH) return fail(MONC_EINVAL, "count must be in [1, %d] (got %d)", MONC_MAX_BATCH, count);
+  for (int i = 0; i < count; ++i) {
+    if (!plans[i]) return fail(MONC_EINVAL, "plans[%d] is null", i);
+    if (plans[i]->dtype != plans[0]->dtype) return fail(MONC_EINVAL, "batch mixes dtypes (member %d)", i);
+    if (plans[i]->device != plans[0]->device) return fail(MONC_EINVAL, "batch spans devices (member %d)", i);
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == plans[i]) return fail(MONC_EINVAL, "plan of member %d repeats member %d (one workspace per plan)", i, j);
+    void* ptrs[4] = {u[i], v[i], w[i], p[i]};
+    char what[64];
+    std::snprintf(what, sizeof what, "batch member %d", i);
+    const int rc = check_fields(plans[i], ptrs, 4, what);
+    if (rc != MONC_OK) return rc;
+  }
+  int rc = check_device(plans[0]);
+  if (rc != MONC_OK) return rc;
+  const bool fp64 = plans[0]->dtype == MONC_FP64;
+  Profiler* prof = plans[0]->prof.mask ? &plans[0]->prof : nullptr;
+  const std::vector<int> ord = batch_order(plans, count);
+
+  // key: plan ids, versions and field pointers
+  std::vector<unsigned long long> key;
+  key.reserve(6 * count);
+  for (int i = 0; i < count; ++i) {
+    key.push_back(plans[i]->id);
+    key.push_back(plans[i]->version);
+    key.push_back((unsigned long long)(uintptr_t)u[i]);
+    key.push_back((unsigned long long)(uintptr_t)v[i]);
+    key.push_back((unsigned long long)(uintptr_t)w[i]);
+    key.push_back((unsigned long long)(uintptr_t)p[i]);
+  }
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  BatchEntry* ent = nullptr;
+  for (auto& e : g_batches)
+    if (e->key == key) ent = e.get();
+  if (!ent) {
+    auto e = std::make_unique<BatchEntry>();
+    e->key = key;
+    for (int i = 0; i < count; ++i) e->plan_ids.push_back(plans[i]->id);
+    if (hipMalloc((void**)&e->d_array, sizeof(MemberDesc) * count) != hipSuccess)
+      return fail(MONC_ENOMEM, "batch descriptor allocation failed");
+    std::vector<MemberDesc> hd(count);
+    for (int t = 0; t < count; ++t) hd[t] = plans[ord[t]]->h;
+    HIP_TRY(hipMemcpy(e->d_array, hd.data(), sizeof(MemberDesc) * count, hipMemcpyHostToDevice));
+    if (g_batches.size() >= kBatchCacheSize) {
+      auto oldest = std::min_element(g_batches.begin(), g_batches.end(),
+                                     [](const std::unique_ptr<BatchEntry>& a, const std::unique_ptr<BatchEntry>& b) {
+                                       return a->last_use < b->last_use;
+                                     });
+      g_batches.erase(oldest);
+    }
+    ent = e.get();
+    g_batches.push_back(std::move(e));
+  }
+  ent->last_use = ++g_batch_clock;
+  std::vector<Group> groups;
+  build_groups(plans, count, u, v, w, p, ent->d_array, ord, groups);
+  const auto& seq = full_sequence(fp64);
+  if (prof) return run_phases(groups, seq, stream, prof);  // eager launches when timing kernels
+  if (!ent->exec) {
+    hipStream_t cs = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      (void)hipStreamDestroy(cs);
+      return fail(MONC_EHIP, "hipStreamBeginCapture failed: %s", hipGetErrorString(e));
+    }
+    rc = run_phases(groups, seq, cs, nullptr);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cs, &graph);
+    (void)hipStreamDestroy(cs);
+    if (rc != MONC_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(MONC_EHIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+    ent->graph = graph;
+    HIP_TRY(hipGraphInstantiate(&ent->exec, graph, nullptr, nullptr, 0));
+  }
+  HIP_TRY(hipGraphLaunch(ent->exec, (hipStream_t)stream));
+  return MONC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// profiling
+// ---------------------------------------------------------------------------
+extern "C" int monc_profile_enable(monc_plan* pl, unsigned mask) {
+  if (!pl) return fail(MONC_EINVAL, "plan is null");
+  std::lock_guard<std::mutex> lk(pl->prof.mu);
+  pl->prof.mask = mask;
+  return MONC_OK;
+}
+
+extern "C" int monc_profile_read(monc_plan* pl, double* ms, int* launches) {
+  if (!pl) return fail(MONC_EINVAL, "plan is null");
+  std::lock_guard<std::mutex> lk(pl->prof.mu);
+  int rc = MONC_OK;
+  for (auto& r : pl->prof.recs) {
+    float t = 0.0f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) {
+      rc = fail(MONC_EHIP, "profiling event query failed");
+    } else {
+      if (ms) ms[r.id] += t;
+      if (launches) launches[r.id] += 1;
+    }
+    pl->prof.pool.push_back(r.a);
+    pl->prof.pool.push_back(r.b);
+  }
+  pl->prof.recs.clear();
+  return rc;
+}
+
+// ---------------------------------------------------------------------------
+// tile parameters and autotuning
+// ---------------------------------------------------------------------------
+extern "C" int monc_plan_params(const monc_plan* pl, int* out4) {
+  if (!pl || !out4) return fail(MONC_EINVAL, "null argument");
+  out4[0] = pl->ex;
+  out4[1] = pl->ey;
+  out4[2] = pl->ymt;
+  out4[3] = pl->triP;
+  return MONC_OK;
+}
+
+extern "C" int monc_plan_set_params(monc_plan* pl, const int* in4) {
+  if (!pl || !in4) return fail(MONC_EINVAL, "null argument");
+  for (int i = 0; i < 4; ++i)
+    if (in4[i] < 0) return fail(MONC_EINVAL, "parameter %d is negative", i);
+  const MemberDesc saved = pl->h;
+  const int sv[4] = {pl->ex, pl->ey, pl->ymt, pl->triP};
+  int rc = configure_tiles(pl, in4[0], in4[1], in4[2], in4[3]);
+  if (rc != MONC_OK) {
+    pl->h = saved;
+    pl->ex = sv[0]; pl->ey = sv[1]; pl->ymt = sv[2]; pl->triP = sv[3];
+    return rc;
+  }
+  HIP_TRY(hipDeviceSynchronize());  // in-flight work may still read the old descriptor
+  rc = upload_desc(pl);
+  if (rc == MONC_OK) ++pl->version;
+  return rc;
+}
+
+extern "C" int monc_autotune(monc_plan* pl, void* stream) {
+  if (!pl) return fail(MONC_EINVAL, "plan is null");
+  int rc = check_device(pl);
+  if (rc != MONC_OK) return rc;
+  const size_t bytes = (size_t)pl->nx * pl->ny * pl->nz * elem_bytes(pl->dtype);
+  void* buf[4] = {nullptr, nullptr, nullptr, nullptr};
+  for (auto& b : buf) {
+    if (hipMalloc(&b, bytes) != hipSuccess) {
+      for (auto& c : buf) if (c) (void)hipFree(c);
+      return fail(MONC_ENOMEM, "autotune scratch allocation failed");
+    }
+    (void)hipMemset(b, 0, bytes);
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const unsigned saved_mask = pl->prof.mask;
+  // time every candidate value of one parameter, all else fixed; the cost of
+  // a candidate is the summed time of the kernels that parameter shapes
+  auto measure = [&](const int* prm, unsigned kmask, double& cost) -> int {
+    int r = monc_plan_set_params(pl, prm);
+    if (r != MONC_OK) return r;
+    pl->prof.mask = kmask;
+    for (int it = 0; it < 2; ++it)
+      if ((r = monc_project(pl, buf[0], buf[1], buf[2], buf[3], st)) != MONC_OK) return r;
+    double ms[MONC_K_COUNT] = {0};
+    int cnt[MONC_K_COUNT] = {0};
+    monc_profile_read(pl, nullptr, nullptr);  // drop warm-up records
+    for (int it = 0; it < 4; ++it)
+      if ((r = monc_project(pl, buf[0], buf[1], buf[2], buf[3], st)) != MONC_OK) return r;
+    if ((r = monc_profile_read(pl, ms, cnt)) != MONC_OK) return r;
+    cost = 0.0;
+    for (int k = 0; k < MONC_K_COUNT; ++k) cost += ms[k];
+    return MONC_OK;
+  };
+  int best[4] = {pl->ex, pl->ey, pl->ymt, pl->triP};
+  const unsigned xmask = (1u << MONC_K_DIV_FFTX) | (1u << MONC_K_IFFTX) | (1u << MONC_K_RESID_FFTX);
+  const unsigned ymask = (1u << MONC_K_FFTY_FWD) | (1u << MONC_K_FFTY_INV);
+  const unsigned tmask = 1u << MONC_K_TRIDIAG;
+  struct Axis {
+    int idx;
+    std::vector<int> vals;
+    unsigned mask;
+  };
+  std::vector<int> pvals;
+  for (int P = 1; P <= kTriPmax; P *= 2)
+    if (tri_rows(pl->nz, P) != 0 && (P == 1 || (pl->nz + P - 1) / P >= 2)) pvals.push_back(P);
+  std::vector<Axis> axes = {{0, {2, 4, 8}, xmask}, {1, {2, 4, 8}, ymask}, {2, {1, 2, 4, 8, 16, 32}, ymask},
+                            {3, pvals, tmask}};
+  for (const auto& ax : axes) {
+    double best_cost = 1e300;
+    int best_val = best[ax.idx];
+    for (int val : ax.vals) {
+      int prm[4] = {best[0], best[1], best[2], best[3]};
+      prm[ax.idx] = val;
+      double cost = 0.0;
+      if (measure(prm, ax.mask, cost) != MONC_OK) continue;
+      int eff[4];
+      monc_plan_params(pl, eff);
+      if (eff[ax.idx] != val) continue;  // clamped to another candidate
+      if (cost < best_cost) {
+        best_cost = cost;
+        best_val = val;
+      }
+    }
+    best[ax.idx] = best_val;
+  }
+  pl->prof.mask = saved_mask;
+  for (auto& b : buf) (void)hipFree(b);
+  rc = monc_plan_set_params(pl, best);
+  if (rc != MONC_OK) return rc;
+  if (const char* path = std::getenv("MONC_TUNE_CACHE")) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto m = read_cache(path);
+    m[cache_key(pl)] = {pl->ex, pl->ey, pl->ymt, pl->triP};
+    write_cache(path, m);
+  }
+  return MONC_OK;
+}

@@ -1,0 +1,308 @@
+// Device FFT building blocks for gfx950: complex helpers, radix-2/3/4/8
+// butterflies, and two Stockham engines sharing them:
+//   * CtFft<T, N, NT, INV>: length fixed at compile time, NT threads per
+//     transform, every index folded to constants; values stay in registers
+//     inside a pass and cross threads through LDS between passes. The first
+//     pass takes its inputs from the caller's registers and the last pass
+//     leaves its outputs there, so the kernels read global memory straight
+//     into the first pass and write the last pass straight to global memory.
+//   * fft_lds(): runtime length (any 2^a 3^b), whole transform in LDS; the
+//     fallback for lengths without a compile-time instance.
+// Twiddles exp(-2 pi i t/N) come from a per-plan table built on the host.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "monc_types.h"
+
+namespace monc {
+
+template <typename T> struct V2;
+template <> struct V2<float> { using t = float2; };
+template <> struct V2<double> { using t = double2; };
+template <typename T> using cx = typename V2<T>::t;
+
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+  return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename C> __device__ __forceinline__ C cmulconj(C a, C b) {  // a * conj(b)
+  return C{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <typename C> __device__ __forceinline__ C mul_mi(C a) { return C{a.y, -a.x}; }  // -i a
+template <typename C> __device__ __forceinline__ C mul_pi(C a) { return C{-a.y, a.x}; }  // +i a
+
+// ---------------------------------------------------------------------------
+// small DFTs (forward: exp(-2 pi i rs/R); inverse: exp(+2 pi i rs/R))
+// ---------------------------------------------------------------------------
+template <bool INV, typename C> __device__ __forceinline__ void dft2(C* v) {
+  C a = v[0];
+  v[0] = cadd(a, v[1]);
+  v[1] = csub(a, v[1]);
+}
+
+template <bool INV, typename C> __device__ __forceinline__ void dft4(C& x0, C& x1, C& x2, C& x3) {
+  C a = cadd(x0, x2), b = csub(x0, x2), c = cadd(x1, x3), d = csub(x1, x3);
+  C jd = INV ? mul_pi(d) : mul_mi(d);
+  x0 = cadd(a, c);
+  x2 = csub(a, c);
+  x1 = cadd(b, jd);
+  x3 = csub(b, jd);
+}
+
+template <bool INV, typename C> __device__ __forceinline__ void dft8(C* v) {
+  using T = decltype(v[0].x);
+  const T h = (T)0.70710678118654752440;  // sqrt(1/2)
+  C e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  C o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4<INV>(e0, e1, e2, e3);
+  dft4<INV>(o0, o1, o2, o3);
+  C t1, t2, t3;  // o_s * W8^(+-s)
+  if (!INV) {
+    t1 = C{h * (o1.x + o1.y), h * (o1.y - o1.x)};
+    t2 = mul_mi(o2);
+    t3 = C{h * (o3.y - o3.x), -h * (o3.x + o3.y)};
+  } else {
+    t1 = C{h * (o1.x - o1.y), h * (o1.x + o1.y)};
+    t2 = mul_pi(o2);
+    t3 = C{-h * (o3.x + o3.y), h * (o3.x - o3.y)};
+  }
+  v[0] = cadd(e0, o0);
+  v[4] = csub(e0, o0);
+  v[1] = cadd(e1, t1);
+  v[5] = csub(e1, t1);
+  v[2] = cadd(e2, t2);
+  v[6] = csub(e2, t2);
+  v[3] = cadd(e3, t3);
+  v[7] = csub(e3, t3);
+}
+
+template <bool INV, typename C> __device__ __forceinline__ void dft3(C* v) {
+  using T = decltype(v[0].x);
+  const T s3 = (T)0.86602540378443864676;  // sin(2 pi/3)
+  C s = cadd(v[1], v[2]);
+  C d = csub(v[1], v[2]);
+  C t = C{v[0].x - (T)0.5 * s.x, v[0].y - (T)0.5 * s.y};
+  C sd = C{s3 * d.x, s3 * d.y};
+  C jsd = INV ? mul_pi(sd) : mul_mi(sd);
+  v[0] = cadd(v[0], s);
+  v[1] = cadd(t, jsd);
+  v[2] = csub(t, jsd);
+}
+
+template <int R, bool INV, typename C> __device__ __forceinline__ void dft_small(C* v) {
+  if constexpr (R == 2) dft2<INV>(v);
+  else if constexpr (R == 3) dft3<INV>(v);
+  else if constexpr (R == 4) dft4<INV>(v[0], v[1], v[2], v[3]);
+  else dft8<INV>(v);
+}
+
+// ---------------------------------------------------------------------------
+// compile-time radix plan: radix 8 as often as the power of two allows, then
+// one 4 or 2, then the 3s
+// ---------------------------------------------------------------------------
+constexpr int ct_exp2(int n) {
+  int a = 0;
+  while (n > 1 && n % 2 == 0) { n /= 2; ++a; }
+  return a;
+}
+constexpr int ct_exp3(int n) {
+  int b = 0;
+  while (n > 1 && n % 3 == 0) { n /= 3; ++b; }
+  return b;
+}
+constexpr int ct_npass(int n) { return ct_exp2(n) / 3 + (ct_exp2(n) % 3 ? 1 : 0) + ct_exp3(n); }
+constexpr int ct_radix(int n, int p) {
+  const int a = ct_exp2(n), n8 = a / 3, rem = a % 3;
+  if (p < n8) return 8;
+  p -= n8;
+  if (rem) {
+    if (p == 0) return rem == 2 ? 4 : 2;
+    p -= 1;
+  }
+  return 3;
+}
+constexpr int ct_ns(int n, int p) {
+  int ns = 1;
+  for (int i = 0; i < p; ++i) ns *= ct_radix(n, i);
+  return ns;
+}
+constexpr int ct_bt(int n, int nt, int p) { return (n / ct_radix(n, p) + nt - 1) / nt; }
+constexpr int ct_vmax(int n, int nt) {
+  int m = 0;
+  for (int p = 0; p < ct_npass(n); ++p) {
+    const int x = ct_bt(n, nt, p) * ct_radix(n, p);
+    m = x > m ? x : m;
+  }
+  return m;
+}
+
+// threads per compile-time transform: eight elements each
+constexpr int ct_threads(int n) { return n >= 8 ? n / 8 : 1; }
+
+// LDS index of element i of an x-direction transform: one pad slot per 128
+// bytes, so the stride-R writes of the first passes spread over all banks.
+template <typename T> __device__ __forceinline__ int xpad(int i) {
+  return i + (i >> (sizeof(T) == 8 ? 3 : 4));
+}
+template <typename T> constexpr int xpad_len(int n) { return n + (n >> (sizeof(T) == 8 ? 3 : 4)) + 1; }
+
+// Compile-time Stockham transform. Thread q (0 <= q < NT) owns butterflies
+// b = q + t NT of every pass. Pass p (radix R, Ns = product of the earlier
+// radices) reads x[b + r N/R] and writes x[(b - b mod Ns) R + b mod Ns + r Ns]
+// after the twiddle W_N^((b mod Ns) r N/(Ns R)); the last pass's outputs are
+// x[b + r N/R] again.
+template <typename T, int N, int NT, bool INV>
+struct CtFft {
+  static constexpr int NP = ct_npass(N);
+  static constexpr int VMAX = ct_vmax(N, NT);
+
+  template <int P> static constexpr int R() { return ct_radix(N, P); }
+  template <int P> static constexpr int NB() { return N / ct_radix(N, P); }
+  template <int P> static constexpr int BT() { return ct_bt(N, NT, P); }
+  template <int P> __device__ static __forceinline__ bool valid(int b) {
+    return (NB<P>() % NT == 0) || b < NB<P>();
+  }
+
+  // element index of value v[t R + r] at the input of pass P
+  template <int P> __device__ static __forceinline__ int in_index(int q, int t, int r) {
+    return q + t * NT + r * NB<P>();
+  }
+
+  template <int P>
+  __device__ static __forceinline__ void butterflies(cx<T>* v, int q, const cx<T>* __restrict__ tw) {
+    constexpr int Rr = R<P>(), NS = ct_ns(N, P), TSTEP = N / (NS * Rr);
+#pragma unroll
+    for (int t = 0; t < BT<P>(); ++t) {
+      const int b = q + t * NT;
+      if (valid<P>(b)) {
+        if constexpr (NS > 1) {
+          const int kk = b % NS;
+#pragma unroll
+          for (int r = 1; r < Rr; ++r) {
+            const cx<T> w = tw[kk * r * TSTEP];
+            v[t * Rr + r] = INV ? cmulconj(v[t * Rr + r], w) : cmul(v[t * Rr + r], w);
+          }
+        }
+        dft_small<Rr, INV>(v + t * Rr);
+      }
+    }
+  }
+
+  // outputs of pass P -> LDS -> inputs of pass P + 1
+  template <int P, class Idx>
+  __device__ static __forceinline__ void exchange(cx<T>* v, cx<T>* lds, const Idx& li, int q) {
+    constexpr int Rr = R<P>(), NS = ct_ns(N, P);
+#pragma unroll
+    for (int t = 0; t < BT<P>(); ++t) {
+      const int b = q + t * NT;
+      if (valid<P>(b)) {
+        const int kk = b % NS;
+        const int d0 = (b - kk) * Rr + kk;
+#pragma unroll
+        for (int r = 0; r < Rr; ++r) lds[li(d0 + r * NS)] = v[t * Rr + r];
+      }
+    }
+    __syncthreads();
+    constexpr int R2 = R<P + 1>();
+#pragma unroll
+    for (int t = 0; t < BT<P + 1>(); ++t) {
+      const int b = q + t * NT;
+      if (valid<P + 1>(b)) {
+#pragma unroll
+        for (int r = 0; r < R2; ++r) v[t * R2 + r] = lds[li(b + r * NB<P + 1>())];
+      }
+    }
+    __syncthreads();
+  }
+
+  template <int P, class Idx>
+  __device__ static __forceinline__ void run_from(cx<T>* v, cx<T>* lds, const Idx& li, int q,
+                                                  const cx<T>* __restrict__ tw) {
+    butterflies<P>(v, q, tw);
+    if constexpr (P + 1 < NP) {
+      exchange<P>(v, lds, li, q);
+      run_from<P + 1>(v, lds, li, q, tw);
+    }
+  }
+
+  // Whole transform: v holds the inputs of pass 0 on entry and the outputs of
+  // the last pass on exit (positions given by in_index<0> / out_index).
+  template <class Idx>
+  __device__ static __forceinline__ void run(cx<T>* v, cx<T>* lds, const Idx& li, int q,
+                                             const cx<T>* __restrict__ tw) {
+    run_from<0>(v, lds, li, q, tw);
+  }
+
+  static constexpr int RL = ct_radix(N, NP - 1);
+  static constexpr int BTL = ct_bt(N, NT, NP - 1);
+  static constexpr int NBL = N / ct_radix(N, NP - 1);
+  __device__ static __forceinline__ bool valid_last(int b) { return (NBL % NT == 0) || b < NBL; }
+  // element index of value v[t RL + r] at the output of the last pass
+  __device__ static __forceinline__ int out_index(int q, int t, int r) { return q + t * NT + r * NBL; }
+
+  static constexpr int R0 = ct_radix(N, 0);
+  static constexpr int BT0 = ct_bt(N, NT, 0);
+  static constexpr int NB0 = N / ct_radix(N, 0);
+  __device__ static __forceinline__ bool valid_first(int b) { return (NB0 % NT == 0) || b < NB0; }
+};
+
+// ---------------------------------------------------------------------------
+// runtime-length Stockham pass, in place in LDS (fallback engine)
+// ---------------------------------------------------------------------------
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void stockham_pass(cx<T>* buf, int stride, int N, int Ns,
+                                              const cx<T>* __restrict__ tw, int q, int nt) {
+  constexpr int BM = (kGenericElems + R - 1) / R;
+  const int nb = N / R;
+  const int tstep = N / (Ns * R);
+  cx<T> v[BM * R];
+#pragma unroll
+  for (int t = 0; t < BM; ++t) {
+    const int b = q + t * nt;
+    if (b < nb) {
+      const int kk = b % Ns;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[t * R + r] = buf[(b + r * nb) * stride];
+      if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const cx<T> w = tw[kk * r * tstep];
+          v[t * R + r] = INV ? cmulconj(v[t * R + r], w) : cmul(v[t * R + r], w);
+        }
+      }
+      dft_small<R, INV>(v + t * R);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < BM; ++t) {
+    const int b = q + t * nt;
+    if (b < nb) {
+      const int kk = b % Ns;
+      const int dst = (b - kk) * R + kk;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[(dst + r * Ns) * stride] = v[t * R + r];
+    }
+  }
+  __syncthreads();
+}
+
+// Whole runtime-length transform in LDS; every thread of the workgroup must
+// call it (barriers).
+template <typename T, bool INV>
+__device__ __noinline__ void fft_lds(cx<T>* buf, int stride, const FftPlan& fp, const cx<T>* __restrict__ tw,
+                                     int q) {
+  const int N = fp.n, nt = fp.nt, np = fp.npass;
+  int Ns = 1;
+  for (int p = 0; p < np; ++p) {
+    const int R = fp.rad[p];
+    if (R == 8) stockham_pass<T, 8, INV>(buf, stride, N, Ns, tw, q, nt);
+    else if (R == 4) stockham_pass<T, 4, INV>(buf, stride, N, Ns, tw, q, nt);
+    else if (R == 2) stockham_pass<T, 2, INV>(buf, stride, N, Ns, tw, q, nt);
+    else stockham_pass<T, 3, INV>(buf, stride, N, Ns, tw, q, nt);
+    Ns *= R;
+  }
+}
+
+}  // namespace monc

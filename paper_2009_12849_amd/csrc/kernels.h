@@ -1,0 +1,31 @@
+// Launchers of the projection kernels (kernels.hip).
+#pragma once
+#include <stddef.h>
+
+#include "monc_types.h"
+
+namespace monc {
+
+// Raise the dynamic-LDS limit of every kernel to the CU's 160 KB.
+void init_kernel_attributes();
+
+// Transform lengths with a compile-time FFT kernel (others take the
+// runtime-length kernels); such kernels use n/8 threads per transform (1 if
+// n < 8) and need blockDim = (transforms or columns per workgroup) * that.
+bool ct_supported(int n);
+inline int ct_threads_host(int n) { return n >= 8 ? n / 8 : 1; }
+
+// ct_n: the compile-time length, or 0 for the runtime-length kernel.
+// mode 0: divergence of (u, v, w); mode 1 (float only): FP64 residual
+// D(u) - D(G p) with p the first-pass pressure.
+void launch_xfwd(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, int mode, int ct_n, void* stream);
+void launch_ffty(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, bool inverse, int ct_n,
+                 void* stream);
+// rows: rows per lane, one of kTriRows (the member's tris)
+void launch_tridiag(const LaunchArgs& a, int grid, size_t lds, bool fp64, int rows, void* stream);
+// mode 0: write p; mode 1 (float only): p = p1 + delta (float) and wbuf (FP64)
+void launch_xinv(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, int mode, int ct_n, void* stream);
+// mixed = 0: pressure from io.p (FP64); mixed = 1: from MemberDesc::wbuf
+void launch_grad(const LaunchArgs& a, int grid, bool fp64, int mixed, void* stream);
+
+}  // namespace monc

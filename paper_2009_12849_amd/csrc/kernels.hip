@@ -1,0 +1,830 @@
+// HIP kernels of the pressure projection for gfx950 (wave64, LDS-staged).
+//
+// Phases of one projection (the FFT pressure solver of the paper's Sec. 4:
+// forward FFT, vertical ODE per wavenumber in Fourier space, backward FFT):
+//   xfwd     divergence D(u*) (or the FP64 residual D(u*) - D(G p1) of the
+//            mixed path) computed straight into the first radix pass of the
+//            x-direction real FFT; two real rows ride in one complex
+//            transform and are separated afterwards
+//   ffty     y-direction complex FFT of every (level, m) column
+//   tridiag  FP64 tridiagonal solve in z of every (m, n) column, partitioned
+//            over lanes, (0,0) column with the gauge
+//   xinv     x-direction complex-to-real FFT, writes p (or p1 + delta)
+//   grad     pressure-gradient correction u -= G p, w lid = 0
+//
+// The FFT phases exist twice: with the transform length fixed at compile
+// time (CtFft, for the lengths listed in kernels.h) and with a runtime length
+// (fft_lds) for every other 2^a 3^b length.
+//
+// Every kernel serves a group of members: blockIdx.x is mapped to a member
+// through LaunchArgs::block_start, and each member's sizes and tables come
+// from its MemberDesc.
+#include <hip/hip_runtime.h>
+
+#include "fft_core.h"
+#include "kernels.h"
+
+namespace monc {
+
+__device__ __forceinline__ int find_member(const LaunchArgs& a, int b) {
+  int m = 0;
+  while (m + 1 < a.nmem && b >= a.block_start[m + 1]) ++m;
+  return m;
+}
+
+// ---------------------------------------------------------------------------
+// per-row context of the stencils: offsets of the neighbouring rows and the
+// vertical metrics of the row's level
+// ---------------------------------------------------------------------------
+struct RowCtx {
+  long long off;    // row (k, j)
+  long long soff;   // row (k, j-1)
+  long long noff;   // row (k, j+1)
+  long long plane;  // ny * nx
+  int k;
+  bool top;         // k < nz-1: a w face above
+  bool bot;         // k > 0: a w face below
+  double rho0, rhow, rhowm, rdz, rdzc, rdzcm;
+  float rho0f, rhowf, rhowmf, rdzf;
+};
+
+__device__ __forceinline__ RowCtx make_row(const MemberDesc& d, long long row, bool valid) {
+  RowCtx c;
+  const int ny = d.ny, nz = d.nz;
+  const long long r = valid ? row : 0;
+  const int k = (int)(r / ny);
+  const int j = (int)(r - (long long)k * ny);
+  c.k = k;
+  c.off = r * d.nx;
+  c.soff = ((long long)k * ny + (j == 0 ? ny - 1 : j - 1)) * d.nx;
+  c.noff = ((long long)k * ny + (j == ny - 1 ? 0 : j + 1)) * d.nx;
+  c.plane = (long long)ny * d.nx;
+  c.top = k < nz - 1;
+  c.bot = k > 0;
+  c.rho0 = d.rho0[k];
+  c.rdz = d.rdz[k];
+  c.rhow = c.top ? d.rhow[k] : 0.0;
+  c.rdzc = c.top ? d.rdzc[k] : 0.0;
+  c.rhowm = c.bot ? d.rhow[k - 1] : 0.0;
+  c.rdzcm = c.bot ? d.rdzc[k - 1] : 0.0;
+  c.rho0f = d.rho0f[k];
+  c.rdzf = d.rdzf[k];
+  c.rhowf = c.top ? d.rhowf[k] : 0.0f;
+  c.rhowmf = c.bot ? d.rhowf[k - 1] : 0.0f;
+  return c;
+}
+
+template <typename T>
+__device__ __forceinline__ T div_at(const MemberDesc& d, const RowCtx& c, const T* __restrict__ u,
+                                    const T* __restrict__ v, const T* __restrict__ w, int i);
+
+template <>
+__device__ __forceinline__ double div_at<double>(const MemberDesc& d, const RowCtx& c, const double* __restrict__ u,
+                                                 const double* __restrict__ v, const double* __restrict__ w, int i) {
+  const int im = (i == 0) ? d.nx - 1 : i - 1;
+  const double hor = (u[c.off + i] - u[c.off + im]) * d.rdx + (v[c.off + i] - v[c.soff + i]) * d.rdy;
+  const double ft = c.top ? c.rhow * w[c.off + i] : 0.0;
+  const double fb = c.bot ? c.rhowm * w[c.off - c.plane + i] : 0.0;
+  return c.rho0 * hor + (ft - fb) * c.rdz;
+}
+
+template <>
+__device__ __forceinline__ float div_at<float>(const MemberDesc& d, const RowCtx& c, const float* __restrict__ u,
+                                               const float* __restrict__ v, const float* __restrict__ w, int i) {
+  const int im = (i == 0) ? d.nx - 1 : i - 1;
+  const float hor = (u[c.off + i] - u[c.off + im]) * d.rdxf + (v[c.off + i] - v[c.soff + i]) * d.rdyf;
+  const float ft = c.top ? c.rhowf * w[c.off + i] : 0.0f;
+  const float fb = c.bot ? c.rhowmf * w[c.off - c.plane + i] : 0.0f;
+  return c.rho0f * hor + (ft - fb) * c.rdzf;
+}
+
+// FP64 residual r = D(u* - G p1) of the mixed path, from float u*, p1.
+__device__ __forceinline__ double resid_at(const MemberDesc& d, const RowCtx& c, const float* __restrict__ u,
+                                           const float* __restrict__ v, const float* __restrict__ w,
+                                           const float* __restrict__ p, int i) {
+  const int nx = d.nx;
+  const int im = (i == 0) ? nx - 1 : i - 1;
+  const int ip = (i == nx - 1) ? 0 : i + 1;
+  const double pc = p[c.off + i];
+  const double ue = (double)u[c.off + i] - ((double)p[c.off + ip] - pc) * d.rdx;
+  const double uw = (double)u[c.off + im] - (pc - (double)p[c.off + im]) * d.rdx;
+  const double vn = (double)v[c.off + i] - ((double)p[c.noff + i] - pc) * d.rdy;
+  const double vs = (double)v[c.soff + i] - (pc - (double)p[c.soff + i]) * d.rdy;
+  double ft = 0.0, fb = 0.0;
+  if (c.top) ft = c.rhow * ((double)w[c.off + i] - ((double)p[c.off + c.plane + i] - pc) * c.rdzc);
+  if (c.bot) fb = c.rhowm * ((double)w[c.off - c.plane + i] - (pc - (double)p[c.off - c.plane + i]) * c.rdzcm);
+  return c.rho0 * ((ue - uw) * d.rdx + (vn - vs) * d.rdy) + (ft - fb) * c.rdz;
+}
+
+template <typename T, int MODE>
+__device__ __forceinline__ T source_at(const MemberDesc& d, const RowCtx& c, const IoPtrs& io, int i) {
+  if constexpr (MODE == 0) {
+    return div_at<T>(d, c, reinterpret_cast<const T*>(io.u), reinterpret_cast<const T*>(io.v),
+                     reinterpret_cast<const T*>(io.w), i);
+  } else {
+    return (T)resid_at(d, c, reinterpret_cast<const float*>(io.u), reinterpret_cast<const float*>(io.v),
+                       reinterpret_cast<const float*>(io.w), reinterpret_cast<const float*>(io.p), i);
+  }
+}
+
+// Separate two real rows packed as z = a + i b:
+// A[m] = (Z[m] + conj Z[N-m])/2, B[m] = (Z[m] - conj Z[N-m])/(2i).
+template <typename T>
+__device__ __forceinline__ void split_store(cx<T>* S, long long r0, long long r1, bool v0, bool v1, int nxp, int m,
+                                            cx<T> z, cx<T> zr) {
+  const T h = (T)0.5;
+  if (v0) S[r0 * nxp + m] = cx<T>{h * (z.x + zr.x), h * (z.y - zr.y)};
+  if (v1) S[r1 * nxp + m] = cx<T>{h * (z.y + zr.y), h * (zr.x - z.x)};
+}
+
+// ---------------------------------------------------------------------------
+// x-direction forward real FFT, compile-time length N (NT = N/8 threads per
+// transform, blockDim = transforms per workgroup * NT)
+// ---------------------------------------------------------------------------
+template <typename T, int MODE, int N>
+__global__ void __launch_bounds__(512) k_xfwd_ct(LaunchArgs a) {
+  constexpr int NT = ct_threads(N);
+  using F = CtFft<T, N, NT, false>;
+  extern __shared__ unsigned char smem_raw[];
+  const int mi = find_member(a, blockIdx.x);
+  const MemberDesc& d = *a.mem[mi];
+  const IoPtrs io = a.io[mi];
+  const int lb = blockIdx.x - a.block_start[mi];
+  const int ipw = blockDim.x / NT;
+  const int inst = threadIdx.x / NT;
+  const int q = threadIdx.x - inst * NT;
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw) + inst * xpad_len<T>(N);
+  const long long pair = (long long)lb * ipw + inst;
+  const long long r0 = 2 * pair, r1 = 2 * pair + 1;
+  const bool v0 = r0 < d.nrow, v1 = r1 < d.nrow;
+  const RowCtx c0 = make_row(d, r0, v0), c1 = make_row(d, r1, v1);
+  cx<T> v[F::VMAX];
+#pragma unroll
+  for (int t = 0; t < F::BT0; ++t) {
+    const int b = q + t * NT;
+    if (F::valid_first(b)) {
+#pragma unroll
+      for (int r = 0; r < F::R0; ++r) {
+        const int i = b + r * F::NB0;
+        const T s0 = v0 ? source_at<T, MODE>(d, c0, io, i) : (T)0;
+        const T s1 = v1 ? source_at<T, MODE>(d, c1, io, i) : (T)0;
+        v[t * F::R0 + r] = cx<T>{s0, s1};
+      }
+    }
+  }
+  auto li = [](int i) { return xpad<T>(i); };
+  F::run(v, lds, li, q, reinterpret_cast<const cx<T>*>(d.twx));
+#pragma unroll
+  for (int t = 0; t < F::BTL; ++t) {
+    const int b = q + t * NT;
+    if (F::valid_last(b)) {
+#pragma unroll
+      for (int r = 0; r < F::RL; ++r) lds[xpad<T>(F::out_index(q, t, r))] = v[t * F::RL + r];
+    }
+  }
+  __syncthreads();
+  cx<T>* S = reinterpret_cast<cx<T>*>(io.spec);
+  for (int m = q; m < d.nxh; m += NT) {
+    const cx<T> z = lds[xpad<T>(m)];
+    const cx<T> zr = lds[xpad<T>(m == 0 ? 0 : N - m)];
+    split_store<T>(S, r0, r1, v0, v1, d.nxp, m, z, zr);
+  }
+}
+
+// runtime length (fallback)
+template <typename T, int MODE>
+__global__ void __launch_bounds__(1024) k_xfwd_gen(LaunchArgs a) {
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* smem = reinterpret_cast<cx<T>*>(smem_raw);
+  const int mi = find_member(a, blockIdx.x);
+  const MemberDesc& d = *a.mem[mi];
+  const IoPtrs io = a.io[mi];
+  const int lb = blockIdx.x - a.block_start[mi];
+  const int N = d.nx, nt = d.fx.nt;
+  const int ipw = blockDim.x / nt;
+  const int inst = threadIdx.x / nt;
+  const bool active = inst < ipw;
+  const int q = active ? (int)(threadIdx.x - inst * nt) : kBig;
+  cx<T>* buf = smem + (active ? inst : 0) * N;
+  const long long pair = (long long)lb * ipw + inst;
+  const long long r0 = 2 * pair, r1 = 2 * pair + 1;
+  const bool v0 = active && r0 < d.nrow, v1 = active && r1 < d.nrow;
+  const RowCtx c0 = make_row(d, r0, v0), c1 = make_row(d, r1, v1);
+  if (active) {
+    for (int i = q; i < N; i += nt) {
+      const T s0 = v0 ? source_at<T, MODE>(d, c0, io, i) : (T)0;
+      const T s1 = v1 ? source_at<T, MODE>(d, c1, io, i) : (T)0;
+      buf[i] = cx<T>{s0, s1};
+    }
+  }
+  __syncthreads();
+  fft_lds<T, false>(buf, 1, d.fx, reinterpret_cast<const cx<T>*>(d.twx), q);
+  if (active) {
+    cx<T>* S = reinterpret_cast<cx<T>*>(io.spec);
+    for (int m = q; m < d.nxh; m += nt) split_store<T>(S, r0, r1, v0, v1, d.nxp, m, buf[m], buf[m == 0 ? 0 : N - m]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// y-direction complex FFT, in place on the spectral buffer. A workgroup takes
+// one level and MT = blockDim / NT consecutive m columns; LDS holds them as
+// [j][c] so that consecutive lanes touch consecutive columns (128-byte rows).
+// ---------------------------------------------------------------------------
+template <typename T, bool INV, int N>
+__global__ void __launch_bounds__(1024) k_ffty_ct(LaunchArgs a) {
+  constexpr int NT = ct_threads(N);
+  using F = CtFft<T, N, NT, INV>;
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  const int mi = find_member(a, blockIdx.x);
+  const MemberDesc& d = *a.mem[mi];
+  const IoPtrs io = a.io[mi];
+  const int lb = blockIdx.x - a.block_start[mi];
+  const int mt = blockDim.x / NT;
+  const int tiles = (d.nxh + mt - 1) / mt;
+  const int k = lb / tiles;
+  const int c = threadIdx.x % mt;
+  const int q = threadIdx.x / mt;
+  const int m = (lb - k * tiles) * mt + c;
+  const bool valid = m < d.nxh;
+  cx<T>* S = reinterpret_cast<cx<T>*>(io.spec) + (long long)k * d.plane + (valid ? m : 0);
+  const int nxp = d.nxp;
+  cx<T> v[F::VMAX];
+#pragma unroll
+  for (int t = 0; t < F::BT0; ++t) {
+    const int b = q + t * NT;
+    if (F::valid_first(b)) {
+#pragma unroll
+      for (int r = 0; r < F::R0; ++r) v[t * F::R0 + r] = valid ? S[(b + r * F::NB0) * nxp] : cx<T>{0, 0};
+    }
+  }
+  auto li = [mt, c](int i) { return i * mt + c; };
+  F::run(v, lds, li, q, reinterpret_cast<const cx<T>*>(d.twy));
+  if (valid) {
+#pragma unroll
+    for (int t = 0; t < F::BTL; ++t) {
+      const int b = q + t * NT;
+      if (F::valid_last(b)) {
+#pragma unroll
+        for (int r = 0; r < F::RL; ++r) S[F::out_index(q, t, r) * nxp] = v[t * F::RL + r];
+      }
+    }
+  }
+}
+
+template <typename T, bool INV>
+__global__ void __launch_bounds__(1024) k_ffty_gen(LaunchArgs a) {
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  const int mi = find_member(a, blockIdx.x);
+  const MemberDesc& d = *a.mem[mi];
+  const IoPtrs io = a.io[mi];
+  const int lb = blockIdx.x - a.block_start[mi];
+  const int mt = d.ymt, ny = d.ny, nt = d.fy.nt;
+  const int tiles = (d.nxh + mt - 1) / mt;
+  const int k = lb / tiles;
+  const int m0 = (lb - k * tiles) * mt;
+  const int c = threadIdx.x % mt;
+  int q = threadIdx.x / mt;
+  if (q >= nt) q = kBig;
+  cx<T>* S = reinterpret_cast<cx<T>*>(io.spec) + (long long)k * d.plane;
+  const int tot = ny * mt;
+  for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+    const int j = idx / mt, cc = idx - j * mt, m = m0 + cc;
+    buf[idx] = (m < d.nxh) ? S[(long long)j * d.nxp + m] : cx<T>{0, 0};
+  }
+  __syncthreads();
+  fft_lds<T, INV>(buf + c, mt, d.fy, reinterpret_cast<const cx<T>*>(d.twy), q);
+  for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+    const int j = idx / mt, cc = idx - j * mt, m = m0 + cc;
+    if (m < d.nxh) S[(long long)j * d.nxp + m] = buf[idx];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// x-direction inverse (complex-to-real) FFT of row pairs.
+// MODE 0: write p (storage type T).
+// MODE 1 (mixed, T = float): the transform is the correction delta; read p1
+//         from p, write p1 + delta to p (float) and to wbuf (FP64).
+// Z[m] = X_a[m] + i X_b[m], Z[N-m] = conj X_a[m] + i conj X_b[m]; the
+// imaginary parts of the self-conjugate bins (m = 0, m = N/2) are dropped.
+// ---------------------------------------------------------------------------
+template <typename T, class Idx>
+__device__ __forceinline__ void pack_rows(cx<T>* buf, const Idx& idx, const cx<T>* __restrict__ S, long long r0,
+                                          long long r1, bool v0, bool v1, int nxp, int N, int m) {
+  cx<T> xa = v0 ? S[r0 * nxp + m] : cx<T>{0, 0};
+  cx<T> xb = v1 ? S[r1 * nxp + m] : cx<T>{0, 0};
+  const bool selfconj = (m == 0) || (2 * m == N);
+  if (selfconj) {
+    xa.y = 0;
+    xb.y = 0;
+  }
+  buf[idx(m)] = cx<T>{xa.x - xb.y, xa.y + xb.x};
+  if (!selfconj) buf[idx(N - m)] = cx<T>{xa.x + xb.y, xb.x - xa.y};
+}
+
+template <typename T, int MODE>
+__device__ __forceinline__ void store_rows(const MemberDesc& d, const IoPtrs& io, long long r0, long long r1, bool v0,
+                                           bool v1, int i, cx<T> z) {
+  const int N = d.nx;
+  T* p = reinterpret_cast<T*>(io.p);
+  if constexpr (MODE == 0) {
+    if (v0) p[r0 * N + i] = z.x;
+    if (v1) p[r1 * N + i] = z.y;
+  } else {
+    if (v0) {
+      const double s = (double)p[r0 * N + i] + (double)z.x;
+      d.wbuf[r0 * N + i] = s;
+      p[r0 * N + i] = (T)s;
+    }
+    if (v1) {
+      const double s = (double)p[r1 * N + i] + (double)z.y;
+      d.wbuf[r1 * N + i] = s;
+      p[r1 * N + i] = (T)s;
+    }
+  }
+}
+
+template <typename T, int MODE, int N>
+__global__ void __launch_bounds__(512) k_xinv_ct(LaunchArgs a) {
+  constexpr int NT = ct_threads(N);
+  using F = CtFft<T, N, NT, true>;
+  extern __shared__ unsigned char smem_raw[];
+  const int mi = find_member(a, blockIdx.x);
+  const MemberDesc& d = *a.mem[mi];
+  const IoPtrs io = a.io[mi];
+  const int lb = blockIdx.x - a.block_start[mi];
+  const int ipw = blockDim.x / NT;
+  const int inst = threadIdx.x / NT;
+  const int q = threadIdx.x - inst * NT;
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw) + inst * xpad_len<T>(N);
+  const long long pair = (long long)lb * ipw + inst;
+  const long long r0 = 2 * pair, r1 = 2 * pair + 1;
+  const bool v0 = r0 < d.nrow, v1 = r1 < d.nrow;
+  const cx<T>* S = reinterpret_cast<const cx<T>*>(io.spec);
+  auto li = [](int i) { return xpad<T>(i); };
+  for (int m = q; m < d.nxh; m += NT) pack_rows<T>(lds, li, S, r0, r1, v0, v1, d.nxp, N, m);
+  __syncthreads();
+  cx<T> v[F::VMAX];
+#pragma unroll
+  for (int t = 0; t < F::BT0; ++t) {
+    const int b = q + t * NT;
+    if (F::valid_first(b)) {
+#pragma unroll
+      for (int r = 0; r < F::R0; ++r) v[t * F::R0 + r] = lds[xpad<T>(b + r * F::NB0)];
+    }
+  }
+  __syncthreads();
+  F::run(v, lds, li, q, reinterpret_cast<const cx<T>*>(d.twx));
+#pragma unroll
+  for (int t = 0; t < F::BTL; ++t) {
+    const int b = q + t * NT;
+    if (F::valid_last(b)) {
+#pragma unroll
+      for (int r = 0; r < F::RL; ++r) store_rows<T, MODE>(d, io, r0, r1, v0, v1, F::out_index(q, t, r), v[t * F::RL + r]);
+    }
+  }
+}
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(1024) k_xinv_gen(LaunchArgs a) {
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* smem = reinterpret_cast<cx<T>*>(smem_raw);
+  const int mi = find_member(a, blockIdx.x);
+  const MemberDesc& d = *a.mem[mi];
+  const IoPtrs io = a.io[mi];
+  const int lb = blockIdx.x - a.block_start[mi];
+  const int N = d.nx, nt = d.fx.nt;
+  const int ipw = blockDim.x / nt;
+  const int inst = threadIdx.x / nt;
+  const bool active = inst < ipw;
+  const int q = active ? (int)(threadIdx.x - inst * nt) : kBig;
+  cx<T>* buf = smem + (active ? inst : 0) * N;
+  const long long pair = (long long)lb * ipw + inst;
+  const long long r0 = 2 * pair, r1 = 2 * pair + 1;
+  const bool v0 = active && r0 < d.nrow, v1 = active && r1 < d.nrow;
+  const cx<T>* S = reinterpret_cast<const cx<T>*>(io.spec);
+  auto ident = [](int i) { return i; };
+  if (active)
+    for (int m = q; m < d.nxh; m += nt) pack_rows<T>(buf, ident, S, r0, r1, v0, v1, d.nxp, N, m);
+  __syncthreads();
+  fft_lds<T, true>(buf, 1, d.fx, reinterpret_cast<const cx<T>*>(d.twx), q);
+  if (active)
+    for (int i = q; i < N; i += nt) store_rows<T, MODE>(d, io, r0, r1, v0, v1, i, buf[i]);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 tridiagonal solve per wavenumber column (partitioned elimination).
+//
+// Column (m, n): rows a_k P_{k-1} + (-a_k - c_k - rho0_k lam) P_k + c_k P_{k+1}
+// = B_k, lam = lamx[m] + lamy[n], solved in FP64 whatever the storage type.
+// P lanes of one wave share a column; lane q owns rows q*S .. q*S+S-1 (rows
+// >= nz are identity rows).
+//  1. each lane eliminates inside its chunk so that every row depends only on
+//     the chunk's first unknown F_q and last unknown L_q;
+//  2. the interface rows of L_q are substituted into those of F_q, leaving a
+//     tridiagonal system in F_0..F_{P-1}, one row per lane;
+//  3. that system is solved by parallel cyclic reduction over the P lanes
+//     (wave shuffles, log2 P steps);
+//  4. L_q follows from F_q, F_{q+1}; every lane substitutes back.
+// The result is scaled by 1/(nx ny) (the inverse-FFT factor). The singular
+// (0,0) column: its right-hand side loses its dz-weighted mean, the top
+// unknown is pinned to 0, and the solution is shifted to the gauge
+// sum_k dz_k P_k = 0.
+// ---------------------------------------------------------------------------
+struct Row5 {
+  double a, b, c, x, y;  // sub, diag, sup, rhs (re, im)
+};
+
+__device__ __forceinline__ double shfl_d(double v, int src) { return __shfl(v, src); }
+
+__device__ __forceinline__ Row5 shfl_row(const Row5& r, int src) {
+  return Row5{shfl_d(r.a, src), shfl_d(r.b, src), shfl_d(r.c, src), shfl_d(r.x, src), shfl_d(r.y, src)};
+}
+
+template <typename TS, int S>
+__global__ void __launch_bounds__(256) k_tridiag(LaunchArgs a) {
+  extern __shared__ unsigned char smem_raw[];
+  double2* stage = reinterpret_cast<double2*>(smem_raw);
+  const int mi = find_member(a, blockIdx.x);
+  const MemberDesc& d = *a.mem[mi];
+  const IoPtrs io = a.io[mi];
+  const int lb = blockIdx.x - a.block_start[mi];
+  const int P = d.triP, CW = d.tricw, nz = d.nz, nxh = d.nxh;
+  constexpr int SP = S + 1;                  // padded chunk length in LDS
+  const int lrow = P * SP;                   // staged column length
+  const int ncols = d.ny * nxh;
+  const int col0 = lb * CW;
+  using CS = cx<TS>;
+  CS* Sg = reinterpret_cast<CS*>(io.spec);
+  auto slot = [](int k) { return (k / S) * SP + (k % S); };
+
+  // 1. coalesced load of CW columns x nz levels into LDS (the thread's
+  //    column is fixed because CW divides the workgroup size)
+  {
+    const int cc = threadIdx.x % CW;
+    const int col = col0 + cc;
+    const bool ok = col < ncols;
+    const int n = ok ? col / nxh : 0;
+    const long long base = (long long)n * d.nxp + (ok ? col - n * nxh : 0);
+    for (int k = threadIdx.x / CW; k < nz; k += 256 / CW) {
+      double2 val = make_double2(0.0, 0.0);
+      if (ok) {
+        const CS x = Sg[(long long)k * d.plane + base];
+        val = make_double2((double)x.x, (double)x.y);
+      }
+      stage[cc * lrow + slot(k)] = val;
+    }
+  }
+
+  const int tid = threadIdx.x;
+  const int c = tid / P, q = tid - c * P;
+  const int col = col0 + c;
+  const bool valid = col < ncols;
+  const bool singular = valid && (col == 0);
+  double2* scol = stage + c * lrow;
+  const int k0 = q * S;
+
+  // coefficients of the lane's rows (identity outside the system), fetched
+  // while the column data is still arriving
+  double lam = 0.0;
+  if (valid) {
+    const int n = col / nxh, m = col - n * nxh;
+    lam = d.lamy[n] + d.lamx[m];
+  }
+  double A[S], B[S], C[S];
+#pragma unroll
+  for (int r = 0; r < S; ++r) {
+    const int k = k0 + r;
+    if (valid && k < nz && !(singular && k == nz - 1)) {
+      A[r] = d.ta[k];
+      C[r] = d.tc[k];
+      B[r] = -(A[r] + C[r]) - d.rho0[k] * lam;
+    } else {
+      A[r] = 0.0;
+      B[r] = 1.0;
+      C[r] = 0.0;
+    }
+  }
+  __syncthreads();
+
+  // (0,0) column: remove the dz-weighted mean of the right-hand side
+  if (singular && q == 0) {
+    double sr = 0.0, si = 0.0;
+    for (int k = 0; k < nz; ++k) {
+      const double2 b = scol[slot(k)];
+      sr += d.dz[k] * b.x;
+      si += d.dz[k] * b.y;
+    }
+    sr *= d.rH;
+    si *= d.rH;
+    for (int k = 0; k < nz; ++k) {
+      double2& b = scol[slot(k)];
+      b.x -= sr;
+      b.y -= si;
+    }
+  }
+  __syncthreads();
+
+  double2 D[S];
+#pragma unroll
+  for (int r = 0; r < S; ++r) {
+    const int k = k0 + r;
+    D[r] = (valid && k < nz && !(singular && k == nz - 1)) ? scol[q * SP + r] : make_double2(0.0, 0.0);
+  }
+
+  // 1. chunk elimination: x_r + al_r x_0 + ga_r x_{r+1} = de_r (r >= 1), then
+  //    backward to x_r = e_r - f_r x_0 - g_r x_{S-1}, kept in (de, al, ga)
+  double al[S], ga[S];
+  double2 de[S];
+#pragma unroll
+  for (int r = 1; r < S; ++r) {
+    if (r == 1) {
+      const double inv = 1.0 / B[1];
+      al[1] = A[1] * inv;
+      ga[1] = C[1] * inv;
+      de[1] = make_double2(D[1].x * inv, D[1].y * inv);
+    } else {
+      const double inv = 1.0 / (B[r] - A[r] * ga[r - 1]);
+      al[r] = -A[r] * al[r - 1] * inv;
+      ga[r] = C[r] * inv;
+      de[r] = make_double2((D[r].x - A[r] * de[r - 1].x) * inv, (D[r].y - A[r] * de[r - 1].y) * inv);
+    }
+  }
+  // interface row of L_q:  al L_q... written as  aL F_q + L_q + cL F_{q+1} = dL
+  const double aL = al[S - 1], cL = ga[S - 1];
+  const double2 dL = de[S - 1];
+  de[S - 1] = make_double2(0.0, 0.0);
+  al[S - 1] = 0.0;
+  ga[S - 1] = -1.0;
+#pragma unroll
+  for (int r = S - 2; r >= 1; --r) {
+    const double g = ga[r];
+    de[r] = make_double2(de[r].x - g * de[r + 1].x, de[r].y - g * de[r + 1].y);
+    al[r] = al[r] - g * al[r + 1];
+    ga[r] = -g * ga[r + 1];
+  }
+  // interface row of F_q:  A0 L_{q-1} + (B0 - C0 f1) F_q - C0 g1 L_q = D0 - C0 e1
+  const double aF = A[0], bF = B[0] - C[0] * al[1], cF = -C[0] * ga[1];
+  const double2 dF = make_double2(D[0].x - C[0] * de[1].x, D[0].y - C[0] * de[1].y);
+
+  // 2. substitute L_{q-1} (from lane q-1) and L_q into the F_q row
+  const int lane = __lane_id();
+  const int up = (q > 0) ? lane - 1 : lane, dn = (q < P - 1) ? lane + 1 : lane;
+  const double aLm = shfl_d(aL, up), cLm = shfl_d(cL, up);
+  const double dLmx = shfl_d(dL.x, up), dLmy = shfl_d(dL.y, up);
+  Row5 row;
+  {
+    const double am = (q > 0) ? aF : 0.0;  // coupling to L_{q-1}
+    row.a = -am * aLm;
+    row.b = bF - am * cLm - cF * aL;
+    row.c = -cF * cL;
+    row.x = dF.x - am * dLmx - cF * dL.x;
+    row.y = dF.y - am * dLmy - cF * dL.y;
+  }
+
+  // 3. parallel cyclic reduction over the P lanes of the column
+  for (int h = 1; h < P; h *= 2) {
+    const bool hasl = q - h >= 0, hasr = q + h < P;
+    const Row5 lo = shfl_row(row, hasl ? lane - h : lane);
+    const Row5 hi = shfl_row(row, hasr ? lane + h : lane);
+    const double k1 = hasl ? row.a / lo.b : 0.0;
+    const double k2 = hasr ? row.c / hi.b : 0.0;
+    Row5 nr;
+    nr.a = hasl ? -lo.a * k1 : 0.0;
+    nr.c = hasr ? -hi.c * k2 : 0.0;
+    nr.b = row.b - (hasl ? lo.c * k1 : 0.0) - (hasr ? hi.a * k2 : 0.0);
+    nr.x = row.x - (hasl ? lo.x * k1 : 0.0) - (hasr ? hi.x * k2 : 0.0);
+    nr.y = row.y - (hasl ? lo.y * k1 : 0.0) - (hasr ? hi.y * k2 : 0.0);
+    row = nr;
+  }
+  const double rb = 1.0 / row.b;
+  const double2 F = make_double2(row.x * rb, row.y * rb);
+
+  // 4. L_q = dL - aL F_q - cL F_{q+1}, then the chunk's interior rows
+  const double Fnx = shfl_d(F.x, dn), Fny = shfl_d(F.y, dn);
+  const double2 Fn = (q < P - 1) ? make_double2(Fnx, Fny) : make_double2(0.0, 0.0);
+  const double2 L = make_double2(dL.x - aL * F.x - cL * Fn.x, dL.y - aL * F.y - cL * Fn.y);
+  __syncthreads();  // the (0,0) lane has finished with the staged right-hand side
+#pragma unroll
+  for (int r = 0; r < S; ++r) {
+    const int k = k0 + r;
+    double2 x;
+    if (r == 0) x = F;
+    else if (r == S - 1) x = L;
+    else x = make_double2(de[r].x - al[r] * F.x - ga[r] * L.x, de[r].y - al[r] * F.y - ga[r] * L.y);
+    if (k < nz) scol[q * SP + r] = x;
+  }
+  __syncthreads();
+
+  // (0,0) column: gauge sum_k dz_k P_k = 0
+  if (singular && q == 0) {
+    double sr = 0.0, si = 0.0;
+    for (int k = 0; k < nz; ++k) {
+      const double2 x = scol[slot(k)];
+      sr += d.dz[k] * x.x;
+      si += d.dz[k] * x.y;
+    }
+    sr *= d.rH;
+    si *= d.rH;
+    for (int k = 0; k < nz; ++k) {
+      double2& x = scol[slot(k)];
+      x.x -= sr;
+      x.y -= si;
+    }
+  }
+  __syncthreads();
+
+  // coalesced store, scaled by 1/(nx ny)
+  {
+    const double sc = d.inv_nxny;
+    const int cc = threadIdx.x % CW;
+    const int cl = col0 + cc;
+    if (cl < ncols) {
+      const int n = cl / nxh;
+      const long long base = (long long)n * d.nxp + (cl - n * nxh);
+      for (int k = threadIdx.x / CW; k < nz; k += 256 / CW) {
+        const double2 x = stage[cc * lrow + slot(k)];
+        Sg[(long long)k * d.plane + base] = CS{(TS)(x.x * sc), (TS)(x.y * sc)};
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pressure-gradient correction u -= G p, evaluated in FP64 from an FP64
+// pressure (p itself on the FP64 path, p1 + delta on the mixed path); the
+// fields are T. One thread per (j, i) column walks kGradChunk levels downward
+// so that p_{k+1} is carried in a register. w[nz-1] = 0.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_grad(LaunchArgs a, int mixed) {
+  const int mi = find_member(a, blockIdx.x);
+  const MemberDesc& d = *a.mem[mi];
+  const IoPtrs io = a.io[mi];
+  const int lb = blockIdx.x - a.block_start[mi];
+  const int nx = d.nx, ny = d.ny, nz = d.nz;
+  const long long nh = (long long)nx * ny;
+  const int hblocks = (int)((nh + blockDim.x - 1) / blockDim.x);
+  const int kc = lb / hblocks;
+  const long long h = (long long)(lb - kc * hblocks) * blockDim.x + threadIdx.x;
+  if (h >= nh) return;
+  const int j = (int)(h / nx), i = (int)(h - (long long)j * nx);
+  const long long he = (long long)j * nx + ((i == nx - 1) ? 0 : i + 1);
+  const long long hn = (long long)((j == ny - 1) ? 0 : j + 1) * nx + i;
+  const double* __restrict__ p = mixed ? d.wbuf : reinterpret_cast<const double*>(io.p);
+  T* __restrict__ u = reinterpret_cast<T*>(io.u);
+  T* __restrict__ v = reinterpret_cast<T*>(io.v);
+  T* __restrict__ w = reinterpret_cast<T*>(io.w);
+  const int k0 = kc * kGradChunk;
+  const int k1 = min(nz, k0 + kGradChunk);
+  double pup = (k1 < nz) ? p[(long long)k1 * nh + h] : 0.0;
+#pragma unroll 4
+  for (int k = k1 - 1; k >= k0; --k) {
+    const long long base = (long long)k * nh;
+    const double pc = p[base + h];
+    const double pe = p[base + he];
+    const double pn = p[base + hn];
+    u[base + h] = (T)((double)u[base + h] - (pe - pc) * d.rdx);
+    v[base + h] = (T)((double)v[base + h] - (pn - pc) * d.rdy);
+    if (k == nz - 1) w[base + h] = (T)0;
+    else w[base + h] = (T)((double)w[base + h] - (pup - pc) * d.rdzc[k]);
+    pup = pc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+// ---------------------------------------------------------------------------
+template <typename K>
+static void set_lds_limit(K kern) {
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+}
+
+#define MONC_TRI_ROWS(X) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(12) X(16)
+#define MONC_CT_SIZES(X) X(16) X(32) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(1536) X(2048) X(4096)
+
+bool ct_supported(int n) {
+  switch (n) {
+#define MONC_CASE(N) case N:
+    MONC_CT_SIZES(MONC_CASE)
+#undef MONC_CASE
+    return true;
+    default:
+      return false;
+  }
+}
+
+void init_kernel_attributes() {
+  set_lds_limit(k_xfwd_gen<double, 0>);
+  set_lds_limit(k_xfwd_gen<float, 0>);
+  set_lds_limit(k_xfwd_gen<float, 1>);
+  set_lds_limit(k_ffty_gen<double, false>);
+  set_lds_limit(k_ffty_gen<double, true>);
+  set_lds_limit(k_ffty_gen<float, false>);
+  set_lds_limit(k_ffty_gen<float, true>);
+  set_lds_limit(k_xinv_gen<double, 0>);
+  set_lds_limit(k_xinv_gen<float, 0>);
+  set_lds_limit(k_xinv_gen<float, 1>);
+#define MONC_TRI_ATTR(S)              \
+  set_lds_limit(k_tridiag<double, S>); \
+  set_lds_limit(k_tridiag<float, S>);
+  MONC_TRI_ROWS(MONC_TRI_ATTR)
+#undef MONC_TRI_ATTR
+#define MONC_ATTR(N)                          \
+  set_lds_limit(k_xfwd_ct<double, 0, N>);     \
+  set_lds_limit(k_xfwd_ct<float, 0, N>);      \
+  set_lds_limit(k_xfwd_ct<float, 1, N>);      \
+  set_lds_limit(k_ffty_ct<double, false, N>); \
+  set_lds_limit(k_ffty_ct<double, true, N>);  \
+  set_lds_limit(k_ffty_ct<float, false, N>);  \
+  set_lds_limit(k_ffty_ct<float, true, N>);   \
+  set_lds_limit(k_xinv_ct<double, 0, N>);     \
+  set_lds_limit(k_xinv_ct<float, 0, N>);      \
+  set_lds_limit(k_xinv_ct<float, 1, N>);
+  MONC_CT_SIZES(MONC_ATTR)
+#undef MONC_ATTR
+}
+
+#define MONC_GO(kern) hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, (hipStream_t)stream, a)
+
+void launch_xfwd(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, int mode, int ct_n, void* stream) {
+  switch (ct_n) {
+#define MONC_CASE(N)                                        \
+  case N:                                                   \
+    if (fp64) MONC_GO((k_xfwd_ct<double, 0, N>));           \
+    else if (mode == 0) MONC_GO((k_xfwd_ct<float, 0, N>));  \
+    else MONC_GO((k_xfwd_ct<float, 1, N>));                 \
+    return;
+    MONC_CT_SIZES(MONC_CASE)
+#undef MONC_CASE
+    default:
+      if (fp64) MONC_GO((k_xfwd_gen<double, 0>));
+      else if (mode == 0) MONC_GO((k_xfwd_gen<float, 0>));
+      else MONC_GO((k_xfwd_gen<float, 1>));
+  }
+}
+
+void launch_ffty(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, bool inverse, int ct_n,
+                 void* stream) {
+  switch (ct_n) {
+#define MONC_CASE(N)                                                  \
+  case N:                                                             \
+    if (fp64) {                                                       \
+      if (inverse) MONC_GO((k_ffty_ct<double, true, N>));             \
+      else MONC_GO((k_ffty_ct<double, false, N>));                    \
+    } else {                                                          \
+      if (inverse) MONC_GO((k_ffty_ct<float, true, N>));              \
+      else MONC_GO((k_ffty_ct<float, false, N>));                     \
+    }                                                                 \
+    return;
+    MONC_CT_SIZES(MONC_CASE)
+#undef MONC_CASE
+    default:
+      if (fp64) {
+        if (inverse) MONC_GO((k_ffty_gen<double, true>));
+        else MONC_GO((k_ffty_gen<double, false>));
+      } else {
+        if (inverse) MONC_GO((k_ffty_gen<float, true>));
+        else MONC_GO((k_ffty_gen<float, false>));
+      }
+  }
+}
+
+void launch_xinv(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, int mode, int ct_n, void* stream) {
+  switch (ct_n) {
+#define MONC_CASE(N)                                        \
+  case N:                                                   \
+    if (fp64) MONC_GO((k_xinv_ct<double, 0, N>));           \
+    else if (mode == 0) MONC_GO((k_xinv_ct<float, 0, N>));  \
+    else MONC_GO((k_xinv_ct<float, 1, N>));                 \
+    return;
+    MONC_CT_SIZES(MONC_CASE)
+#undef MONC_CASE
+    default:
+      if (fp64) MONC_GO((k_xinv_gen<double, 0>));
+      else if (mode == 0) MONC_GO((k_xinv_gen<float, 0>));
+      else MONC_GO((k_xinv_gen<float, 1>));
+  }
+}
+
+void launch_tridiag(const LaunchArgs& a, int grid, size_t lds, bool fp64, int rows, void* stream) {
+  const int block = 256;
+  switch (rows) {
+#define MONC_CASE(S)                       \
+  case S:                                  \
+    if (fp64) MONC_GO((k_tridiag<double, S>)); \
+    else MONC_GO((k_tridiag<float, S>));   \
+    return;
+    MONC_TRI_ROWS(MONC_CASE)
+#undef MONC_CASE
+  }
+}
+
+void launch_grad(const LaunchArgs& a, int grid, bool fp64, int mixed, void* stream) {
+  if (fp64) hipLaunchKernelGGL((k_grad<double>), dim3(grid), dim3(256), 0, (hipStream_t)stream, a, mixed);
+  else hipLaunchKernelGGL((k_grad<float>), dim3(grid), dim3(256), 0, (hipStream_t)stream, a, mixed);
+}
+
+}  // namespace monc

@@ -1,0 +1,83 @@
+// Shared host/device descriptors of the projection library.
+//
+// A launch covers one phase (e.g. "y-direction FFT") for a group of members
+// (one member for monc_project, every member of a batch for
+// monc_project_batched). Static per-member data (sizes, metric tables,
+// twiddles, FFT plans, tile parameters, workspace) lives in a device array of
+// MemberDesc; the per-call field pointers and the block ranges of the members
+// travel by value in LaunchArgs (about 3.3 KB, under the 4 KB kernel-argument
+// limit).
+#pragma once
+#include <stdint.h>
+
+namespace monc {
+
+constexpr int kMaxPass = 16;            // radix passes of one FFT (3^8 needs 8)
+constexpr int kMaxLaunchMembers = 64;   // members per grouped launch
+constexpr int kTriSmax = 16;            // rows per lane in the tridiagonal solver
+constexpr int kTriPmax = 64;            // lanes per column (one wave)
+constexpr int kGradChunk = 16;          // levels per thread in the gradient kernel
+constexpr int kBig = 1 << 30;           // "inactive" lane index
+constexpr int kGenericElems = 8;        // max elements per thread of the runtime-length FFT
+
+struct FftPlan {
+  int n;                  // transform length (2^a 3^b)
+  int npass;              // number of Stockham passes
+  int nt;                 // threads cooperating on one transform
+  int rad[kMaxPass];      // radix of each pass (2, 3, 4 or 8)
+};
+
+struct MemberDesc {
+  int nx, ny, nz;
+  int nxh;                // nx/2 + 1 spectral values per row
+  int nxp;                // padded spectral row length (complex elements)
+  int dtype;              // 0 = FP64, 1 = mixed
+  long long nrow;         // nz * ny real rows
+  long long plane;        // ny * nxp complex values per level
+  double rdx, rdy;        // 1/dx, 1/dy
+  double inv_nxny;        // 1/(nx ny), the inverse-FFT normalisation
+  double rH;              // 1 / sum(dz)
+  float rdxf, rdyf;       // FP32 copies for the FP32 stencil
+  // FP64 vertical tables, all of length nz
+  const double* rho0;     // reference density at centres
+  const double* rhow;     // density on the top face of cell k (0 at k = nz-1)
+  const double* rdz;      // 1/dz_k
+  const double* rdzc;     // 1/dzc_k (0 at k = nz-1)
+  const double* dz;       // dz_k (gauge weights)
+  const double* ta;       // tridiagonal sub-diagonal a_k (a_0 = 0)
+  const double* tc;       // tridiagonal super-diagonal c_k (c_{nz-1} = 0)
+  // FP32 copies for the FP32 stencil
+  const float* rho0f;
+  const float* rhowf;
+  const float* rdzf;
+  // horizontal eigenvalues
+  const double* lamx;     // [nxh]
+  const double* lamy;     // [ny]
+  // twiddles exp(-2 pi i t / n), complex in the storage precision
+  const void* twx;        // [nx]
+  const void* twy;        // [ny]
+  FftPlan fx, fy;
+  int ymt;                // y-FFT columns per workgroup
+  int triP;               // tridiagonal lanes per column (power of 2)
+  int tris;               // rows per lane (>= 2)
+  int tricw;              // columns per workgroup (256 / triP)
+  void* spec;             // spectral workspace (nz, ny, nxp) complex
+  double* wbuf;           // mixed path: p1 + delta in FP64, (nz, ny, nx)
+};
+
+struct IoPtrs {
+  void* u;
+  void* v;
+  void* w;
+  void* p;
+  void* spec;             // spectral buffer used by this launch
+};
+
+struct LaunchArgs {
+  int nmem;
+  int block_start[kMaxLaunchMembers + 1];
+  const MemberDesc* mem[kMaxLaunchMembers];  // device descriptors
+  IoPtrs io[kMaxLaunchMembers];
+};
+
+}  // namespace monc

@@ -1,0 +1,345 @@
+"""Parity of the HIP path (called through the C ABI) with the FP64 oracle.
+
+Tolerances (errors are normwise: velocities relative to the input velocity
+scale, p relative to max|p|):
+  FP64 path   velocities within 1e-12 of the oracle; p within
+              max(1e-12, 4 u kappa), where kappa is the infinity-norm condition
+              number of the worst-conditioned wavenumber column (smallest
+              nonzero lambda) and u = 2^-53: the GPU's partitioned elimination
+              and the oracle's Thomas sweep are both backward stable, so each
+              lies within about kappa u of the exact solution. The output's
+              divergence stays below 1e-12 in SI units.
+  mixed path  every field within 1e-6 of the FP64 oracle run on the FP32
+              inputs upcast to FP64 (the accuracy target of the mixed path).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.helpers import relerr
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2009_12849_amd as monc  # noqa: E402
+
+DEV = "cuda:0"
+TOL64 = 1e-12
+TOL_MIXED = 1e-6
+
+
+def to_dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device=DEV, dtype=dtype)
+
+
+def run_gpu(g, u, v, w, dtype="f64", plan=None):
+    plan = plan or monc.Plan.from_grid(g, dtype)
+    tdt = plan.torch_dtype
+    tu, tv, tw = to_dev(u, tdt), to_dev(v, tdt), to_dev(w, tdt)
+    tp = torch.empty_like(tu)
+    plan.project(tu, tv, tw, tp)
+    torch.cuda.synchronize()
+    return [t.cpu().numpy().astype(np.float64) for t in (tu, tv, tw, tp)]
+
+
+def worst_column_condition(g):
+    """kappa_inf of the worst-conditioned column system: the tridiagonal of
+    the smallest nonzero horizontal eigenvalue, or the (0,0) column's system
+    with the top unknown pinned (rows 0..nz-2)."""
+    a, c = oracle.tridiag_coefficients(g.dz, g.rho0)
+    cond = lambda T: float(np.linalg.norm(T, np.inf) * np.linalg.norm(np.linalg.inv(T), np.inf))
+    kappa = 1.0
+    if g.nz > 1:
+        m = g.nz - 1
+        T0 = np.diag(-(a[:m] + c[:m])) + np.diag(a[1:m], -1) + np.diag(c[:m - 1], 1)
+        kappa = cond(T0)
+    lamx, lamy = oracle.modified_wavenumbers(g.nx, g.ny, g.dx, g.dy)
+    lam = (lamy[:, None] + lamx[None, :]).ravel()
+    lam = lam[lam > 0]
+    if lam.size:
+        T = np.diag(-(a + c) - g.rho0 * lam.min()) + np.diag(a[1:], -1) + np.diag(c[:-1], 1)
+        kappa = max(kappa, cond(T))
+    return kappa
+
+
+def p_tolerance(g):
+    return max(TOL64, 4 * 2.0 ** -53 * worst_column_condition(g))
+
+
+def field_errors(out, ref, u, v, w):
+    vs = max(np.max(np.abs(u)), np.max(np.abs(v)), np.max(np.abs(w)))
+    errs = [np.max(np.abs(out[t] - ref[t])) / vs for t in range(3)]
+    errs.append(relerr(out[3], ref[3]))
+    return errs
+
+
+def check_fp64(g, u, v, w, tol=TOL64):
+    print(f"case {g.nx}x{g.ny}x{g.nz} fp64", flush=True)
+    ref = oracle.project(u, v, w, g.dx, g.dy, g.dz, g.rho0)
+    out = run_gpu(g, u, v, w, "f64")
+    errs = field_errors(out, ref, u, v, w)
+    assert max(errs[:3]) <= tol, errs
+    assert errs[3] <= max(tol, p_tolerance(g)), (errs, p_tolerance(g))
+    assert np.all(out[2][-1] == 0.0)
+    div = oracle.divergence(out[0], out[1], out[2], g.dx, g.dy, g.dz, g.rho0)
+    assert np.max(np.abs(div)) <= 1e-12
+    return errs
+
+
+# ---------------------------------------------------------------------------
+# stage-wise
+# ---------------------------------------------------------------------------
+STAGE_SHAPES = [(32, 32, 32), (48, 27, 13), (24, 18, 9), (1, 6, 5), (12, 1, 3), (64, 64, 130)]
+
+
+def _case(shape, seed):
+    # dz grows by at most a factor 20 over the column (as 5 m -> 100 m)
+    rng = np.random.default_rng(seed)
+    g = synth.random_grid(rng, *shape, stretch=(1.0, min(1.1, 20.0 ** (1.0 / max(shape[2], 1)))))
+    return (g,) + synth.random_fields(rng, g)
+
+
+@pytest.mark.parametrize("shape", STAGE_SHAPES)
+def test_stage_forward_spectrum(shape):
+    g, u, v, w = _case(shape, 1)
+    ref = oracle.project(u, v, w, g.dx, g.dy, g.dz, g.rho0, intermediates=True)
+    plan = monc.Plan.from_grid(g, "f64")
+    spec = plan.spectral_buffer()
+    bufs = [to_dev(a, torch.float64) for a in (u, v, w)] + [spec]
+    plan.debug_stage(monc.STAGE_FORWARD, bufs)
+    torch.cuda.synchronize()
+    got = spec.cpu().numpy()[:, :, : g.nx // 2 + 1]
+    assert relerr(got, ref["B"]) <= 1e-13
+
+
+@pytest.mark.parametrize("shape", STAGE_SHAPES)
+def test_stage_solve_columns(shape):
+    g, u, v, w = _case(shape, 2)
+    ref = oracle.project(u, v, w, g.dx, g.dy, g.dz, g.rho0, intermediates=True)
+    plan = monc.Plan.from_grid(g, "f64")
+    spec = plan.spectral_buffer()
+    nxh = g.nx // 2 + 1
+    spec[:, :, :nxh] = torch.from_numpy(ref["B"]).to(DEV)
+    plan.debug_stage(monc.STAGE_SOLVE, [spec])
+    torch.cuda.synchronize()
+    got = spec.cpu().numpy()[:, :, :nxh]
+    assert relerr(got, ref["P"] / (g.nx * g.ny)) <= 1e-12
+
+
+@pytest.mark.parametrize("shape", STAGE_SHAPES)
+def test_stage_inverse_and_gradient(shape):
+    g, u, v, w = _case(shape, 3)
+    ref = oracle.project(u, v, w, g.dx, g.dy, g.dz, g.rho0, intermediates=True)
+    plan = monc.Plan.from_grid(g, "f64")
+    spec = plan.spectral_buffer()
+    nxh = g.nx // 2 + 1
+    spec[:, :, :nxh] = torch.from_numpy(ref["P"] / (g.nx * g.ny)).to(DEV)
+    p = torch.empty((g.nz, g.ny, g.nx), dtype=torch.float64, device=DEV)
+    plan.debug_stage(monc.STAGE_INVERSE, [spec, p])
+    torch.cuda.synchronize()
+    assert relerr(p.cpu().numpy(), ref["p"]) <= 1e-13
+    tu, tv, tw = (to_dev(a, torch.float64) for a in (u, v, w))
+    pp = to_dev(ref["p"], torch.float64)
+    plan.debug_stage(monc.STAGE_GRADIENT, [pp, tu, tv, tw])
+    torch.cuda.synchronize()
+    out = [t.cpu().numpy() for t in (tu, tv, tw)]
+    for o, r in zip(out, (ref["u"], ref["v"], ref["w"])):
+        assert np.max(np.abs(o - r)) <= 1e-14 * max(np.abs(u).max(), np.abs(w).max())
+
+
+# ---------------------------------------------------------------------------
+# end to end, FP64
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("shape", [(4, 4, 3), (6, 3, 4), (6, 4, 5), (8, 8, 6), (1, 1, 4), (4, 4, 1),
+                                   (3, 2, 2), (9, 6, 3), (2, 3, 5), (1, 1, 1)])
+def test_fp64_tiny_grids(shape):
+    g, u, v, w = _case(shape, sum(shape))
+    check_fp64(g, u, v, w)
+
+
+@pytest.mark.parametrize("shape", [(48, 27, 13), (192, 96, 40), (64, 1, 8), (3, 64, 7), (96, 72, 33),
+                                   (256, 8, 17), (16, 16, 700), (8, 6, 1024), (2048, 4, 3), (6, 1536, 2)])
+def test_fp64_ragged_and_extreme_shapes(shape):
+    g, u, v, w = _case(shape, 7)
+    check_fp64(g, u, v, w)
+
+
+def test_fp64_c0():
+    m = synth.make_workload("c0").members[0]
+    check_fp64(m.grid, m.u, m.v, m.w)
+
+
+def test_fp64_c1_full_size():
+    m = synth.make_workload("c1").members[0]
+    errs = check_fp64(m.grid, m.u, m.v, m.w)
+    print("c1 fp64 errors u,v,w,p:", errs)
+
+
+def test_fp64_deterministic_and_bitwise_repeatable():
+    g, u, v, w = _case((96, 72, 33), 9)
+    plan = monc.Plan.from_grid(g, "f64")
+    a = run_gpu(g, u, v, w, plan=plan)
+    b = run_gpu(g, u, v, w, plan=plan)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_lid_input_ignored():
+    g, u, v, w = _case((32, 24, 10), 10)
+    w2 = w.copy()
+    w2[-1] = 123.0
+    a = run_gpu(g, u, v, w)
+    b = run_gpu(g, u, v, w2)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+# ---------------------------------------------------------------------------
+# mixed path
+# ---------------------------------------------------------------------------
+def mixed_case(g, u, v, w):
+    u32, v32, w32 = (a.astype(np.float32) for a in (u, v, w))
+    ref = oracle.project(u32.astype(np.float64), v32.astype(np.float64), w32.astype(np.float64),
+                         g.dx, g.dy, g.dz, g.rho0)
+    out = run_gpu(g, u32, v32, w32, "mixed")
+    errs = field_errors(out, ref, u32, v32, w32)
+    return errs, out, ref
+
+
+@pytest.mark.parametrize("shape", [(32, 32, 32), (48, 27, 13), (192, 96, 40), (1, 1, 4), (64, 64, 130)])
+def test_mixed_small(shape):
+    g, u, v, w = _case(shape, 11)
+    errs, out, ref = mixed_case(g, u, v, w)
+    print(f"mixed {shape}: {errs}")
+    assert max(errs) <= TOL_MIXED, errs
+    assert np.all(out[2][-1] == 0.0)
+
+
+def test_mixed_c1_grid_with_ir_gain():
+    m = synth.make_workload("c1").members[0]
+    g = m.grid
+    errs, out, ref = mixed_case(g, m.u, m.v, m.w)
+    print("c1 mixed errors u,v,w,p:", errs)
+    assert max(errs) <= TOL_MIXED, errs
+    # first pass alone (forward, solve, inverse stages) is clearly worse
+    plan = monc.Plan.from_grid(g, "mixed")
+    u32, v32, w32 = (to_dev(a.astype(np.float32), torch.float32) for a in (m.u, m.v, m.w))
+    spec = plan.spectral_buffer()
+    plan.debug_stage(monc.STAGE_FORWARD, [u32, v32, w32, spec])
+    plan.debug_stage(monc.STAGE_SOLVE, [spec])
+    p1 = torch.empty_like(u32)
+    plan.debug_stage(monc.STAGE_INVERSE, [spec, p1])
+    torch.cuda.synchronize()
+    e1 = relerr(p1.cpu().numpy().astype(np.float64), ref[3])
+    print("c1 mixed p error before refinement:", e1, "after:", errs[3])
+    assert errs[3] < e1
+
+
+# ---------------------------------------------------------------------------
+# batched
+# ---------------------------------------------------------------------------
+def _ensemble(n, shapes, seed):
+    rng = np.random.default_rng(seed)
+    mem = []
+    for i in range(n):
+        shp = shapes[rng.integers(len(shapes))]
+        g = synth.random_grid(rng, *shp, stretch=(1.0, 1.02))
+        mem.append((g,) + synth.random_fields(rng, g))
+    return mem
+
+
+@pytest.mark.parametrize("dtype", ["f64", "mixed"])
+def test_batched_equals_members_and_oracle(dtype):
+    mem = _ensemble(7, [(32, 32, 16), (48, 48, 24), (64, 32, 20), (24, 36, 12), (96, 96, 9)], 12)
+    plans = [monc.Plan.from_grid(g, dtype) for g, *_ in mem]
+    tdt = plans[0].torch_dtype
+    cast = np.float64 if dtype == "f64" else np.float32
+    fields = [[to_dev(a.astype(cast), tdt) for a in (u, v, w)] for _, u, v, w in mem]
+    ps = [torch.empty_like(f[0]) for f in fields]
+    monc.project_batched(plans, [f[0] for f in fields], [f[1] for f in fields], [f[2] for f in fields], ps)
+    torch.cuda.synchronize()
+    for i, (g, u, v, w) in enumerate(mem):
+        single = run_gpu(g, u.astype(cast), v.astype(cast), w.astype(cast), dtype)
+        got = [f.cpu().numpy().astype(np.float64) for f in fields[i]] + [ps[i].cpu().numpy().astype(np.float64)]
+        for a, b in zip(got, single):
+            assert np.array_equal(a, b), f"member {i} differs from its single projection"
+        ref = oracle.project(u.astype(cast).astype(np.float64), v.astype(cast).astype(np.float64),
+                             w.astype(cast).astype(np.float64), g.dx, g.dy, g.dz, g.rho0)
+        errs = field_errors(got, ref, u, v, w)
+        if dtype == "f64":
+            assert max(errs[:3]) <= TOL64 and errs[3] <= p_tolerance(g), (i, errs)
+        else:
+            assert max(errs) <= TOL_MIXED, (i, errs)
+
+
+def test_batched_graph_replays():
+    mem = _ensemble(5, [(32, 32, 16), (48, 24, 12), (64, 64, 8)], 13)
+    plans = [monc.Plan.from_grid(g, "mixed") for g, *_ in mem]
+    base = [[a.astype(np.float32) for a in (u, v, w)] for _, u, v, w in mem]
+    fields = [[to_dev(a, torch.float32) for a in b] for b in base]
+    ps = [torch.empty_like(f[0]) for f in fields]
+    results = []
+    for rep in range(3):
+        for f, b in zip(fields, base):           # restore the inputs eagerly
+            for t, a in zip(f, b):
+                t.copy_(torch.from_numpy(a).to(DEV))
+        torch.cuda.synchronize()
+        monc.project_batched(plans, [f[0] for f in fields], [f[1] for f in fields],
+                             [f[2] for f in fields], ps)
+        torch.cuda.synchronize()
+        results.append([[t.cpu().numpy().copy() for t in f + [p]] for f, p in zip(fields, ps)])
+    for rep in (1, 2):
+        for a, b in zip(results[0], results[rep]):
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y)
+
+
+def test_batched_rejects_mixed_dtypes():
+    g, u, v, w = _case((16, 16, 8), 14)
+    p64 = monc.Plan.from_grid(g, "f64")
+    p32 = monc.Plan.from_grid(g, "mixed")
+    a = [to_dev(x, torch.float64) for x in (u, v, w)] + [torch.empty((8, 16, 16), dtype=torch.float64, device=DEV)]
+    b = [to_dev(x, torch.float32) for x in (u, v, w)] + [torch.empty((8, 16, 16), dtype=torch.float32, device=DEV)]
+    with pytest.raises(monc.MoncError, match="mixes dtypes"):
+        monc.project_batched([p64, p32], [a[0], b[0]], [a[1], b[1]], [a[2], b[2]], [a[3], b[3]])
+
+
+def test_plan_rejects_too_many_elements_per_thread():
+    g, u, v, w = _case((96, 48, 16), 17)
+    plan = monc.Plan.from_grid(g, "f64")
+    with pytest.raises(monc.MoncError, match="elements per thread"):
+        plan.params = [16, 16, 0, 0]
+
+
+def test_plan_rejects_prime_factor_5():
+    with pytest.raises(monc.MoncError, match="prime factor"):
+        monc.Plan(5, 3, 4, 10.0, 10.0, np.full(4, 10.0), np.ones(4))
+
+
+def test_project_rejects_bad_pointers():
+    g, u, v, w = _case((16, 16, 8), 15)
+    plan = monc.Plan.from_grid(g, "f64")
+    t = to_dev(u, torch.float64)
+    L = monc.lib()
+    import ctypes
+    vp = ctypes.c_void_p
+    rc = L.monc_project(plan.handle, vp(t.data_ptr()), vp(t.data_ptr()), vp(t.data_ptr() + 8 * 16),
+                        vp(t.data_ptr()), None)
+    assert rc == monc.EINVAL
+    rc = L.monc_project(plan.handle, vp(t.data_ptr() + 8), vp(0), vp(0), vp(0), None)
+    assert rc == monc.EINVAL
+
+
+# ---------------------------------------------------------------------------
+# tuning parameters keep results within tolerance
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("params", [[4, 4, 1, 0], [2, 2, 4, 0], [8, 8, 32, 0], [8, 8, 8, 64], [8, 8, 8, 32]])
+def test_tile_parameters_do_not_change_results(params):
+    g, u, v, w = _case((96, 48, 130), 16)
+    plan = monc.Plan.from_grid(g, "f64")
+    plan.params = params
+    ref = oracle.project(u, v, w, g.dx, g.dy, g.dz, g.rho0)
+    out = run_gpu(g, u, v, w, plan=plan)
+    errs = field_errors(out, ref, u, v, w)
+    assert max(errs[:3]) <= TOL64 and errs[3] <= p_tolerance(g), errs
