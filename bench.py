@@ -1,14 +1,21 @@
 """Benchmark of the MI355X pressure projection (one GPU).
 
-    python bench.py [--steps K] [--warmup W] [--workload c1] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--workload c1|c2|c3|c4] [--no-cpu]
 
 A step is one whole projection (divergence, forward FFTs, FP64 tridiagonal
 solves, inverse FFTs, gradient correction) of the workload's fields, already
 resident in HBM; the projection re-projects its own output in place, which
-costs exactly the same kernels and bytes as the first pass. The headline is the
-plain FP64 path on the 256^2 x 128 stretched anelastic grid; the mixed
-FP32/FP64 path (with its FP64 refinement step) is timed on the same grid and
-reported beside it. Prints one JSON line.
+costs exactly the same kernels and bytes as the first pass.
+
+Workloads (seeded synthetic stand-ins for the paper's dry boundary-layer
+case, see synth/):
+  c1  256^2 x 128 stretched anelastic grid; headline = plain FP64 path, the
+      mixed FP32/FP64 path (one FP64 refinement step) timed beside it (default)
+  c2  1024^2 x 256, c1's profiles; headline = mixed path, FP64 beside it
+  c3  48-member ensemble of uneven grids, one batched call (HIP graph);
+      headline = mixed, FP64 beside it
+  c4  2048^2 x 160, k^-5/3 spectra; headline = mixed, FP64 beside it
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -28,7 +35,8 @@ sys.path.insert(0, ROOT)
 METRIC = "grid-points/s full projection (mixed vs FP64 GPU) at rel err ≤1e-6, %HBM roofline"
 HBM_PEAK_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_2009_12849_amd", "csrc", "kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c1.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+KERNELS = ["div_fftx", "ffty_fwd", "tridiag", "ffty_inv", "ifftx", "grad", "resid_fftx", "grad_final"]
 
 
 def spectral_words(nx):
@@ -67,7 +75,7 @@ def kernel_source_hash():
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def read_traffic(kernel, mixed):
+def read_traffic(workload, kernel, mixed):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None if it is missing or was taken on another version of the kernels."""
     if not os.path.exists(TRAFFIC_FILE):
@@ -81,75 +89,153 @@ def read_traffic(kernel, mixed):
                 vals[k.strip()] = v.strip()
     if vals.get("kernels_sha256_16") != kernel_source_hash():
         return None
-    key = f"{'mixed' if mixed else 'fp64'}.{kernel}.bytes_per_launch"
+    key = f"{workload}.{'mixed' if mixed else 'fp64'}.{kernel}.bytes_per_launch"
     return float(vals[key]) if key in vals else None
 
 
-def time_path(plan, fields, steps, warmup, torch, profile_kernel=None):
-    u, v, w, p = fields
-    stream = torch.cuda.current_stream()
-    for _ in range(warmup):
-        plan.project(u, v, w, p, stream)
-    torch.cuda.synchronize()
-    if profile_kernel is not None:
-        plan.profile_read()
-        from paper_2009_12849_amd import KERNELS
-        plan.profile_enable(1 << KERNELS.index(profile_kernel))
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+class Runner:
+    """Owns the plans and device fields of one path (FP64 or mixed) of a
+    workload and runs whole projections on them."""
+
+    def __init__(self, monc, torch, members, dtype):
+        self.torch = torch
+        self.monc = monc
+        self.mixed = dtype == "mixed"
+        cast = np.float32 if self.mixed else np.float64
+        self.plans = [monc.Plan.from_grid(m.grid, dtype) for m in members]
+        self.fields = []
+        for m in members:
+            f = [torch.from_numpy(a.astype(cast, copy=False)).to("cuda:0") for a in (m.u, m.v, m.w)]
+            f.append(torch.empty_like(f[0]))
+            self.fields.append(f)
+        self.batched = len(members) > 1
+        self.points = sum(m.grid.points for m in members)
+
+    def step(self, stream=None):
+        if self.batched:
+            f = self.fields
+            self.monc.project_batched(self.plans, [x[0] for x in f], [x[1] for x in f], [x[2] for x in f],
+                                      [x[3] for x in f], stream)
+        else:
+            self.plans[0].project(*self.fields[0], stream)
+
+    def breakdown(self, steps):
+        """Average ms per launch of every kernel (HIP events per launch)."""
+        torch = self.torch
+        self.plans[0].profile_read()
+        self.plans[0].profile_enable((1 << len(KERNELS)) - 1)
+        for _ in range(steps):
+            self.step()
+        torch.cuda.synchronize()
+        prof = self.plans[0].profile_read()
+        self.plans[0].profile_enable(0)
+        return {k: (ms / n, n // steps) for k, (ms, n) in prof.items()}
+
+    def timed(self, steps, warmup, profile_kernel=None):
+        """Wall-clock time of `steps` projections; with profile_kernel, HIP
+        events on the launch stream bracket every launch of that kernel."""
+        torch = self.torch
+        stream = torch.cuda.current_stream()
+        for _ in range(warmup):
+            self.step(stream)
+        torch.cuda.synchronize()
+        if profile_kernel is not None:
+            self.plans[0].profile_read()
+            self.plans[0].profile_enable(1 << KERNELS.index(profile_kernel))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            self.step(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        prof = None
+        if profile_kernel is not None:
+            prof = self.plans[0].profile_read()
+            self.plans[0].profile_enable(0)
+        return wall, prof
+
+
+def measure(runner, steps, warmup, workload, nx_bytes):
+    """Throughput, kernel breakdown and dominant-kernel roofline of a path."""
+    bd = runner.breakdown(3)
+    dom = max(bd, key=lambda k: bd[k][0] * bd[k][1])
+    wall, _ = runner.timed(steps, warmup)                    # clean timing
+    _, prof = runner.timed(steps, 0, profile_kernel=dom)     # events around the dominant kernel
+    value = runner.points * steps / wall
+    dom_ms, dom_n = prof[dom]
+    dom_avg_s = dom_ms / dom_n / 1e3
+    # bytes per launch: the kernel's bytes per step (it runs once per step, the
+    # spectral phases twice on the mixed path) over its launches per step
+    # (one, or one per group of batch members that share a kernel instance)
+    occ = 2 if (runner.mixed and dom in ("ffty_fwd", "tridiag", "ffty_inv", "ifftx")) else 1
+    per_step = occ * sum(kernel_bytes_per_point(dom, p.nx, runner.mixed) * p.nx * p.ny * p.nz
+                         for p in runner.plans)
+    per_launch = per_step / max(1, dom_n // steps)
+    achieved = per_launch / dom_avg_s / 1e9
+    path_bytes = sum(path_bytes_per_point(p.nx, runner.mixed) * p.nx * p.ny * p.nz for p in runner.plans)
+    return {
+        "value": value,
+        "ms_per_step": 1e3 * wall / steps,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": read_traffic(workload, dom, runner.mixed),
+                     "avg_launch_ms": dom_avg_s * 1e3, "algorithmic_bytes_per_launch": per_launch},
+        "path": {"algorithmic_bytes_per_point": path_bytes / runner.points,
+                 "end_to_end_hbm_frac": path_bytes * steps / wall / 1e9 / HBM_PEAK_GBS,
+                 "kernels_ms": {k: round(v[0], 5) for k, v in bd.items()},
+                 "launches_per_step": {k: v[1] for k, v in bd.items()}},
+    }
+
+
+def device_copy_gbps(torch, mb=2048, reps=10):
+    """Read+write bandwidth of a plain device-to-device copy (context for the
+    HBM peak)."""
+    n = mb * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(steps):
-        plan.project(u, v, w, p, stream)
-    e1.record(stream)
+    for _ in range(reps):
+        dst.copy_(src)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    prof = None
-    if profile_kernel is not None:
-        prof = plan.profile_read()
-        plan.profile_enable(0)
-    return wall, e0.elapsed_time(e1) / 1e3, prof
+    dt = (time.perf_counter() - t0) / reps
+    del src, dst
+    return 2 * n * 4 / dt / 1e9
 
 
-def kernel_breakdown(plan, fields, steps, torch):
-    u, v, w, p = fields
-    plan.profile_read()
-    plan.profile_enable((1 << 8) - 1)
-    for _ in range(steps):
-        plan.project(u, v, w, p)
-    torch.cuda.synchronize()
-    prof = plan.profile_read()
-    plan.profile_enable(0)
-    return {k: (ms / n, n // steps) for k, (ms, n) in prof.items()}
+def max_errors(out, ref, members_in):
+    """Normwise errors of u, v, w (relative to the input velocity scale) and p."""
+    u, v, w = members_in
+    vs = max(np.abs(u).max(), np.abs(v).max(), np.abs(w).max())
+    errs = [float(np.abs(out[t] - ref[t]).max() / vs) for t in range(3)]
+    errs.append(float(np.abs(out[3] - ref[3]).max() / np.abs(ref[3]).max()))
+    return errs
 
 
-def cpu_baseline(member, gpu_out, budget_s=25.0):
-    """The FP64 oracle timed on this host (whole projections of the same
-    workload, as many as fit the budget, at least one)."""
+def cpu_baseline(members, budget_s=25.0):
+    """The FP64 oracle timed on this host: whole projections of the workload
+    (of its first members for the ensemble), as many as fit the budget, at
+    least one. Returns the timing record and the oracle's outputs."""
     import oracle
-    g = member.grid
     workers = len(os.sched_getaffinity(0))
-    times = []
-    out = None
-    while True:
+    times, outs, pts = [], [], 0
+    for m in members:
+        g = m.grid
         t0 = time.perf_counter()
-        out = oracle.project(member.u, member.v, member.w, g.dx, g.dy, g.dz, g.rho0, workers=workers)
+        outs.append(oracle.project(m.u, m.v, m.w, g.dx, g.dy, g.dz, g.rho0, workers=workers))
         times.append(time.perf_counter() - t0)
-        if sum(times) + times[-1] > budget_s or len(times) >= 5:
+        pts += g.points
+        if sum(times) > budget_s:
             break
-    med = float(np.median(times))
-    res = {"value": g.points / med, "unit": "grid-points/s", "cores": workers, "kind": "oracle",
-           "sample": f"{len(times)} whole FP64 projections of the {g.nx}x{g.ny}x{g.nz} grid, median "
-                     f"{med:.2f} s (scipy.fft workers={workers}, NumPy elsewhere), host {platform.processor() or platform.machine()}"}
-    acc = None
-    if gpu_out is not None:
-        vs = max(np.abs(member.u).max(), np.abs(member.v).max(), np.abs(member.w).max())
-        errs = [float(np.abs(gpu_out[t] - out[t]).max() / vs) for t in range(3)]
-        errs.append(float(np.abs(gpu_out[3] - out[3]).max() / np.abs(out[3]).max()))
-        div = oracle.divergence(gpu_out[0], gpu_out[1], gpu_out[2], g.dx, g.dy, g.dz, g.rho0)
-        acc = {"max_rel_err": max(errs), "rel_err_u_v_w_p": errs, "max_abs_divergence": float(np.abs(div).max())}
-    return res, acc, out
+    tot = sum(times)
+    g0 = members[0].grid
+    what = (f"{len(times)} whole FP64 projection(s) of the {g0.nx}x{g0.ny}x{g0.nz} grid"
+            if len(members) == 1 else f"the first {len(times)} ensemble members ({pts} points)")
+    rec = {"value": pts / tot, "unit": "grid-points/s", "cores": workers, "kind": "oracle",
+           "sample": f"{what}, {tot:.2f} s (scipy.fft workers={workers}, NumPy elsewhere), "
+                     f"host {platform.processor() or platform.machine()}"}
+    return rec, outs
 
 
 def main():
@@ -157,9 +243,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c1", choices=["c1"])
+    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline leg")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--no-other", action="store_true", help="time only the headline path")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
                     help="also run a device copy of this many MB (counter calibration)")
     args = ap.parse_args()
@@ -172,95 +258,102 @@ def main():
     import synth
     import paper_2009_12849_amd as monc
 
-    dev = torch.device("cuda:0")
     wl = synth.make_workload(args.workload)
-    m = wl.members[0]
-    g = m.grid
-    npts = g.points
+    members = wl.members
+    head = "f64" if args.workload == "c1" else "mixed"
+    other = "mixed" if head == "f64" else "f64"
+    g = members[0].grid
+    desc = {
+        "c1": f"c1: plain FP64 projection {g.nx}x{g.ny}x{g.nz}, dx=dy=25 m, dz=min(10*1.015^k,60) m, "
+              f"rho0=1.2exp(-z/8 km), periodic x,y, rigid lids",
+        "c2": f"c2: mixed FP32/FP64 projection with one FP64 refinement step, {g.nx}x{g.ny}x{g.nz}, "
+              f"dz=min(10*1.015^k,60) m, rho0=1.2exp(-z/8 km)",
+        "c3": f"c3: batched ensemble of {len(members)} uneven grids (64^2x64..256^2x128), one graph launch, mixed",
+        "c4": f"c4: mixed projection {g.nx}x{g.ny}x{g.nz}, dz=5*20^(k/159) m, rho0=1.2exp(-z/8 km), "
+              f"k^-5/3 horizontal spectra",
+    }[args.workload]
 
-    # ---- FP64 path ----------------------------------------------------------
-    plan = monc.Plan.from_grid(g, "f64")
-    fields = [torch.from_numpy(a).to(dev) for a in (m.u, m.v, m.w)]
-    fields.append(torch.empty_like(fields[0]))
-    plan.project(*fields)
+    copy_gbps = device_copy_gbps(torch)
+    runner = Runner(monc, torch, members, head)
+    runner.step()
     torch.cuda.synchronize()
-    first_out = [t.cpu().numpy() for t in fields]
-    breakdown = kernel_breakdown(plan, fields, 5, torch)
-    dom = max(breakdown, key=lambda k: breakdown[k][0] * breakdown[k][1])
-    wall, ev_s, prof = time_path(plan, fields, args.steps, args.warmup, torch, profile_kernel=dom)
-    ms_step = 1e3 * wall / args.steps
-    value = npts * args.steps / wall
-    dom_ms, dom_n = prof[dom]
-    dom_avg_s = dom_ms / dom_n / 1e3
-    dom_bytes = kernel_bytes_per_point(dom, g.nx, False) * npts
-    achieved = dom_bytes / dom_avg_s / 1e9
-    traffic = read_traffic(dom, False)
-
+    nchk = 1 if len(members) == 1 else 3      # members whose outputs the oracle checks
+    first = ([[t.cpu().numpy().astype(np.float64) for t in f] for f in runner.fields[:nchk]]
+             if not args.no_cpu else None)
+    res = measure(runner, args.steps, args.warmup, args.workload, None)
     result = {
         "metric": METRIC,
-        "value": value,
+        "value": res["value"],
         "unit": "grid-points/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": res["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if head == "f64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: plain FP64 projection {g.nx}x{g.ny}x{g.nz}, dx=dy={g.dx:g} m, "
-                               f"dz=min(10*1.015^k,60) m, rho0=1.2exp(-z/8 km), periodic x,y, rigid lids",
-                   "grid_points": npts, "fields": "u,v ~ N(0,4)+8 modes, w ~ N(0,0.25), seed 2000"},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "avg_launch_ms": dom_avg_s * 1e3,
-                     "algorithmic_bytes_per_launch": dom_bytes},
-        "path": {"event_ms_per_step": 1e3 * ev_s / args.steps,
-                 "algorithmic_bytes_per_point": path_bytes_per_point(g.nx, False),
-                 "end_to_end_hbm_frac": path_bytes_per_point(g.nx, False) * value / 1e9 / HBM_PEAK_GBS,
-                 "kernels_ms": {k: round(v[0], 5) for k, v in breakdown.items()}},
+        "config": {"workload": desc, "grid_points": runner.points, "members": len(members),
+                   "path": "fp64" if head == "f64" else "mixed"},
+        "roofline": res["roofline"],
+        "path": res["path"],
+        "device_copy_GBps": copy_gbps,
     }
-
-    # ---- mixed path on the same grid ------------------------------------------
-    if not args.no_mixed:
-        mplan = monc.Plan.from_grid(g, "mixed")
-        mf = [torch.from_numpy(a.astype(np.float32)).to(dev) for a in (m.u, m.v, m.w)]
-        mf.append(torch.empty_like(mf[0]))
-        mplan.project(*mf)
+    if not args.no_other:
+        del runner
+        torch.cuda.empty_cache()
+        orun = Runner(monc, torch, members, other)
+        orun.step()
         torch.cuda.synchronize()
-        mixed_out = [t.cpu().numpy().astype(np.float64) for t in mf]
-        mbreak = kernel_breakdown(mplan, mf, 5, torch)
-        mwall, mev, _ = time_path(mplan, mf, args.steps, args.warmup, torch)
-        mvalue = npts * args.steps / mwall
-        result["mixed"] = {"value": mvalue, "ms_per_step": 1e3 * mwall / args.steps,
-                           "speedup_vs_fp64": mvalue / value,
-                           "algorithmic_bytes_per_point": path_bytes_per_point(g.nx, True),
-                           "end_to_end_hbm_frac": path_bytes_per_point(g.nx, True) * mvalue / 1e9 / HBM_PEAK_GBS,
-                           "kernels_ms": {k: round(v[0], 5) for k, v in mbreak.items()}}
+        ofirst = ([[t.cpu().numpy().astype(np.float64) for t in f] for f in orun.fields[:nchk]]
+                  if not args.no_cpu else None)
+        ores = measure(orun, args.steps, args.warmup, args.workload, None)
+        key = "mixed" if other == "mixed" else "fp64"
+        result[key] = {"value": ores["value"], "ms_per_step": ores["ms_per_step"],
+                       "roofline": ores["roofline"], "path": ores["path"]}
+        sp = res["value"] / ores["value"] if head == "mixed" else ores["value"] / res["value"]
+        result["mixed_speedup_vs_fp64"] = sp
+        del orun
+    else:
+        ofirst = None
 
     if args.calibrate_copy:
         n = args.calibrate_copy * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device=dev)
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
         result["calibration_copy_bytes"] = 2 * n * 4
 
-    # ---- CPU baseline (oracle) and accuracy ------------------------------------
     if not args.no_cpu:
-        base, acc, ref = cpu_baseline(m, first_out)
+        base, refs = cpu_baseline(members)
         result["cpu_baseline"] = base
-        result["accuracy"] = {"fp64": acc}
-        if not args.no_mixed:
-            import oracle
-            ref32 = oracle.project(*(a.astype(np.float32).astype(np.float64) for a in (m.u, m.v, m.w)),
-                                   g.dx, g.dy, g.dz, g.rho0)
-            vs = max(np.abs(m.u).max(), np.abs(m.v).max(), np.abs(m.w).max())
-            errs = [float(np.abs(mixed_out[t] - ref32[t]).max() / vs) for t in range(3)]
-            errs.append(float(np.abs(mixed_out[3] - ref32[3]).max() / np.abs(ref32[3]).max()))
-            result["accuracy"]["mixed"] = {"max_rel_err": max(errs), "rel_err_u_v_w_p": errs}
+        acc = {}
+        import oracle
+        n = min(len(refs), nchk)
+        for name, outs in (("head", first), ("other", ofirst)):
+            if outs is None:
+                continue
+            path = head if name == "head" else other
+            errs = []
+            for i in range(n):
+                m = members[i]
+                ins = (m.u, m.v, m.w)
+                ref = refs[i]
+                if path == "mixed":   # the oracle on the FP32-rounded inputs
+                    g_ = m.grid
+                    ins = tuple(a.astype(np.float32).astype(np.float64) for a in ins)
+                    ref = oracle.project(*ins, g_.dx, g_.dy, g_.dz, g_.rho0)
+                errs.append(max_errors(outs[i], ref, ins))
+            worst = [max(e[t] for e in errs) for t in range(4)]
+            div = max(float(np.abs(oracle.divergence(outs[i][0], outs[i][1], outs[i][2], members[i].grid.dx,
+                                                     members[i].grid.dy, members[i].grid.dz,
+                                                     members[i].grid.rho0)).max()) for i in range(n))
+            acc["fp64" if path == "f64" else "mixed"] = {"max_rel_err": max(worst), "rel_err_u_v_w_p": worst,
+                                                         "max_abs_divergence": div, "members_checked": n}
+        result["accuracy"] = acc
     else:
         result["cpu_baseline"] = None
     print(json.dumps(result), flush=True)

@@ -122,10 +122,13 @@ const char* monc_last_error(void);
  * and the benchmark; not needed for ordinary use).
  * ------------------------------------------------------------------- */
 
-/* Geometry of the spectral workspace: complex values are stored (nz, ny,
- * row) with row = *row_len >= nx/2+1 (padded); *elem_bytes is 16 (FP64) or
- * 8 (MIXED). Returns the number of complex elements, or 0 for NULL plan. */
-size_t monc_spectral_layout(const monc_plan* plan, int* row_len, int* elem_bytes);
+/* Geometry of the spectral workspace: value (k, n, m) of the half spectrum
+ * (m = 0..nx/2) sits at element k * (*plane_len) + n * (*row_len) + m, with
+ * row_len >= nx/2+1 and plane_len >= ny * row_len (both padded);
+ * *elem_bytes is 16 (FP64) or 8 (MIXED). Any output pointer may be NULL.
+ * Returns the number of complex elements (nz * plane_len), or 0 for a NULL
+ * plan. */
+size_t monc_spectral_layout(const monc_plan* plan, int* row_len, long long* plane_len, int* elem_bytes);
 
 /* Stage-wise execution on caller buffers (all device pointers, sizes as in
  * monc_project; `spec` holds monc_spectral_layout() complex elements):

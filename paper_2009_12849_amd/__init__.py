@@ -57,7 +57,7 @@ def lib() -> ctypes.CDLL:
     L.monc_last_error.restype = ctypes.c_char_p
     L.monc_last_error.argtypes = []
     L.monc_spectral_layout.restype = ctypes.c_size_t
-    L.monc_spectral_layout.argtypes = [vp, ctypes.POINTER(ip), ctypes.POINTER(ip)]
+    L.monc_spectral_layout.argtypes = [vp, ctypes.POINTER(ip), ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ip)]
     L.monc_debug_stage.restype = ip
     L.monc_debug_stage.argtypes = [vp, ip, ctypes.POINTER(vp), ip, vp]
     L.monc_kernel_name.restype = ctypes.c_char_p
@@ -159,16 +159,22 @@ class Plan:
 
     # -- introspection / stages / profiling / tuning ---------------------
     def spectral_layout(self):
-        row, eb = ctypes.c_int(), ctypes.c_int()
-        n = lib().monc_spectral_layout(self._h, ctypes.byref(row), ctypes.byref(eb))
-        return int(n), row.value, eb.value
+        """(elements, row length, plane length, bytes per complex value)."""
+        row, plane, eb = ctypes.c_int(), ctypes.c_longlong(), ctypes.c_int()
+        n = lib().monc_spectral_layout(self._h, ctypes.byref(row), ctypes.byref(plane), ctypes.byref(eb))
+        return int(n), row.value, plane.value, eb.value
 
     def spectral_buffer(self):
-        """A zeroed device tensor with the spectral layout (nz, ny, row)."""
+        """A zeroed device buffer with the spectral layout, shape (nz, plane)."""
         import torch
-        n, row, eb = self.spectral_layout()
+        n, row, plane, eb = self.spectral_layout()
         dt = torch.complex128 if self.dtype == FP64 else torch.complex64
-        return torch.zeros((self.nz, self.ny, row), dtype=dt, device="cuda")
+        return torch.zeros((self.nz, plane), dtype=dt, device="cuda")
+
+    def spectral_view(self, buf):
+        """The (nz, ny, nx/2+1) half spectrum inside a spectral buffer."""
+        n, row, plane, eb = self.spectral_layout()
+        return buf[:, : self.ny * row].reshape(self.nz, self.ny, row)[:, :, : self.nx // 2 + 1]
 
     def debug_stage(self, stage: int, bufs, stream=None):
         arr = (ctypes.c_void_p * len(bufs))(*[ctypes.c_void_p(b.data_ptr()) for b in bufs])

@@ -130,8 +130,9 @@ static int configure_tiles(monc_plan* pl, int ex, int ey, int ymt, int triP) {
     return fail(MONC_EUNSUPPORTED, "FFT of nx=%d or ny=%d needs more than 1024 threads", pl->nx, pl->ny);
   const size_t cb = cplx_bytes(pl->dtype);
   // y-FFT columns per workgroup: 128-byte rows by default, bounded by the
-  // workgroup size (1024) and 64 KB of LDS
-  const int mt_cap = std::max(1, std::min(1024 / fy.nt, (int)(65536 / (pl->ny * cb))));
+  // workgroup size (1024) and 128 KB of LDS
+  const int nty = ct_supported(pl->ny) ? ct_threads_y_host(pl->ny) : fy.nt;
+  const int mt_cap = std::max(1, std::min(1024 / nty, (int)(131072 / (pl->ny * cb))));
   if (ymt <= 0) ymt = pl->ymt > 0 ? pl->ymt : (int)(128 / cb);
   if (ymt > 64) return fail(MONC_EINVAL, "y-FFT columns per workgroup must be <= 64 (got %d)", ymt);
   ymt = std::max(1, std::min(ymt, mt_cap));
@@ -254,7 +255,13 @@ extern "C" monc_plan* monc_plan_create(int nx, int ny, int nz, double dx, double
   h.nxp = (h.nxh + 7) / 8 * 8;
   h.dtype = dtype;
   h.nrow = (long long)nz * ny;
+  // spectral level stride: an odd multiple of 256 bytes, so that the
+  // tridiagonal solver's walk down a column does not revisit one HBM channel
   h.plane = (long long)ny * h.nxp;
+  {
+    const long long cbytes = (long long)cplx_bytes(dtype);
+    if (((h.plane * cbytes) / 256) % 2 == 0) h.plane += 256 / cbytes;
+  }
   h.rdx = 1.0 / dx;
   h.rdy = 1.0 / dy;
   h.inv_nxny = 1.0 / ((double)nx * (double)ny);
@@ -325,7 +332,7 @@ extern "C" monc_plan* monc_plan_create(int nx, int ny, int nz, double dx, double
     fail(MONC_EHIP, "hipGetDevice failed (no usable HIP device)");
     return nullptr;
   }
-  pl->spec_elems = (size_t)nz * ny * h.nxp;
+  pl->spec_elems = (size_t)nz * h.plane;
   auto release = [&]() {
     if (pl->d_tables) (void)hipFree(pl->d_tables);
     if (pl->d_spec) (void)hipFree(pl->d_spec);
@@ -388,9 +395,10 @@ extern "C" void monc_plan_destroy(monc_plan* pl) {
 
 extern "C" const char* monc_last_error(void) { return g_err.c_str(); }
 
-extern "C" size_t monc_spectral_layout(const monc_plan* pl, int* row_len, int* eb) {
+extern "C" size_t monc_spectral_layout(const monc_plan* pl, int* row_len, long long* plane_len, int* eb) {
   if (!pl) return 0;
   if (row_len) *row_len = pl->h.nxp;
+  if (plane_len) *plane_len = pl->h.plane;
   if (eb) *eb = (int)cplx_bytes(pl->dtype);
   return pl->spec_elems;
 }
@@ -467,7 +475,7 @@ static Shape member_shape(const MemberDesc& d, Phase ph, bool fp64) {
     }
   } else if (is_yphase(ph)) {
     if (ct_supported(d.ny)) {
-      const int nt = ct_threads_host(d.ny);
+      const int nt = ct_threads_y_host(d.ny);
       const int mt = std::max(1, std::min(d.ymt, 1024 / nt));
       s.variant = d.ny;
       s.block = mt * nt;
@@ -480,11 +488,13 @@ static Shape member_shape(const MemberDesc& d, Phase ph, bool fp64) {
     }
   } else if (ph == PH_TRI) {
     s.variant = d.tris;
-    s.lds = (size_t)256 * (d.tris + 1) * 16;
+    s.lds = (size_t)d.tricw * (d.triP * (d.tris + 1) + 1) * 16;  // matches the kernel's column stride
     s.blocks = ((long long)d.ny * d.nxh + d.tricw - 1) / d.tricw;
   } else {
-    const long long nh = (long long)d.nx * d.ny;
-    s.blocks = ((nh + 255) / 256) * ((d.nz + kGradChunk - 1) / kGradChunk);
+    const int vec = (d.nx % 2 == 0) ? 2 : 1;
+    const long long nvec = (long long)d.nx * d.ny * d.nz / vec;
+    s.variant = vec;
+    s.blocks = (nvec + 255) / 256;
   }
   return s;
 }
@@ -531,8 +541,8 @@ static int launch_one(const Group& g, const std::vector<int>& idx, Phase ph, con
     case PH_TRI: launch_tridiag(a, grid, lds, g.fp64, v, stream); break;
     case PH_XINV: launch_xinv(a, grid, block, lds, g.fp64, 0, v, stream); break;
     case PH_XINV_CORR: launch_xinv(a, grid, block, lds, false, 1, v, stream); break;
-    case PH_GRAD: launch_grad(a, grid, g.fp64, 0, stream); break;
-    case PH_GRAD_MIXED: launch_grad(a, grid, false, 1, stream); break;
+    case PH_GRAD: launch_grad(a, grid, g.fp64, 0, v, stream); break;
+    case PH_GRAD_MIXED: launch_grad(a, grid, false, 1, v, stream); break;
   }
   hipError_t le = hipGetLastError();
   if (timed) {

@@ -11,9 +11,11 @@ void init_kernel_attributes();
 
 // Transform lengths with a compile-time FFT kernel (others take the
 // runtime-length kernels); such kernels use n/8 threads per transform (1 if
-// n < 8) and need blockDim = (transforms or columns per workgroup) * that.
+// n < 8; along y n/16 from n = 2048 on) and need blockDim = (transforms or
+// columns per workgroup) * that.
 bool ct_supported(int n);
 inline int ct_threads_host(int n) { return n >= 8 ? n / 8 : 1; }
+inline int ct_threads_y_host(int n) { return n >= 2048 ? n / 16 : ct_threads_host(n); }
 
 // ct_n: the compile-time length, or 0 for the runtime-length kernel.
 // mode 0: divergence of (u, v, w); mode 1 (float only): FP64 residual
@@ -25,7 +27,8 @@ void launch_ffty(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64
 void launch_tridiag(const LaunchArgs& a, int grid, size_t lds, bool fp64, int rows, void* stream);
 // mode 0: write p; mode 1 (float only): p = p1 + delta (float) and wbuf (FP64)
 void launch_xinv(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, int mode, int ct_n, void* stream);
-// mixed = 0: pressure from io.p (FP64); mixed = 1: from MemberDesc::wbuf
-void launch_grad(const LaunchArgs& a, int grid, bool fp64, int mixed, void* stream);
+// mixed = 0: pressure from io.p (FP64); mixed = 1: from MemberDesc::wbuf.
+// vec: points per thread (2 needs an even nx, else 1)
+void launch_grad(const LaunchArgs& a, int grid, bool fp64, int mixed, int vec, void* stream);
 
 }  // namespace monc

@@ -32,6 +32,28 @@ __device__ __forceinline__ int find_member(const LaunchArgs& a, int b) {
   return m;
 }
 
+// Load through a global-address-space pointer (table pointers held in a
+// descriptor are generic, which would otherwise become flat loads).
+template <typename T>
+__device__ __forceinline__ T ldg(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+
+// Workgroups go to the 8 XCDs round-robin (XCD = blockIdx mod 8), each XCD
+// with its own L2. Remap a member's local block index so that every XCD
+// works through one contiguous range of tiles: neighbouring rows and levels,
+// which the stencils read twice, then meet in the same L2. Applies when the
+// member's first block sits on XCD 0; the tail beyond a multiple of 8 keeps
+// its index.
+__device__ __forceinline__ int xcd_local_block(const LaunchArgs& a, int mi) {
+  const int start = a.block_start[mi];
+  const int lb = blockIdx.x - start;
+  if (start & 7) return lb;
+  const int full = (a.block_start[mi + 1] - start) & ~7;
+  if (lb >= full) return lb;
+  return (lb & 7) * (full >> 3) + (lb >> 3);
+}
+
 // ---------------------------------------------------------------------------
 // per-row context of the stencils: offsets of the neighbouring rows and the
 // vertical metrics of the row's level
@@ -61,16 +83,17 @@ __device__ __forceinline__ RowCtx make_row(const MemberDesc& d, long long row, b
   c.plane = (long long)ny * d.nx;
   c.top = k < nz - 1;
   c.bot = k > 0;
-  c.rho0 = d.rho0[k];
-  c.rdz = d.rdz[k];
-  c.rhow = c.top ? d.rhow[k] : 0.0;
-  c.rdzc = c.top ? d.rdzc[k] : 0.0;
-  c.rhowm = c.bot ? d.rhow[k - 1] : 0.0;
-  c.rdzcm = c.bot ? d.rdzc[k - 1] : 0.0;
-  c.rho0f = d.rho0f[k];
-  c.rdzf = d.rdzf[k];
-  c.rhowf = c.top ? d.rhowf[k] : 0.0f;
-  c.rhowmf = c.bot ? d.rhowf[k - 1] : 0.0f;
+  const int km = c.bot ? k - 1 : k;
+  c.rho0 = ldg(d.rho0 + k);
+  c.rdz = ldg(d.rdz + k);
+  c.rhow = ldg(d.rhow + k);    // 0 on the lid row
+  c.rdzc = ldg(d.rdzc + k);    // 0 on the lid row
+  c.rhowm = c.bot ? ldg(d.rhow + km) : 0.0;
+  c.rdzcm = c.bot ? ldg(d.rdzc + km) : 0.0;
+  c.rho0f = ldg(d.rho0f + k);
+  c.rdzf = ldg(d.rdzf + k);
+  c.rhowf = ldg(d.rhowf + k);
+  c.rhowmf = c.bot ? ldg(d.rhowf + km) : 0.0f;
   return c;
 }
 
@@ -130,11 +153,18 @@ __device__ __forceinline__ T source_at(const MemberDesc& d, const RowCtx& c, con
 // Separate two real rows packed as z = a + i b:
 // A[m] = (Z[m] + conj Z[N-m])/2, B[m] = (Z[m] - conj Z[N-m])/(2i).
 template <typename T>
-__device__ __forceinline__ void split_store(cx<T>* S, long long r0, long long r1, bool v0, bool v1, int nxp, int m,
-                                            cx<T> z, cx<T> zr) {
+__device__ __forceinline__ void split_store(cx<T>* S, long long o0, long long o1, bool v0, bool v1, int m, cx<T> z,
+                                            cx<T> zr) {
   const T h = (T)0.5;
-  if (v0) S[r0 * nxp + m] = cx<T>{h * (z.x + zr.x), h * (z.y - zr.y)};
-  if (v1) S[r1 * nxp + m] = cx<T>{h * (z.y + zr.y), h * (zr.x - z.x)};
+  if (v0) S[o0 + m] = cx<T>{h * (z.x + zr.x), h * (z.y - zr.y)};
+  if (v1) S[o1 + m] = cx<T>{h * (z.y + zr.y), h * (zr.x - z.x)};
+}
+
+// Offset of spectral row r = k*ny + j: levels are `plane` apart (padded so
+// that the plane stride is an odd multiple of 256 bytes), rows nxp apart.
+__device__ __forceinline__ long long spec_row(const MemberDesc& d, long long r) {
+  const int k = (int)(r / d.ny);
+  return (long long)k * d.plane + (r - (long long)k * d.ny) * d.nxp;
 }
 
 // ---------------------------------------------------------------------------
@@ -149,7 +179,7 @@ __global__ void __launch_bounds__(512) k_xfwd_ct(LaunchArgs a) {
   const int mi = find_member(a, blockIdx.x);
   const MemberDesc& d = *a.mem[mi];
   const IoPtrs io = a.io[mi];
-  const int lb = blockIdx.x - a.block_start[mi];
+  const int lb = xcd_local_block(a, mi);
   const int ipw = blockDim.x / NT;
   const int inst = threadIdx.x / NT;
   const int q = threadIdx.x - inst * NT;
@@ -184,10 +214,11 @@ __global__ void __launch_bounds__(512) k_xfwd_ct(LaunchArgs a) {
   }
   __syncthreads();
   cx<T>* S = reinterpret_cast<cx<T>*>(io.spec);
+  const long long so0 = spec_row(d, v0 ? r0 : 0), so1 = spec_row(d, v1 ? r1 : 0);
   for (int m = q; m < d.nxh; m += NT) {
     const cx<T> z = lds[xpad<T>(m)];
     const cx<T> zr = lds[xpad<T>(m == 0 ? 0 : N - m)];
-    split_store<T>(S, r0, r1, v0, v1, d.nxp, m, z, zr);
+    split_store<T>(S, so0, so1, v0, v1, m, z, zr);
   }
 }
 
@@ -199,7 +230,7 @@ __global__ void __launch_bounds__(1024) k_xfwd_gen(LaunchArgs a) {
   const int mi = find_member(a, blockIdx.x);
   const MemberDesc& d = *a.mem[mi];
   const IoPtrs io = a.io[mi];
-  const int lb = blockIdx.x - a.block_start[mi];
+  const int lb = xcd_local_block(a, mi);
   const int N = d.nx, nt = d.fx.nt;
   const int ipw = blockDim.x / nt;
   const int inst = threadIdx.x / nt;
@@ -221,7 +252,8 @@ __global__ void __launch_bounds__(1024) k_xfwd_gen(LaunchArgs a) {
   fft_lds<T, false>(buf, 1, d.fx, reinterpret_cast<const cx<T>*>(d.twx), q);
   if (active) {
     cx<T>* S = reinterpret_cast<cx<T>*>(io.spec);
-    for (int m = q; m < d.nxh; m += nt) split_store<T>(S, r0, r1, v0, v1, d.nxp, m, buf[m], buf[m == 0 ? 0 : N - m]);
+    const long long so0 = spec_row(d, v0 ? r0 : 0), so1 = spec_row(d, v1 ? r1 : 0);
+    for (int m = q; m < d.nxh; m += nt) split_store<T>(S, so0, so1, v0, v1, m, buf[m], buf[m == 0 ? 0 : N - m]);
   }
 }
 
@@ -232,14 +264,14 @@ __global__ void __launch_bounds__(1024) k_xfwd_gen(LaunchArgs a) {
 // ---------------------------------------------------------------------------
 template <typename T, bool INV, int N>
 __global__ void __launch_bounds__(1024) k_ffty_ct(LaunchArgs a) {
-  constexpr int NT = ct_threads(N);
+  constexpr int NT = ct_threads_y(N);
   using F = CtFft<T, N, NT, INV>;
   extern __shared__ unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   const int mi = find_member(a, blockIdx.x);
   const MemberDesc& d = *a.mem[mi];
   const IoPtrs io = a.io[mi];
-  const int lb = blockIdx.x - a.block_start[mi];
+  const int lb = xcd_local_block(a, mi);
   const int mt = blockDim.x / NT;
   const int tiles = (d.nxh + mt - 1) / mt;
   const int k = lb / tiles;
@@ -279,7 +311,7 @@ __global__ void __launch_bounds__(1024) k_ffty_gen(LaunchArgs a) {
   const int mi = find_member(a, blockIdx.x);
   const MemberDesc& d = *a.mem[mi];
   const IoPtrs io = a.io[mi];
-  const int lb = blockIdx.x - a.block_start[mi];
+  const int lb = xcd_local_block(a, mi);
   const int mt = d.ymt, ny = d.ny, nt = d.fy.nt;
   const int tiles = (d.nxh + mt - 1) / mt;
   const int k = lb / tiles;
@@ -310,10 +342,21 @@ __global__ void __launch_bounds__(1024) k_ffty_gen(LaunchArgs a) {
 // imaginary parts of the self-conjugate bins (m = 0, m = N/2) are dropped.
 // ---------------------------------------------------------------------------
 template <typename T, class Idx>
-__device__ __forceinline__ void pack_rows(cx<T>* buf, const Idx& idx, const cx<T>* __restrict__ S, long long r0,
-                                          long long r1, bool v0, bool v1, int nxp, int N, int m) {
-  cx<T> xa = v0 ? S[r0 * nxp + m] : cx<T>{0, 0};
-  cx<T> xb = v1 ? S[r1 * nxp + m] : cx<T>{0, 0};
+__device__ __forceinline__ void pack_bins(cx<T>* buf, const Idx& idx, cx<T> xa, cx<T> xb, int N, int m) {
+  const bool selfconj = (m == 0) || (2 * m == N);
+  if (selfconj) {
+    xa.y = 0;
+    xb.y = 0;
+  }
+  buf[idx(m)] = cx<T>{xa.x - xb.y, xa.y + xb.x};
+  if (!selfconj) buf[idx(N - m)] = cx<T>{xa.x + xb.y, xb.x - xa.y};
+}
+
+template <typename T, class Idx>
+__device__ __forceinline__ void pack_rows(cx<T>* buf, const Idx& idx, const cx<T>* __restrict__ S, long long o0,
+                                          long long o1, bool v0, bool v1, int N, int m) {
+  cx<T> xa = v0 ? S[o0 + m] : cx<T>{0, 0};
+  cx<T> xb = v1 ? S[o1 + m] : cx<T>{0, 0};
   const bool selfconj = (m == 0) || (2 * m == N);
   if (selfconj) {
     xa.y = 0;
@@ -363,7 +406,24 @@ __global__ void __launch_bounds__(512) k_xinv_ct(LaunchArgs a) {
   const bool v0 = r0 < d.nrow, v1 = r1 < d.nrow;
   const cx<T>* S = reinterpret_cast<const cx<T>*>(io.spec);
   auto li = [](int i) { return xpad<T>(i); };
-  for (int m = q; m < d.nxh; m += NT) pack_rows<T>(lds, li, S, r0, r1, v0, v1, d.nxp, N, m);
+  {
+    // nx/2 + 1 bins over NT threads: N/(2 NT) + 1 rounds, loads issued first
+    constexpr int RND = N / (2 * NT) + 1;
+    const long long so0 = spec_row(d, v0 ? r0 : 0), so1 = spec_row(d, v1 ? r1 : 0);
+    cx<T> xa[RND], xb[RND];
+#pragma unroll
+    for (int t = 0; t < RND; ++t) {
+      const int m = q + t * NT;
+      const bool in = m <= N / 2;
+      xa[t] = (in && v0) ? S[so0 + m] : cx<T>{0, 0};
+      xb[t] = (in && v1) ? S[so1 + m] : cx<T>{0, 0};
+    }
+#pragma unroll
+    for (int t = 0; t < RND; ++t) {
+      const int m = q + t * NT;
+      if (m <= N / 2) pack_bins<T>(lds, li, xa[t], xb[t], N, m);
+    }
+  }
   __syncthreads();
   cx<T> v[F::VMAX];
 #pragma unroll
@@ -405,8 +465,9 @@ __global__ void __launch_bounds__(1024) k_xinv_gen(LaunchArgs a) {
   const bool v0 = active && r0 < d.nrow, v1 = active && r1 < d.nrow;
   const cx<T>* S = reinterpret_cast<const cx<T>*>(io.spec);
   auto ident = [](int i) { return i; };
+  const long long so0 = spec_row(d, v0 ? r0 : 0), so1 = spec_row(d, v1 ? r1 : 0);
   if (active)
-    for (int m = q; m < d.nxh; m += nt) pack_rows<T>(buf, ident, S, r0, r1, v0, v1, d.nxp, N, m);
+    for (int m = q; m < d.nxh; m += nt) pack_rows<T>(buf, ident, S, so0, so1, v0, v1, N, m);
   __syncthreads();
   fft_lds<T, true>(buf, 1, d.fx, reinterpret_cast<const cx<T>*>(d.twx), q);
   if (active)
@@ -442,6 +503,24 @@ __device__ __forceinline__ Row5 shfl_row(const Row5& r, int src) {
   return Row5{shfl_d(r.a, src), shfl_d(r.b, src), shfl_d(r.c, src), shfl_d(r.x, src), shfl_d(r.y, src)};
 }
 
+// 1/x in FP64: the hardware reciprocal refined by one Newton step (error
+// about one ulp; the solve does not need the correctly rounded quotient)
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  const double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  return r;
+}
+
+// sum over the P lanes of a column (aligned power-of-two lane group)
+__device__ __forceinline__ double2 column_sum(double2 v, int P) {
+  for (int o = P / 2; o > 0; o /= 2) {
+    v.x += __shfl_xor(v.x, o);
+    v.y += __shfl_xor(v.y, o);
+  }
+  return v;
+}
+
 template <typename TS, int S>
 __global__ void __launch_bounds__(256) k_tridiag(LaunchArgs a) {
   extern __shared__ unsigned char smem_raw[];
@@ -449,31 +528,37 @@ __global__ void __launch_bounds__(256) k_tridiag(LaunchArgs a) {
   const int mi = find_member(a, blockIdx.x);
   const MemberDesc& d = *a.mem[mi];
   const IoPtrs io = a.io[mi];
-  const int lb = blockIdx.x - a.block_start[mi];
+  const int lb = xcd_local_block(a, mi);
   const int P = d.triP, CW = d.tricw, nz = d.nz, nxh = d.nxh;
   constexpr int SP = S + 1;                  // padded chunk length in LDS
-  const int lrow = P * SP;                   // staged column length
+  const int lrow = P * SP + 1;               // odd stride: columns start in different banks
   const int ncols = d.ny * nxh;
   const int col0 = lb * CW;
   using CS = cx<TS>;
   CS* Sg = reinterpret_cast<CS*>(io.spec);
   auto slot = [](int k) { return (k / S) * SP + (k % S); };
 
-  // 1. coalesced load of CW columns x nz levels into LDS (the thread's
-  //    column is fixed because CW divides the workgroup size)
+  // 1. coalesced load of CW columns x nz levels into LDS. CW divides the
+  //    workgroup, so a thread's column is fixed and it stages levels
+  //    k = tid/CW + j P, j < S (256/CW = P lanes, S rows each cover nz);
+  //    every load is issued before the first LDS write.
+  const int kth = threadIdx.x / CW;
   {
     const int cc = threadIdx.x % CW;
     const int col = col0 + cc;
     const bool ok = col < ncols;
     const int n = ok ? col / nxh : 0;
-    const long long base = (long long)n * d.nxp + (ok ? col - n * nxh : 0);
-    for (int k = threadIdx.x / CW; k < nz; k += 256 / CW) {
-      double2 val = make_double2(0.0, 0.0);
-      if (ok) {
-        const CS x = Sg[(long long)k * d.plane + base];
-        val = make_double2((double)x.x, (double)x.y);
-      }
-      stage[cc * lrow + slot(k)] = val;
+    const CS* src = Sg + (long long)n * d.nxp + (ok ? col - n * nxh : 0);
+    CS ld[S];
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      const int k = kth + j * P;
+      ld[j] = (ok && k < nz) ? src[(long long)k * d.plane] : CS{0, 0};
+    }
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      const int k = kth + j * P;
+      if (k < nz) stage[cc * lrow + slot(k)] = make_double2((double)ld[j].x, (double)ld[j].y);
     }
   }
 
@@ -492,14 +577,19 @@ __global__ void __launch_bounds__(256) k_tridiag(LaunchArgs a) {
     const int n = col / nxh, m = col - n * nxh;
     lam = d.lamy[n] + d.lamx[m];
   }
-  double A[S], B[S], C[S];
+  double A[S], B[S], C[S], R0[S];
+#pragma unroll
+  for (int r = 0; r < S; ++r) {  // unconditional loads (clamped level), selected below
+    const int k = min(k0 + r, nz - 1);
+    A[r] = ldg(d.ta + k);
+    C[r] = ldg(d.tc + k);
+    R0[r] = ldg(d.rho0 + k);
+  }
 #pragma unroll
   for (int r = 0; r < S; ++r) {
     const int k = k0 + r;
     if (valid && k < nz && !(singular && k == nz - 1)) {
-      A[r] = d.ta[k];
-      C[r] = d.tc[k];
-      B[r] = -(A[r] + C[r]) - d.rho0[k] * lam;
+      B[r] = -(A[r] + C[r]) - R0[r] * lam;
     } else {
       A[r] = 0.0;
       B[r] = 1.0;
@@ -508,29 +598,35 @@ __global__ void __launch_bounds__(256) k_tridiag(LaunchArgs a) {
   }
   __syncthreads();
 
-  // (0,0) column: remove the dz-weighted mean of the right-hand side
-  if (singular && q == 0) {
-    double sr = 0.0, si = 0.0;
-    for (int k = 0; k < nz; ++k) {
-      const double2 b = scol[slot(k)];
-      sr += d.dz[k] * b.x;
-      si += d.dz[k] * b.y;
-    }
-    sr *= d.rH;
-    si *= d.rH;
-    for (int k = 0; k < nz; ++k) {
-      double2& b = scol[slot(k)];
-      b.x -= sr;
-      b.y -= si;
-    }
-  }
-  __syncthreads();
-
   double2 D[S];
 #pragma unroll
   for (int r = 0; r < S; ++r) {
     const int k = k0 + r;
-    D[r] = (valid && k < nz && !(singular && k == nz - 1)) ? scol[q * SP + r] : make_double2(0.0, 0.0);
+    D[r] = (valid && k < nz) ? scol[q * SP + r] : make_double2(0.0, 0.0);
+  }
+  // (0,0) column (one per member, lanes of one wave): remove the dz-weighted
+  // mean of the right-hand side, then pin the top row (identity, rhs 0)
+  double DZ[S];
+  if (singular) {
+#pragma unroll
+    for (int r = 0; r < S; ++r) DZ[r] = (k0 + r < nz) ? ldg(d.dz + (k0 + r)) : 0.0;
+    double2 sum = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int r = 0; r < S; ++r) {
+      sum.x += DZ[r] * D[r].x;
+      sum.y += DZ[r] * D[r].y;
+    }
+    sum = column_sum(sum, P);
+#pragma unroll
+    for (int r = 0; r < S; ++r) {
+      const int k = k0 + r;
+      if (k < nz - 1) {
+        D[r].x -= sum.x * d.rH;
+        D[r].y -= sum.y * d.rH;
+      } else {
+        D[r] = make_double2(0.0, 0.0);
+      }
+    }
   }
 
   // 1. chunk elimination: x_r + al_r x_0 + ga_r x_{r+1} = de_r (r >= 1), then
@@ -540,12 +636,12 @@ __global__ void __launch_bounds__(256) k_tridiag(LaunchArgs a) {
 #pragma unroll
   for (int r = 1; r < S; ++r) {
     if (r == 1) {
-      const double inv = 1.0 / B[1];
+      const double inv = rcp64(B[1]);
       al[1] = A[1] * inv;
       ga[1] = C[1] * inv;
       de[1] = make_double2(D[1].x * inv, D[1].y * inv);
     } else {
-      const double inv = 1.0 / (B[r] - A[r] * ga[r - 1]);
+      const double inv = rcp64(B[r] - A[r] * ga[r - 1]);
       al[r] = -A[r] * al[r - 1] * inv;
       ga[r] = C[r] * inv;
       de[r] = make_double2((D[r].x - A[r] * de[r - 1].x) * inv, (D[r].y - A[r] * de[r - 1].y) * inv);
@@ -588,8 +684,8 @@ __global__ void __launch_bounds__(256) k_tridiag(LaunchArgs a) {
     const bool hasl = q - h >= 0, hasr = q + h < P;
     const Row5 lo = shfl_row(row, hasl ? lane - h : lane);
     const Row5 hi = shfl_row(row, hasr ? lane + h : lane);
-    const double k1 = hasl ? row.a / lo.b : 0.0;
-    const double k2 = hasr ? row.c / hi.b : 0.0;
+    const double k1 = hasl ? row.a * rcp64(lo.b) : 0.0;
+    const double k2 = hasr ? row.c * rcp64(hi.b) : 0.0;
     Row5 nr;
     nr.a = hasl ? -lo.a * k1 : 0.0;
     nr.c = hasr ? -hi.c * k2 : 0.0;
@@ -598,41 +694,38 @@ __global__ void __launch_bounds__(256) k_tridiag(LaunchArgs a) {
     nr.y = row.y - (hasl ? lo.y * k1 : 0.0) - (hasr ? hi.y * k2 : 0.0);
     row = nr;
   }
-  const double rb = 1.0 / row.b;
+  const double rb = rcp64(row.b);
   const double2 F = make_double2(row.x * rb, row.y * rb);
 
   // 4. L_q = dL - aL F_q - cL F_{q+1}, then the chunk's interior rows
   const double Fnx = shfl_d(F.x, dn), Fny = shfl_d(F.y, dn);
   const double2 Fn = (q < P - 1) ? make_double2(Fnx, Fny) : make_double2(0.0, 0.0);
   const double2 L = make_double2(dL.x - aL * F.x - cL * Fn.x, dL.y - aL * F.y - cL * Fn.y);
-  __syncthreads();  // the (0,0) lane has finished with the staged right-hand side
+  double2 X[S];
 #pragma unroll
   for (int r = 0; r < S; ++r) {
-    const int k = k0 + r;
-    double2 x;
-    if (r == 0) x = F;
-    else if (r == S - 1) x = L;
-    else x = make_double2(de[r].x - al[r] * F.x - ga[r] * L.x, de[r].y - al[r] * F.y - ga[r] * L.y);
-    if (k < nz) scol[q * SP + r] = x;
+    if (r == 0) X[r] = F;
+    else if (r == S - 1) X[r] = L;
+    else X[r] = make_double2(de[r].x - al[r] * F.x - ga[r] * L.x, de[r].y - al[r] * F.y - ga[r] * L.y);
   }
-  __syncthreads();
-
   // (0,0) column: gauge sum_k dz_k P_k = 0
-  if (singular && q == 0) {
-    double sr = 0.0, si = 0.0;
-    for (int k = 0; k < nz; ++k) {
-      const double2 x = scol[slot(k)];
-      sr += d.dz[k] * x.x;
-      si += d.dz[k] * x.y;
+  if (singular) {
+    double2 sum = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int r = 0; r < S; ++r) {
+      sum.x += DZ[r] * X[r].x;
+      sum.y += DZ[r] * X[r].y;
     }
-    sr *= d.rH;
-    si *= d.rH;
-    for (int k = 0; k < nz; ++k) {
-      double2& x = scol[slot(k)];
-      x.x -= sr;
-      x.y -= si;
+    sum = column_sum(sum, P);
+#pragma unroll
+    for (int r = 0; r < S; ++r) {
+      X[r].x -= sum.x * d.rH;
+      X[r].y -= sum.y * d.rH;
     }
   }
+#pragma unroll
+  for (int r = 0; r < S; ++r)
+    if (k0 + r < nz) scol[q * SP + r] = X[r];
   __syncthreads();
 
   // coalesced store, scaled by 1/(nx ny)
@@ -642,10 +735,17 @@ __global__ void __launch_bounds__(256) k_tridiag(LaunchArgs a) {
     const int cl = col0 + cc;
     if (cl < ncols) {
       const int n = cl / nxh;
-      const long long base = (long long)n * d.nxp + (cl - n * nxh);
-      for (int k = threadIdx.x / CW; k < nz; k += 256 / CW) {
-        const double2 x = stage[cc * lrow + slot(k)];
-        Sg[(long long)k * d.plane + base] = CS{(TS)(x.x * sc), (TS)(x.y * sc)};
+      CS* dst = Sg + (long long)n * d.nxp + (cl - n * nxh);
+      double2 x[S];
+#pragma unroll
+      for (int j = 0; j < S; ++j) {
+        const int k = kth + j * P;
+        if (k < nz) x[j] = stage[cc * lrow + slot(k)];
+      }
+#pragma unroll
+      for (int j = 0; j < S; ++j) {
+        const int k = kth + j * P;
+        if (k < nz) dst[(long long)k * d.plane] = CS{(TS)(x[j].x * sc), (TS)(x[j].y * sc)};
       }
     }
   }
@@ -654,43 +754,51 @@ __global__ void __launch_bounds__(256) k_tridiag(LaunchArgs a) {
 // ---------------------------------------------------------------------------
 // Pressure-gradient correction u -= G p, evaluated in FP64 from an FP64
 // pressure (p itself on the FP64 path, p1 + delta on the mixed path); the
-// fields are T. One thread per (j, i) column walks kGradChunk levels downward
-// so that p_{k+1} is carried in a register. w[nz-1] = 0.
+// fields are T. A thread owns VEC consecutive points of one row of one
+// level (vector loads and stores need nx % VEC == 0); w[nz-1] = 0.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int VEC>
 __global__ void __launch_bounds__(256) k_grad(LaunchArgs a, int mixed) {
+  typedef T tv __attribute__((ext_vector_type(VEC)));
+  typedef double dv __attribute__((ext_vector_type(VEC)));
   const int mi = find_member(a, blockIdx.x);
   const MemberDesc& d = *a.mem[mi];
   const IoPtrs io = a.io[mi];
-  const int lb = blockIdx.x - a.block_start[mi];
+  const int lb = xcd_local_block(a, mi);
   const int nx = d.nx, ny = d.ny, nz = d.nz;
   const long long nh = (long long)nx * ny;
-  const int hblocks = (int)((nh + blockDim.x - 1) / blockDim.x);
-  const int kc = lb / hblocks;
-  const long long h = (long long)(lb - kc * hblocks) * blockDim.x + threadIdx.x;
-  if (h >= nh) return;
+  const long long g = ((long long)lb * blockDim.x + threadIdx.x) * VEC;  // first point
+  if (g >= nh * nz) return;
+  const int k = (int)(g / nh);
+  const long long h = g - (long long)k * nh;
   const int j = (int)(h / nx), i = (int)(h - (long long)j * nx);
-  const long long he = (long long)j * nx + ((i == nx - 1) ? 0 : i + 1);
-  const long long hn = (long long)((j == ny - 1) ? 0 : j + 1) * nx + i;
+  const long long base = (long long)k * nh;
+  const long long he = base + (long long)j * nx + ((i + VEC == nx) ? 0 : i + VEC);  // east of the last point
+  const long long hn = base + (long long)((j == ny - 1) ? 0 : j + 1) * nx + i;
   const double* __restrict__ p = mixed ? d.wbuf : reinterpret_cast<const double*>(io.p);
   T* __restrict__ u = reinterpret_cast<T*>(io.u);
   T* __restrict__ v = reinterpret_cast<T*>(io.v);
   T* __restrict__ w = reinterpret_cast<T*>(io.w);
-  const int k0 = kc * kGradChunk;
-  const int k1 = min(nz, k0 + kGradChunk);
-  double pup = (k1 < nz) ? p[(long long)k1 * nh + h] : 0.0;
-#pragma unroll 4
-  for (int k = k1 - 1; k >= k0; --k) {
-    const long long base = (long long)k * nh;
-    const double pc = p[base + h];
-    const double pe = p[base + he];
-    const double pn = p[base + hn];
-    u[base + h] = (T)((double)u[base + h] - (pe - pc) * d.rdx);
-    v[base + h] = (T)((double)v[base + h] - (pn - pc) * d.rdy);
-    if (k == nz - 1) w[base + h] = (T)0;
-    else w[base + h] = (T)((double)w[base + h] - (pup - pc) * d.rdzc[k]);
-    pup = pc;
+  const bool top = k == nz - 1;
+  const dv pc = *reinterpret_cast<const dv*>(p + g);
+  const dv pn = *reinterpret_cast<const dv*>(p + hn);
+  const double pel = p[he];
+  const dv pu = top ? pc : *reinterpret_cast<const dv*>(p + g + nh);
+  tv uu = *reinterpret_cast<const tv*>(u + g);
+  tv vv = *reinterpret_cast<const tv*>(v + g);
+  tv ww = *reinterpret_cast<const tv*>(w + g);
+  const double rz = ldg(d.rdzc + k);  // 0 on the lid row
+  const double rdx = d.rdx, rdy = d.rdy;
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) {
+    const double pe = (e + 1 < VEC) ? pc[(e + 1) % VEC] : pel;
+    uu[e] = (T)((double)uu[e] - (pe - pc[e]) * rdx);
+    vv[e] = (T)((double)vv[e] - (pn[e] - pc[e]) * rdy);
+    ww[e] = top ? (T)0 : (T)((double)ww[e] - (pu[e] - pc[e]) * rz);
   }
+  *reinterpret_cast<tv*>(u + g) = uu;
+  *reinterpret_cast<tv*>(v + g) = vv;
+  *reinterpret_cast<tv*>(w + g) = ww;
 }
 
 // ---------------------------------------------------------------------------
@@ -822,9 +930,16 @@ void launch_tridiag(const LaunchArgs& a, int grid, size_t lds, bool fp64, int ro
   }
 }
 
-void launch_grad(const LaunchArgs& a, int grid, bool fp64, int mixed, void* stream) {
-  if (fp64) hipLaunchKernelGGL((k_grad<double>), dim3(grid), dim3(256), 0, (hipStream_t)stream, a, mixed);
-  else hipLaunchKernelGGL((k_grad<float>), dim3(grid), dim3(256), 0, (hipStream_t)stream, a, mixed);
+void launch_grad(const LaunchArgs& a, int grid, bool fp64, int mixed, int vec, void* stream) {
+  const dim3 g(grid), b(256);
+  hipStream_t st = (hipStream_t)stream;
+  if (vec == 2) {
+    if (fp64) hipLaunchKernelGGL((k_grad<double, 2>), g, b, 0, st, a, mixed);
+    else hipLaunchKernelGGL((k_grad<float, 2>), g, b, 0, st, a, mixed);
+  } else {
+    if (fp64) hipLaunchKernelGGL((k_grad<double, 1>), g, b, 0, st, a, mixed);
+    else hipLaunchKernelGGL((k_grad<float, 1>), g, b, 0, st, a, mixed);
+  }
 }
 
 }  // namespace monc

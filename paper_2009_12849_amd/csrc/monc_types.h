@@ -16,7 +16,6 @@ constexpr int kMaxPass = 16;            // radix passes of one FFT (3^8 needs 8)
 constexpr int kMaxLaunchMembers = 64;   // members per grouped launch
 constexpr int kTriSmax = 16;            // rows per lane in the tridiagonal solver
 constexpr int kTriPmax = 64;            // lanes per column (one wave)
-constexpr int kGradChunk = 16;          // levels per thread in the gradient kernel
 constexpr int kBig = 1 << 30;           // "inactive" lane index
 constexpr int kGenericElems = 8;        // max elements per thread of the runtime-length FFT
 

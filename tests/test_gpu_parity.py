@@ -109,7 +109,7 @@ def test_stage_forward_spectrum(shape):
     bufs = [to_dev(a, torch.float64) for a in (u, v, w)] + [spec]
     plan.debug_stage(monc.STAGE_FORWARD, bufs)
     torch.cuda.synchronize()
-    got = spec.cpu().numpy()[:, :, : g.nx // 2 + 1]
+    got = plan.spectral_view(spec).cpu().numpy()
     assert relerr(got, ref["B"]) <= 1e-13
 
 
@@ -119,12 +119,11 @@ def test_stage_solve_columns(shape):
     ref = oracle.project(u, v, w, g.dx, g.dy, g.dz, g.rho0, intermediates=True)
     plan = monc.Plan.from_grid(g, "f64")
     spec = plan.spectral_buffer()
-    nxh = g.nx // 2 + 1
-    spec[:, :, :nxh] = torch.from_numpy(ref["B"]).to(DEV)
+    plan.spectral_view(spec).copy_(torch.from_numpy(ref["B"]).to(DEV))
     plan.debug_stage(monc.STAGE_SOLVE, [spec])
     torch.cuda.synchronize()
-    got = spec.cpu().numpy()[:, :, :nxh]
-    assert relerr(got, ref["P"] / (g.nx * g.ny)) <= 1e-12
+    got = plan.spectral_view(spec).cpu().numpy()
+    assert relerr(got, ref["P"] / (g.nx * g.ny)) <= p_tolerance(g)
 
 
 @pytest.mark.parametrize("shape", STAGE_SHAPES)
@@ -133,8 +132,7 @@ def test_stage_inverse_and_gradient(shape):
     ref = oracle.project(u, v, w, g.dx, g.dy, g.dz, g.rho0, intermediates=True)
     plan = monc.Plan.from_grid(g, "f64")
     spec = plan.spectral_buffer()
-    nxh = g.nx // 2 + 1
-    spec[:, :, :nxh] = torch.from_numpy(ref["P"] / (g.nx * g.ny)).to(DEV)
+    plan.spectral_view(spec).copy_(torch.from_numpy(ref["P"] / (g.nx * g.ny)).to(DEV))
     p = torch.empty((g.nz, g.ny, g.nx), dtype=torch.float64, device=DEV)
     plan.debug_stage(monc.STAGE_INVERSE, [spec, p])
     torch.cuda.synchronize()
