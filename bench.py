@@ -97,12 +97,23 @@ class Runner:
     """Owns the plans and device fields of one path (FP64 or mixed) of a
     workload and runs whole projections on them."""
 
-    def __init__(self, monc, torch, members, dtype):
+    def __init__(self, monc, torch, members, dtype, tune=True):
         self.torch = torch
         self.monc = monc
         self.mixed = dtype == "mixed"
         cast = np.float32 if self.mixed else np.float64
         self.plans = [monc.Plan.from_grid(m.grid, dtype) for m in members]
+        self.tuned = {}
+        if tune:
+            # the library's autotuner picks the tile parameters once per
+            # distinct grid (untimed); plans of the same grid reuse them
+            for pl in self.plans:
+                key = (pl.nx, pl.ny, pl.nz)
+                if key not in self.tuned:
+                    pl.autotune()
+                    self.tuned[key] = pl.params
+                else:
+                    pl.params = self.tuned[key]
         self.fields = []
         for m in members:
             f = [torch.from_numpy(a.astype(cast, copy=False)).to("cuda:0") for a in (m.u, m.v, m.w)]
@@ -246,6 +257,7 @@ def main():
     ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline leg")
     ap.add_argument("--no-other", action="store_true", help="time only the headline path")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default tile parameters")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
                     help="also run a device copy of this many MB (counter calibration)")
     args = ap.parse_args()
@@ -274,7 +286,7 @@ def main():
     }[args.workload]
 
     copy_gbps = device_copy_gbps(torch)
-    runner = Runner(monc, torch, members, head)
+    runner = Runner(monc, torch, members, head, tune=not args.no_tune)
     runner.step()
     torch.cuda.synchronize()
     nchk = 1 if len(members) == 1 else 3      # members whose outputs the oracle checks
@@ -295,7 +307,8 @@ def main():
         "dtype": "f64" if head == "f64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": desc, "grid_points": runner.points, "members": len(members),
-                   "path": "fp64" if head == "f64" else "mixed"},
+                   "path": "fp64" if head == "f64" else "mixed",
+                   "tile_params": {f"{k[0]}x{k[1]}x{k[2]}": v for k, v in runner.tuned.items()}},
         "roofline": res["roofline"],
         "path": res["path"],
         "device_copy_GBps": copy_gbps,
@@ -303,7 +316,7 @@ def main():
     if not args.no_other:
         del runner
         torch.cuda.empty_cache()
-        orun = Runner(monc, torch, members, other)
+        orun = Runner(monc, torch, members, other, tune=not args.no_tune)
         orun.step()
         torch.cuda.synchronize()
         ofirst = ([[t.cpu().numpy().astype(np.float64) for t in f] for f in orun.fields[:nchk]]
@@ -311,7 +324,8 @@ def main():
         ores = measure(orun, args.steps, args.warmup, args.workload, None)
         key = "mixed" if other == "mixed" else "fp64"
         result[key] = {"value": ores["value"], "ms_per_step": ores["ms_per_step"],
-                       "roofline": ores["roofline"], "path": ores["path"]}
+                       "roofline": ores["roofline"], "path": ores["path"],
+                       "tile_params": {f"{k[0]}x{k[1]}x{k[2]}": v for k, v in orun.tuned.items()}}
         sp = res["value"] / ores["value"] if head == "mixed" else ores["value"] / res["value"]
         result["mixed_speedup_vs_fp64"] = sp
         del orun

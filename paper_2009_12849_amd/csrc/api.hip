@@ -158,7 +158,9 @@ static int configure_tiles(monc_plan* pl, int ex, int ey, int ymt, int triP) {
   h.ymt = ymt;
   h.triP = triP;
   h.tris = s;
-  h.tricw = 256 / triP;
+  // tridiagonal tile: >= 256 threads and >= 128-byte rows of columns, at
+  // most 512 threads
+  h.tricw = std::min(std::max(256 / triP, (int)(128 / cb)), std::max(1, 512 / triP));
   return MONC_OK;
 }
 
@@ -488,6 +490,7 @@ static Shape member_shape(const MemberDesc& d, Phase ph, bool fp64) {
     }
   } else if (ph == PH_TRI) {
     s.variant = d.tris;
+    s.block = d.tricw * d.triP;
     s.lds = (size_t)d.tricw * (d.triP * (d.tris + 1) + 1) * 16;  // matches the kernel's column stride
     s.blocks = ((long long)d.ny * d.nxh + d.tricw - 1) / d.tricw;
   } else {
@@ -538,7 +541,7 @@ static int launch_one(const Group& g, const std::vector<int>& idx, Phase ph, con
     case PH_RESID: launch_xfwd(a, grid, block, lds, false, 1, v, stream); break;
     case PH_YFWD: launch_ffty(a, grid, block, lds, g.fp64, false, v, stream); break;
     case PH_YINV: launch_ffty(a, grid, block, lds, g.fp64, true, v, stream); break;
-    case PH_TRI: launch_tridiag(a, grid, lds, g.fp64, v, stream); break;
+    case PH_TRI: launch_tridiag(a, grid, block, lds, g.fp64, v, stream); break;
     case PH_XINV: launch_xinv(a, grid, block, lds, g.fp64, 0, v, stream); break;
     case PH_XINV_CORR: launch_xinv(a, grid, block, lds, false, 1, v, stream); break;
     case PH_GRAD: launch_grad(a, grid, g.fp64, 0, v, stream); break;
@@ -939,8 +942,12 @@ extern "C" int monc_autotune(monc_plan* pl, void* stream) {
   std::vector<int> pvals;
   for (int P = 1; P <= kTriPmax; P *= 2)
     if (tri_rows(pl->nz, P) != 0 && (P == 1 || (pl->nz + P - 1) / P >= 2)) pvals.push_back(P);
-  std::vector<Axis> axes = {{0, {2, 4, 8}, xmask}, {1, {2, 4, 8}, ymask}, {2, {1, 2, 4, 8, 16, 32}, ymask},
-                            {3, pvals, tmask}};
+  // elements per thread only shape the runtime-length FFT kernels
+  std::vector<Axis> axes;
+  if (!ct_supported(pl->nx)) axes.push_back({0, {2, 4, 8}, xmask});
+  if (!ct_supported(pl->ny)) axes.push_back({1, {2, 4, 8}, ymask});
+  axes.push_back({2, {1, 2, 4, 8, 16, 32}, ymask});
+  axes.push_back({3, pvals, tmask});
   for (const auto& ax : axes) {
     double best_cost = 1e300;
     int best_val = best[ax.idx];

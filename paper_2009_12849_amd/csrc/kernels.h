@@ -24,7 +24,7 @@ void launch_xfwd(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64
 void launch_ffty(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, bool inverse, int ct_n,
                  void* stream);
 // rows: rows per lane, one of kTriRows (the member's tris)
-void launch_tridiag(const LaunchArgs& a, int grid, size_t lds, bool fp64, int rows, void* stream);
+void launch_tridiag(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, int rows, void* stream);
 // mode 0: write p; mode 1 (float only): p = p1 + delta (float) and wbuf (FP64)
 void launch_xinv(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, int mode, int ct_n, void* stream);
 // mixed = 0: pressure from io.p (FP64); mixed = 1: from MemberDesc::wbuf.

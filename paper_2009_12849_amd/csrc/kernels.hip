@@ -521,8 +521,8 @@ __device__ __forceinline__ double2 column_sum(double2 v, int P) {
   return v;
 }
 
-template <typename TS, int S>
-__global__ void __launch_bounds__(256) k_tridiag(LaunchArgs a) {
+template <typename TS, int S, int MAXT>
+__global__ void __launch_bounds__(MAXT) k_tridiag(LaunchArgs a) {
   extern __shared__ unsigned char smem_raw[];
   double2* stage = reinterpret_cast<double2*>(smem_raw);
   const int mi = find_member(a, blockIdx.x);
@@ -538,10 +538,10 @@ __global__ void __launch_bounds__(256) k_tridiag(LaunchArgs a) {
   CS* Sg = reinterpret_cast<CS*>(io.spec);
   auto slot = [](int k) { return (k / S) * SP + (k % S); };
 
-  // 1. coalesced load of CW columns x nz levels into LDS. CW divides the
-  //    workgroup, so a thread's column is fixed and it stages levels
-  //    k = tid/CW + j P, j < S (256/CW = P lanes, S rows each cover nz);
-  //    every load is issued before the first LDS write.
+  // 1. coalesced load of CW columns x nz levels into LDS. blockDim = CW P,
+  //    so a thread's column is fixed and it stages levels k = tid/CW + j P,
+  //    j < S (P lanes of S rows cover nz); every load is issued before the
+  //    first LDS write.
   const int kth = threadIdx.x / CW;
   {
     const int cc = threadIdx.x % CW;
@@ -835,9 +835,11 @@ void init_kernel_attributes() {
   set_lds_limit(k_xinv_gen<double, 0>);
   set_lds_limit(k_xinv_gen<float, 0>);
   set_lds_limit(k_xinv_gen<float, 1>);
-#define MONC_TRI_ATTR(S)              \
-  set_lds_limit(k_tridiag<double, S>); \
-  set_lds_limit(k_tridiag<float, S>);
+#define MONC_TRI_ATTR(S)                   \
+  set_lds_limit(k_tridiag<double, S, 256>); \
+  set_lds_limit(k_tridiag<float, S, 256>);  \
+  set_lds_limit(k_tridiag<double, S, 512>); \
+  set_lds_limit(k_tridiag<float, S, 512>);
   MONC_TRI_ROWS(MONC_TRI_ATTR)
 #undef MONC_TRI_ATTR
 #define MONC_ATTR(N)                          \
@@ -917,13 +919,17 @@ void launch_xinv(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64
   }
 }
 
-void launch_tridiag(const LaunchArgs& a, int grid, size_t lds, bool fp64, int rows, void* stream) {
-  const int block = 256;
+void launch_tridiag(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, int rows, void* stream) {
   switch (rows) {
-#define MONC_CASE(S)                       \
-  case S:                                  \
-    if (fp64) MONC_GO((k_tridiag<double, S>)); \
-    else MONC_GO((k_tridiag<float, S>));   \
+#define MONC_CASE(S)                                  \
+  case S:                                             \
+    if (block <= 256) {                               \
+      if (fp64) MONC_GO((k_tridiag<double, S, 256>)); \
+      else MONC_GO((k_tridiag<float, S, 256>));       \
+    } else {                                          \
+      if (fp64) MONC_GO((k_tridiag<double, S, 512>)); \
+      else MONC_GO((k_tridiag<float, S, 512>));       \
+    }                                                 \
     return;
     MONC_TRI_ROWS(MONC_CASE)
 #undef MONC_CASE

@@ -59,7 +59,7 @@ struct MemberDesc {
   int ymt;                // y-FFT columns per workgroup
   int triP;               // tridiagonal lanes per column (power of 2)
   int tris;               // rows per lane (>= 2)
-  int tricw;              // columns per workgroup (256 / triP)
+  int tricw;              // columns per workgroup (blockDim / triP)
   void* spec;             // spectral workspace (nz, ny, nxp) complex
   double* wbuf;           // mixed path: p1 + delta in FP64, (nz, ny, nx)
 };
