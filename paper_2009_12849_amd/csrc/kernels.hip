@@ -150,6 +150,101 @@ __device__ __forceinline__ T source_at(const MemberDesc& d, const RowCtx& c, con
   }
 }
 
+// ---------------------------------------------------------------------------
+// Vector forms of the stencils: V = 16 bytes / sizeof(T) consecutive points
+// of one row from 16-byte loads (rows start 16-byte aligned: nx is a
+// multiple of V for every compile-time length). The x-neighbours outside
+// the vector come from scalar loads (cache hits).
+// ---------------------------------------------------------------------------
+template <typename T> struct Vec {
+  static constexpr int n = 16 / sizeof(T);
+  typedef T type __attribute__((ext_vector_type(16 / sizeof(T))));
+};
+
+template <typename T>
+__device__ __forceinline__ typename Vec<T>::type ldv(const T* p) {
+  return *reinterpret_cast<const typename Vec<T>::type*>(p);
+}
+
+template <typename T>
+__device__ __forceinline__ void stv(T* p, typename Vec<T>::type x) {
+  *reinterpret_cast<typename Vec<T>::type*>(p) = x;
+}
+
+// divergence D(u) at points i0 .. i0+V-1 of a row, arithmetic in T
+template <typename T>
+__device__ __forceinline__ void div_vec(const MemberDesc& d, const RowCtx& c, const IoPtrs& io, int i0, T* out) {
+  constexpr int V = Vec<T>::n;
+  using vt = typename Vec<T>::type;
+  const T* __restrict__ u = reinterpret_cast<const T*>(io.u);
+  const T* __restrict__ v = reinterpret_cast<const T*>(io.v);
+  const T* __restrict__ w = reinterpret_cast<const T*>(io.w);
+  const bool f64 = sizeof(T) == 8;
+  const T rdx = f64 ? (T)d.rdx : (T)d.rdxf, rdy = f64 ? (T)d.rdy : (T)d.rdyf;
+  const T rho0 = f64 ? (T)c.rho0 : (T)c.rho0f, rdz = f64 ? (T)c.rdz : (T)c.rdzf;
+  const T rhow = f64 ? (T)c.rhow : (T)c.rhowf, rhowm = f64 ? (T)c.rhowm : (T)c.rhowmf;
+  const vt uc = ldv(u + c.off + i0);
+  const T um = u[c.off + (i0 == 0 ? d.nx - 1 : i0 - 1)];
+  const vt vc = ldv(v + c.off + i0), vs = ldv(v + c.soff + i0);
+  vt wc = (vt)(T)0, wb = (vt)(T)0;
+  if (c.top) wc = ldv(w + c.off + i0);
+  if (c.bot) wb = ldv(w + c.off - c.plane + i0);
+#pragma unroll
+  for (int e = 0; e < V; ++e) {
+    const T uw = e ? uc[e - 1] : um;
+    out[e] = rho0 * ((uc[e] - uw) * rdx + (vc[e] - vs[e]) * rdy) + (rhow * wc[e] - rhowm * wb[e]) * rdz;
+  }
+}
+
+// FP64 residual D(u* - G p1) at points i0 .. i0+3 of a row (float data)
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void resid_vec(const MemberDesc& d, const RowCtx& c, const IoPtrs& io, int i0,
+                                          float* out) {
+  const float* __restrict__ u = reinterpret_cast<const float*>(io.u);
+  const float* __restrict__ v = reinterpret_cast<const float*>(io.v);
+  const float* __restrict__ w = reinterpret_cast<const float*>(io.w);
+  const float* __restrict__ p = reinterpret_cast<const float*>(io.p);
+  const int nx = d.nx;
+  const int iw = (i0 == 0) ? nx - 1 : i0 - 1, ie = (i0 + 4 == nx) ? 0 : i0 + 4;
+  const f4v pc = ldv(p + c.off + i0);
+  const float pw = p[c.off + iw], pe = p[c.off + ie];
+  const f4v pn = ldv(p + c.noff + i0), ps = ldv(p + c.soff + i0);
+  const f4v uc = ldv(u + c.off + i0);
+  const float um = u[c.off + iw];
+  const f4v vc = ldv(v + c.off + i0), vs = ldv(v + c.soff + i0);
+  f4v pu = pc, pd = pc, wc = (f4v)0.0f, wb = (f4v)0.0f;
+  if (c.top) {
+    pu = ldv(p + c.off + c.plane + i0);
+    wc = ldv(w + c.off + i0);
+  }
+  if (c.bot) {
+    pd = ldv(p + c.off - c.plane + i0);
+    wb = ldv(w + c.off - c.plane + i0);
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const double p0 = pc[e];
+    const double pE = (e < 3) ? (double)pc[(e + 1) & 3] : (double)pe;
+    const double pW = (e > 0) ? (double)pc[(e + 3) & 3] : (double)pw;
+    const double uW = (e > 0) ? (double)uc[(e + 3) & 3] : (double)um;
+    const double ue = (double)uc[e] - (pE - p0) * d.rdx;
+    const double uw = uW - (p0 - pW) * d.rdx;
+    const double vn = (double)vc[e] - ((double)pn[e] - p0) * d.rdy;
+    const double vv = (double)vs[e] - (p0 - (double)ps[e]) * d.rdy;
+    double ft = 0.0, fb = 0.0;
+    if (c.top) ft = c.rhow * ((double)wc[e] - ((double)pu[e] - p0) * c.rdzc);
+    if (c.bot) fb = c.rhowm * ((double)wb[e] - (p0 - (double)pd[e]) * c.rdzcm);
+    out[e] = (float)(c.rho0 * ((ue - uw) * d.rdx + (vn - vv) * d.rdy) + (ft - fb) * c.rdz);
+  }
+}
+
+template <typename T, int MODE>
+__device__ __forceinline__ void source_vec(const MemberDesc& d, const RowCtx& c, const IoPtrs& io, int i0, T* out) {
+  if constexpr (MODE == 0) div_vec<T>(d, c, io, i0, out);
+  else resid_vec(d, c, io, i0, out);
+}
+
 // Separate two real rows packed as z = a + i b:
 // A[m] = (Z[m] + conj Z[N-m])/2, B[m] = (Z[m] - conj Z[N-m])/(2i).
 template <typename T>
@@ -188,20 +283,33 @@ __global__ void __launch_bounds__(512) k_xfwd_ct(LaunchArgs a) {
   const long long r0 = 2 * pair, r1 = 2 * pair + 1;
   const bool v0 = r0 < d.nrow, v1 = r1 < d.nrow;
   const RowCtx c0 = make_row(d, r0, v0), c1 = make_row(d, r1, v1);
+  // 1. vector phase: the stencil on 16-byte chunks of both rows, packed as
+  //    z = row0 + i row1 into LDS in natural order
+  constexpr int V = Vec<T>::n;
+#pragma unroll
+  for (int t = 0; t < N / (V * NT); ++t) {
+    const int i0 = (q + t * NT) * V;
+    T s0[V], s1[V];
+    if (v0) source_vec<T, MODE>(d, c0, io, i0, s0);
+    else
+      for (int e = 0; e < V; ++e) s0[e] = (T)0;
+    if (v1) source_vec<T, MODE>(d, c1, io, i0, s1);
+    else
+      for (int e = 0; e < V; ++e) s1[e] = (T)0;
+#pragma unroll
+    for (int e = 0; e < V; ++e) lds[xpad<T>(i0 + e)] = cx<T>{s0[e], s1[e]};
+  }
+  __syncthreads();
   cx<T> v[F::VMAX];
 #pragma unroll
   for (int t = 0; t < F::BT0; ++t) {
     const int b = q + t * NT;
     if (F::valid_first(b)) {
 #pragma unroll
-      for (int r = 0; r < F::R0; ++r) {
-        const int i = b + r * F::NB0;
-        const T s0 = v0 ? source_at<T, MODE>(d, c0, io, i) : (T)0;
-        const T s1 = v1 ? source_at<T, MODE>(d, c1, io, i) : (T)0;
-        v[t * F::R0 + r] = cx<T>{s0, s1};
-      }
+      for (int r = 0; r < F::R0; ++r) v[t * F::R0 + r] = lds[xpad<T>(b + r * F::NB0)];
     }
   }
+  __syncthreads();
   auto li = [](int i) { return xpad<T>(i); };
   F::run(v, lds, li, q, reinterpret_cast<const cx<T>*>(d.twx));
 #pragma unroll
@@ -441,7 +549,49 @@ __global__ void __launch_bounds__(512) k_xinv_ct(LaunchArgs a) {
     const int b = q + t * NT;
     if (F::valid_last(b)) {
 #pragma unroll
-      for (int r = 0; r < F::RL; ++r) store_rows<T, MODE>(d, io, r0, r1, v0, v1, F::out_index(q, t, r), v[t * F::RL + r]);
+      for (int r = 0; r < F::RL; ++r) lds[xpad<T>(F::out_index(q, t, r))] = v[t * F::RL + r];
+    }
+  }
+  __syncthreads();
+  // vector phase: 16-byte chunks of both rows
+  constexpr int V = Vec<T>::n;
+  using vt = typename Vec<T>::type;
+  T* __restrict__ p = reinterpret_cast<T*>(io.p);
+#pragma unroll
+  for (int t = 0; t < N / (V * NT); ++t) {
+    const int i0 = (q + t * NT) * V;
+    vt a0, a1;
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      const cx<T> z = lds[xpad<T>(i0 + e)];
+      a0[e] = z.x;
+      a1[e] = z.y;
+    }
+    if constexpr (MODE == 0) {
+      if (v0) stv(p + r0 * N + i0, a0);
+      if (v1) stv(p + r1 * N + i0, a1);
+    } else {
+      // p1 + delta in FP64: to the FP64 buffer, rounded to p
+#pragma unroll
+      for (int row = 0; row < 2; ++row) {
+        const bool ok = row ? v1 : v0;
+        if (!ok) continue;
+        const long long o = (row ? r1 : r0) * N + i0;
+        const vt p1 = ldv(p + o);
+        const vt dl = row ? a1 : a0;
+        double2 sv[V / 2];
+        vt pf;
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          const double sum = (double)p1[e] + (double)dl[e];
+          if (e & 1) sv[e / 2].y = sum;
+          else sv[e / 2].x = sum;
+          pf[e] = (T)sum;
+        }
+#pragma unroll
+        for (int h = 0; h < V / 2; ++h) *reinterpret_cast<double2*>(d.wbuf + o + 2 * h) = sv[h];
+        stv(p + o, pf);
+      }
     }
   }
 }
