@@ -177,18 +177,27 @@ int monc_profile_enable(monc_plan* plan, unsigned mask);
 int monc_profile_read(monc_plan* plan, double* ms, int* launches);
 
 /* Autotune the tile parameters of a plan (FFT elements per thread, y-FFT
- * columns per workgroup, tridiagonal lanes per column) by timing the
- * candidates on scratch buffers on `stream`; the choice is stored in the plan
- * and in the JSON cache named by the MONC_TUNE_CACHE environment variable
- * (if set). Synchronises the stream. Returns MONC_OK or an error. */
+ * columns per workgroup, tridiagonal lanes per column and columns per
+ * workgroup) by timing the candidates on scratch buffers on `stream`; the
+ * choice is stored in the plan and in the JSON cache named by the
+ * MONC_TUNE_CACHE environment variable (if set). Synchronises the stream.
+ * Returns MONC_OK or an error. */
 int monc_autotune(monc_plan* plan, void* stream);
 
-/* Current tile parameters of a plan: out[0] = x-FFT elements per thread,
- * out[1] = y-FFT elements per thread, out[2] = y-FFT columns per workgroup,
- * out[3] = tridiagonal lanes per column. */
-int monc_plan_params(const monc_plan* plan, int* out4);
-/* Set them (values are checked; 0 keeps the current value). */
-int monc_plan_set_params(monc_plan* plan, const int* in4);
+/* Number of tile parameters. */
+#define MONC_NPARAMS 5
+
+/* Current tile parameters of a plan, out[MONC_NPARAMS]:
+ *   out[0] = x-FFT elements per thread (runtime-length FFTs only),
+ *   out[1] = y-FFT elements per thread (runtime-length FFTs only),
+ *   out[2] = y-FFT columns per workgroup,
+ *   out[3] = tridiagonal lanes per column (power of 2, <= 64),
+ *   out[4] = tridiagonal columns per workgroup (power of 2, times out[3]
+ *            at most 1024 threads). */
+int monc_plan_params(const monc_plan* plan, int* out);
+/* Set them from in[MONC_NPARAMS] (values are checked; 0 keeps the current
+ * value). Synchronises the device. */
+int monc_plan_set_params(monc_plan* plan, const int* in);
 
 #ifdef __cplusplus
 }

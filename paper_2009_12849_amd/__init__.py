@@ -24,6 +24,8 @@ __all__ = ["Plan", "project_batched", "lib", "last_error", "MoncError",
 FP64, MIXED = 0, 1
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP = 0, -1, -2, -3, -4
 STAGE_FORWARD, STAGE_SOLVE, STAGE_INVERSE, STAGE_GRADIENT, STAGE_RESIDUAL = 1, 2, 3, 4, 5
+NPARAMS = 5  # tile parameters: x/y FFT elements per thread, y-FFT columns,
+             # tridiagonal lanes per column, tridiagonal columns per workgroup
 KERNELS = ["div_fftx", "ffty_fwd", "tridiag", "ffty_inv", "ifftx", "grad",
            "resid_fftx", "grad_final"]
 
@@ -194,13 +196,16 @@ class Plan:
 
     @property
     def params(self):
-        out = (ctypes.c_int * 4)()
+        out = (ctypes.c_int * NPARAMS)()
         _check(lib().monc_plan_params(self._h, out))
         return list(out)
 
     @params.setter
     def params(self, vals):
-        arr = (ctypes.c_int * 4)(*[int(x) for x in vals])
+        vals = list(vals) + [0] * (NPARAMS - len(vals))
+        if len(vals) != NPARAMS:
+            raise ValueError(f"expected at most {NPARAMS} tile parameters")
+        arr = (ctypes.c_int * NPARAMS)(*[int(x) for x in vals])
         _check(lib().monc_plan_set_params(self._h, arr))
 
 

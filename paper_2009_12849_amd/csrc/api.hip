@@ -87,7 +87,7 @@ struct monc_plan {
   int nx = 0, ny = 0, nz = 0, dtype = 0, device = 0;
   double dx = 0, dy = 0;
   std::vector<double> dz, rho0;
-  int ex = 8, ey = 8, ymt = 0, triP = 0;  // tile parameters
+  int ex = 8, ey = 8, ymt = 0, triP = 0, tricw = 0;  // tile parameters (tricw 0 = automatic)
   MemberDesc h{};                          // host copy with device pointers
   MemberDesc* d_desc = nullptr;            // device copy
   void* d_tables = nullptr;
@@ -116,8 +116,8 @@ static int tri_rows(int nz, int P) {
   return 0;
 }
 
-// Derive FFT plans and tile parameters from (ex, ey, ymt, triP); 0 = default.
-static int configure_tiles(monc_plan* pl, int ex, int ey, int ymt, int triP) {
+// Derive FFT plans and tile parameters from (ex, ey, ymt, triP, tricw); 0 = default.
+static int configure_tiles(monc_plan* pl, int ex, int ey, int ymt, int triP, int tricw) {
   MemberDesc& h = pl->h;
   FftPlan fx{}, fy{};
   if (!radix_plan(pl->nx, fx) || !radix_plan(pl->ny, fy))
@@ -138,29 +138,35 @@ static int configure_tiles(monc_plan* pl, int ex, int ey, int ymt, int triP) {
   ymt = std::max(1, std::min(ymt, mt_cap));
   const int nxh = pl->nx / 2 + 1;
   ymt = std::min(ymt, pow2_floor(nxh) * 2);
-  // tridiagonal lanes per column: default = fewest lanes with <= 8 rows each
+  // tridiagonal lanes per column: default = fewest lanes with <= 6 rows each
   if (triP <= 0) triP = pl->triP;
   if (triP <= 0) {
     triP = 1;
-    while ((pl->nz + triP - 1) / triP > 8 && triP < kTriPmax) triP *= 2;
+    while ((pl->nz + triP - 1) / triP > 6 && triP < kTriPmax) triP *= 2;
   }
   if (triP & (triP - 1) || triP > kTriPmax)
     return fail(MONC_EINVAL, "tridiagonal lanes per column must be a power of 2 <= %d (got %d)", kTriPmax, triP);
   const int s = tri_rows(pl->nz, triP);
   if (s == 0)
     return fail(MONC_EINVAL, "%d lanes leave %d rows per lane (max %d)", triP, (pl->nz + triP - 1) / triP, kTriSmax);
+  // tridiagonal tile: columns per workgroup (0 = automatic: 256 threads, four
+  // waves, so that five workgroups fit a CU at ~100 registers per lane)
+  if (tricw <= 0) tricw = pl->tricw;
+  const int cw = tricw > 0 ? tricw : std::max(1, 256 / triP);
+  if (cw & (cw - 1) || cw * triP > 512)
+    return fail(MONC_EINVAL, "tridiagonal columns per workgroup must be a power of 2 with %d lanes <= 512 threads (got %d)",
+                triP, cw);
   pl->ex = ex;
   pl->ey = ey;
   pl->ymt = ymt;
   pl->triP = triP;
+  pl->tricw = tricw;
   h.fx = fx;
   h.fy = fy;
   h.ymt = ymt;
   h.triP = triP;
   h.tris = s;
-  // tridiagonal tile: >= 256 threads and >= 128-byte rows of columns, at
-  // most 512 threads
-  h.tricw = std::min(std::max(256 / triP, (int)(128 / cb)), std::max(1, 512 / triP));
+  h.tricw = cw;
   return MONC_OK;
 }
 
@@ -170,7 +176,7 @@ static int upload_desc(monc_plan* pl) {
 }
 
 // ---------------------------------------------------------------------------
-// tuning cache (flat JSON object: "arch:nx,ny,nz:dtype" -> [ex, ey, ymt, triP])
+// tuning cache (flat JSON object: "arch:nx,ny,nz:dtype" -> [ex, ey, ymt, triP, tricw])
 // ---------------------------------------------------------------------------
 static std::mutex g_cache_mu;
 
@@ -270,20 +276,21 @@ extern "C" monc_plan* monc_plan_create(int nx, int ny, int nz, double dx, double
   h.rdxf = (float)h.rdx;
   h.rdyf = (float)h.rdy;
   // tile parameters (cached tuning first)
-  int ex = 0, ey = 0, ymt = 0, triP = 0;
+  int ex = 0, ey = 0, ymt = 0, triP = 0, tricw = 0;
   if (const char* path = std::getenv("MONC_TUNE_CACHE")) {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     auto m = read_cache(path);
     auto it = m.find(cache_key(pl.get()));
-    if (it != m.end() && it->second.size() == 4) {
+    if (it != m.end() && it->second.size() == MONC_NPARAMS) {
       ex = it->second[0];
       ey = it->second[1];
       ymt = it->second[2];
       triP = it->second[3];
+      tricw = it->second[4];
     }
   }
-  if (configure_tiles(pl.get(), ex, ey, ymt, triP) != MONC_OK &&
-      configure_tiles(pl.get(), 8, 8, 0, 0) != MONC_OK)
+  if (configure_tiles(pl.get(), ex, ey, ymt, triP, tricw) != MONC_OK &&
+      configure_tiles(pl.get(), 8, 8, 0, 0, 0) != MONC_OK)
     return nullptr;
 
   // host tables
@@ -492,7 +499,7 @@ static Shape member_shape(const MemberDesc& d, Phase ph, bool fp64) {
     s.variant = d.tris;
     s.block = d.tricw * d.triP;
     s.lds = (size_t)d.tricw * (d.triP * (d.tris + 1) + 1) * 16;  // matches the kernel's column stride
-    s.blocks = ((long long)d.ny * d.nxh + d.tricw - 1) / d.tricw;
+    s.blocks = ((long long)d.ny * d.nxp + d.tricw - 1) / d.tricw;  // over the padded plane
   } else {
     const int vec = (d.nx % 2 == 0) ? 2 : 1;
     const long long nvec = (long long)d.nx * d.ny * d.nz / vec;
@@ -870,25 +877,26 @@ extern "C" int monc_profile_read(monc_plan* pl, double* ms, int* launches) {
 // ---------------------------------------------------------------------------
 // tile parameters and autotuning
 // ---------------------------------------------------------------------------
-extern "C" int monc_plan_params(const monc_plan* pl, int* out4) {
-  if (!pl || !out4) return fail(MONC_EINVAL, "null argument");
-  out4[0] = pl->ex;
-  out4[1] = pl->ey;
-  out4[2] = pl->ymt;
-  out4[3] = pl->triP;
+extern "C" int monc_plan_params(const monc_plan* pl, int* out) {
+  if (!pl || !out) return fail(MONC_EINVAL, "null argument");
+  out[0] = pl->ex;
+  out[1] = pl->ey;
+  out[2] = pl->ymt;
+  out[3] = pl->triP;
+  out[4] = pl->h.tricw;
   return MONC_OK;
 }
 
-extern "C" int monc_plan_set_params(monc_plan* pl, const int* in4) {
-  if (!pl || !in4) return fail(MONC_EINVAL, "null argument");
-  for (int i = 0; i < 4; ++i)
-    if (in4[i] < 0) return fail(MONC_EINVAL, "parameter %d is negative", i);
+extern "C" int monc_plan_set_params(monc_plan* pl, const int* in) {
+  if (!pl || !in) return fail(MONC_EINVAL, "null argument");
+  for (int i = 0; i < MONC_NPARAMS; ++i)
+    if (in[i] < 0) return fail(MONC_EINVAL, "parameter %d is negative", i);
   const MemberDesc saved = pl->h;
-  const int sv[4] = {pl->ex, pl->ey, pl->ymt, pl->triP};
-  int rc = configure_tiles(pl, in4[0], in4[1], in4[2], in4[3]);
+  const int sv[MONC_NPARAMS] = {pl->ex, pl->ey, pl->ymt, pl->triP, pl->tricw};
+  int rc = configure_tiles(pl, in[0], in[1], in[2], in[3], in[4]);
   if (rc != MONC_OK) {
     pl->h = saved;
-    pl->ex = sv[0]; pl->ey = sv[1]; pl->ymt = sv[2]; pl->triP = sv[3];
+    pl->ex = sv[0]; pl->ey = sv[1]; pl->ymt = sv[2]; pl->triP = sv[3]; pl->tricw = sv[4];
     return rc;
   }
   HIP_TRY(hipDeviceSynchronize());  // in-flight work may still read the old descriptor
@@ -930,7 +938,7 @@ extern "C" int monc_autotune(monc_plan* pl, void* stream) {
     for (int k = 0; k < MONC_K_COUNT; ++k) cost += ms[k];
     return MONC_OK;
   };
-  int best[4] = {pl->ex, pl->ey, pl->ymt, pl->triP};
+  int best[MONC_NPARAMS] = {pl->ex, pl->ey, pl->ymt, pl->triP, pl->tricw};
   const unsigned xmask = (1u << MONC_K_DIV_FFTX) | (1u << MONC_K_IFFTX) | (1u << MONC_K_RESID_FFTX);
   const unsigned ymask = (1u << MONC_K_FFTY_FWD) | (1u << MONC_K_FFTY_INV);
   const unsigned tmask = 1u << MONC_K_TRIDIAG;
@@ -948,15 +956,17 @@ extern "C" int monc_autotune(monc_plan* pl, void* stream) {
   if (!ct_supported(pl->ny)) axes.push_back({1, {2, 4, 8}, ymask});
   axes.push_back({2, {1, 2, 4, 8, 16, 32}, ymask});
   axes.push_back({3, pvals, tmask});
+  axes.push_back({4, {4, 8, 16, 32}, tmask});
   for (const auto& ax : axes) {
     double best_cost = 1e300;
     int best_val = best[ax.idx];
     for (int val : ax.vals) {
-      int prm[4] = {best[0], best[1], best[2], best[3]};
+      int prm[MONC_NPARAMS];
+      std::copy(best, best + MONC_NPARAMS, prm);
       prm[ax.idx] = val;
       double cost = 0.0;
       if (measure(prm, ax.mask, cost) != MONC_OK) continue;
-      int eff[4];
+      int eff[MONC_NPARAMS];
       monc_plan_params(pl, eff);
       if (eff[ax.idx] != val) continue;  // clamped to another candidate
       if (cost < best_cost) {
@@ -973,7 +983,7 @@ extern "C" int monc_autotune(monc_plan* pl, void* stream) {
   if (const char* path = std::getenv("MONC_TUNE_CACHE")) {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     auto m = read_cache(path);
-    m[cache_key(pl)] = {pl->ex, pl->ey, pl->ymt, pl->triP};
+    m[cache_key(pl)] = {pl->ex, pl->ey, pl->ymt, pl->triP, pl->tricw};
     write_cache(path, m);
   }
   return MONC_OK;

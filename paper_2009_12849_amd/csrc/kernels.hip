@@ -286,8 +286,7 @@ __global__ void __launch_bounds__(512) k_xfwd_ct(LaunchArgs a) {
   // 1. vector phase: the stencil on 16-byte chunks of both rows, packed as
   //    z = row0 + i row1 into LDS in natural order
   constexpr int V = Vec<T>::n;
-#pragma unroll
-  for (int t = 0; t < N / (V * NT); ++t) {
+  auto stencil = [&](int t) {
     const int i0 = (q + t * NT) * V;
     T s0[V], s1[V];
     if (v0) source_vec<T, MODE>(d, c0, io, i0, s0);
@@ -298,6 +297,15 @@ __global__ void __launch_bounds__(512) k_xfwd_ct(LaunchArgs a) {
       for (int e = 0; e < V; ++e) s1[e] = (T)0;
 #pragma unroll
     for (int e = 0; e < V; ++e) lds[xpad<T>(i0 + e)] = cx<T>{s0[e], s1[e]};
+  };
+  if constexpr (MODE == 0) {
+#pragma unroll
+    for (int t = 0; t < N / (V * NT); ++t) stencil(t);
+  } else {
+    // the residual stencil reads ten vectors per row: one chunk at a time
+    // keeps the registers (and so the occupancy) of the divergence variant
+#pragma unroll 1
+    for (int t = 0; t < N / (V * NT); ++t) stencil(t);
   }
   __syncthreads();
   cx<T> v[F::VMAX];
@@ -679,43 +687,43 @@ __global__ void __launch_bounds__(MAXT) k_tridiag(LaunchArgs a) {
   const MemberDesc& d = *a.mem[mi];
   const IoPtrs io = a.io[mi];
   const int lb = xcd_local_block(a, mi);
-  const int P = d.triP, CW = d.tricw, nz = d.nz, nxh = d.nxh;
+  const int P = d.triP, CW = d.tricw, nz = d.nz, nxh = d.nxh, nxp = d.nxp;
   constexpr int SP = S + 1;                  // padded chunk length in LDS
   const int lrow = P * SP + 1;               // odd stride: columns start in different banks
-  const int ncols = d.ny * nxh;
+  // columns run linearly over the padded level plane (index n nxp + m), so a
+  // tile is one aligned contiguous run of each level; padding columns
+  // (m >= nxh) ride along as identity systems and are neither read nor written
+  const int ncolp = d.ny * nxp;
   const int col0 = lb * CW;
   using CS = cx<TS>;
   CS* Sg = reinterpret_cast<CS*>(io.spec);
-  auto slot = [](int k) { return (k / S) * SP + (k % S); };
+  const long long plane = d.plane;
 
-  // 1. coalesced load of CW columns x nz levels into LDS. blockDim = CW P,
-  //    so a thread's column is fixed and it stages levels k = tid/CW + j P,
-  //    j < S (P lanes of S rows cover nz); every load is issued before the
-  //    first LDS write.
-  const int kth = threadIdx.x / CW;
+  // 1. coalesced load of CW columns x nz levels into LDS. blockDim = CW P:
+  //    thread (cc, kq) = (tid mod CW, tid / CW) stages rows kq S .. kq S + S-1
+  //    of column cc, i.e. exactly the rows that lane kq of that column will
+  //    eliminate; a wave's load touches CW consecutive columns of each of its
+  //    levels. Every load is issued before the first LDS write.
+  const int cc = threadIdx.x % CW, kq = threadIdx.x / CW;
+  const int ks = kq * S;
+  double2* sst = stage + cc * lrow + kq * SP;
+  const int scol_g = col0 + cc;
+  const bool sok = scol_g < ncolp && scol_g - (scol_g / nxp) * nxp < nxh;
   {
-    const int cc = threadIdx.x % CW;
-    const int col = col0 + cc;
-    const bool ok = col < ncols;
-    const int n = ok ? col / nxh : 0;
-    const CS* src = Sg + (long long)n * d.nxp + (ok ? col - n * nxh : 0);
+    const CS* src = Sg + (sok ? scol_g : 0) + (long long)ks * plane;
     CS ld[S];
 #pragma unroll
-    for (int j = 0; j < S; ++j) {
-      const int k = kth + j * P;
-      ld[j] = (ok && k < nz) ? src[(long long)k * d.plane] : CS{0, 0};
-    }
+    for (int j = 0; j < S; ++j) ld[j] = (sok && ks + j < nz) ? src[j * plane] : CS{0, 0};
 #pragma unroll
-    for (int j = 0; j < S; ++j) {
-      const int k = kth + j * P;
-      if (k < nz) stage[cc * lrow + slot(k)] = make_double2((double)ld[j].x, (double)ld[j].y);
-    }
+    for (int j = 0; j < S; ++j)
+      if (ks + j < nz) sst[j] = make_double2((double)ld[j].x, (double)ld[j].y);
   }
 
   const int tid = threadIdx.x;
   const int c = tid / P, q = tid - c * P;
   const int col = col0 + c;
-  const bool valid = col < ncols;
+  const int ncol = col / nxp, mcol = col - ncol * nxp;
+  const bool valid = col < ncolp && mcol < nxh;
   const bool singular = valid && (col == 0);
   double2* scol = stage + c * lrow;
   const int k0 = q * S;
@@ -723,10 +731,7 @@ __global__ void __launch_bounds__(MAXT) k_tridiag(LaunchArgs a) {
   // coefficients of the lane's rows (identity outside the system), fetched
   // while the column data is still arriving
   double lam = 0.0;
-  if (valid) {
-    const int n = col / nxh, m = col - n * nxh;
-    lam = d.lamy[n] + d.lamx[m];
-  }
+  if (valid) lam = d.lamy[ncol] + d.lamx[mcol];
   double A[S], B[S], C[S], R0[S];
 #pragma unroll
   for (int r = 0; r < S; ++r) {  // unconditional loads (clamped level), selected below
@@ -878,26 +883,17 @@ __global__ void __launch_bounds__(MAXT) k_tridiag(LaunchArgs a) {
     if (k0 + r < nz) scol[q * SP + r] = X[r];
   __syncthreads();
 
-  // coalesced store, scaled by 1/(nx ny)
-  {
+  // coalesced store (the staging thread's rows), scaled by 1/(nx ny)
+  if (sok) {
     const double sc = d.inv_nxny;
-    const int cc = threadIdx.x % CW;
-    const int cl = col0 + cc;
-    if (cl < ncols) {
-      const int n = cl / nxh;
-      CS* dst = Sg + (long long)n * d.nxp + (cl - n * nxh);
-      double2 x[S];
+    CS* dst = Sg + scol_g + (long long)ks * plane;
+    double2 x[S];
 #pragma unroll
-      for (int j = 0; j < S; ++j) {
-        const int k = kth + j * P;
-        if (k < nz) x[j] = stage[cc * lrow + slot(k)];
-      }
+    for (int j = 0; j < S; ++j)
+      if (ks + j < nz) x[j] = sst[j];
 #pragma unroll
-      for (int j = 0; j < S; ++j) {
-        const int k = kth + j * P;
-        if (k < nz) dst[(long long)k * d.plane] = CS{(TS)(x[j].x * sc), (TS)(x[j].y * sc)};
-      }
-    }
+    for (int j = 0; j < S; ++j)
+      if (ks + j < nz) dst[j * plane] = CS{(TS)(x[j].x * sc), (TS)(x[j].y * sc)};
   }
 }
 

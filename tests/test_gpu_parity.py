@@ -307,7 +307,7 @@ def test_plan_rejects_too_many_elements_per_thread():
     g, u, v, w = _case((96, 48, 16), 17)
     plan = monc.Plan.from_grid(g, "f64")
     with pytest.raises(monc.MoncError, match="elements per thread"):
-        plan.params = [16, 16, 0, 0]
+        plan.params = [16, 16, 0, 0, 0]
 
 
 def test_plan_rejects_prime_factor_5():
@@ -332,11 +332,52 @@ def test_project_rejects_bad_pointers():
 # ---------------------------------------------------------------------------
 # tuning parameters keep results within tolerance
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("params", [[4, 4, 1, 0], [2, 2, 4, 0], [8, 8, 32, 0], [8, 8, 8, 64], [8, 8, 8, 32]])
+TILE_PARAMS = [[4, 4, 1, 0, 0], [2, 2, 4, 0, 0], [8, 8, 32, 0, 0], [8, 8, 8, 64, 0], [8, 8, 8, 32, 0],
+               [8, 8, 8, 16, 32], [8, 8, 8, 32, 4], [8, 8, 8, 64, 8], [8, 8, 8, 32, 16]]
+
+
+@pytest.mark.parametrize("params", TILE_PARAMS)
 def test_tile_parameters_do_not_change_results(params):
     g, u, v, w = _case((96, 48, 130), 16)
     plan = monc.Plan.from_grid(g, "f64")
     plan.params = params
+    assert all(e == p for e, p in zip(plan.params[3:], params[3:]) if p), (plan.params, params)
+    ref = oracle.project(u, v, w, g.dx, g.dy, g.dz, g.rho0)
+    out = run_gpu(g, u, v, w, plan=plan)
+    errs = field_errors(out, ref, u, v, w)
+    assert max(errs[:3]) <= TOL64 and errs[3] <= p_tolerance(g), errs
+
+
+@pytest.mark.parametrize("params", [[8, 8, 8, 16, 32], [8, 8, 8, 32, 8], [8, 8, 8, 64, 4]])
+def test_tile_parameters_mixed(params):
+    g, u, v, w = _case((96, 48, 130), 18)
+    errs_default, _, _ = mixed_case(g, u, v, w)
+    plan = monc.Plan.from_grid(g, "mixed")
+    plan.params = params
+    u32, v32, w32 = (a.astype(np.float32) for a in (u, v, w))
+    ref = oracle.project(u32.astype(np.float64), v32.astype(np.float64), w32.astype(np.float64),
+                         g.dx, g.dy, g.dz, g.rho0)
+    out = run_gpu(g, u32, v32, w32, "mixed", plan=plan)
+    errs = field_errors(out, ref, u32, v32, w32)
+    assert max(errs) <= TOL_MIXED, (errs, errs_default)
+
+
+@pytest.mark.parametrize("params", [[8, 8, 8, 16, 3], [8, 8, 8, 32, 32], [8, 8, 8, 64, 16], [8, 8, 8, 3, 0]])
+def test_plan_rejects_bad_tridiagonal_tiles(params):
+    g, u, v, w = _case((32, 16, 130), 19)
+    plan = monc.Plan.from_grid(g, "f64")
+    before = plan.params
+    with pytest.raises(monc.MoncError, match="tridiagonal"):
+        plan.params = params
+    assert plan.params == before
+
+
+def test_autotune_keeps_results():
+    g, u, v, w = _case((64, 48, 40), 20)
+    plan = monc.Plan.from_grid(g, "f64")
+    plan.autotune()
+    prm = plan.params
+    assert len(prm) == monc.NPARAMS and prm[3] * prm[4] <= 512, prm
     ref = oracle.project(u, v, w, g.dx, g.dy, g.dz, g.rho0)
     out = run_gpu(g, u, v, w, plan=plan)
     errs = field_errors(out, ref, u, v, w)
