@@ -298,15 +298,8 @@ __global__ void __launch_bounds__(512) k_xfwd_ct(LaunchArgs a) {
 #pragma unroll
     for (int e = 0; e < V; ++e) lds[xpad<T>(i0 + e)] = cx<T>{s0[e], s1[e]};
   };
-  if constexpr (MODE == 0) {
 #pragma unroll
-    for (int t = 0; t < N / (V * NT); ++t) stencil(t);
-  } else {
-    // the residual stencil reads ten vectors per row: one chunk at a time
-    // keeps the registers (and so the occupancy) of the divergence variant
-#pragma unroll 1
-    for (int t = 0; t < N / (V * NT); ++t) stencil(t);
-  }
+  for (int t = 0; t < N / (V * NT); ++t) stencil(t);
   __syncthreads();
   cx<T> v[F::VMAX];
 #pragma unroll
@@ -761,15 +754,13 @@ __global__ void __launch_bounds__(MAXT) k_tridiag(LaunchArgs a) {
   }
   // (0,0) column (one per member, lanes of one wave): remove the dz-weighted
   // mean of the right-hand side, then pin the top row (identity, rhs 0)
-  double DZ[S];
   if (singular) {
-#pragma unroll
-    for (int r = 0; r < S; ++r) DZ[r] = (k0 + r < nz) ? ldg(d.dz + (k0 + r)) : 0.0;
     double2 sum = make_double2(0.0, 0.0);
 #pragma unroll
     for (int r = 0; r < S; ++r) {
-      sum.x += DZ[r] * D[r].x;
-      sum.y += DZ[r] * D[r].y;
+      const double dzr = (k0 + r < nz) ? ldg(d.dz + (k0 + r)) : 0.0;
+      sum.x += dzr * D[r].x;
+      sum.y += dzr * D[r].y;
     }
     sum = column_sum(sum, P);
 #pragma unroll
@@ -818,6 +809,11 @@ __global__ void __launch_bounds__(MAXT) k_tridiag(LaunchArgs a) {
   // interface row of F_q:  A0 L_{q-1} + (B0 - C0 f1) F_q - C0 g1 L_q = D0 - C0 e1
   const double aF = A[0], bF = B[0] - C[0] * al[1], cF = -C[0] * ga[1];
   const double2 dF = make_double2(D[0].x - C[0] * de[1].x, D[0].y - C[0] * de[1].y);
+  // park e_r in the lane's own LDS slots (their right-hand sides are
+  // consumed) while the interface system is solved: fewer live registers
+#pragma unroll
+  for (int r = 1; r < S - 1; ++r) scol[q * SP + r] = de[r];
+  asm volatile("" ::: "memory");
 
   // 2. substitute L_{q-1} (from lane q-1) and L_q into the F_q row
   const int lane = __lane_id();
@@ -834,23 +830,34 @@ __global__ void __launch_bounds__(MAXT) k_tridiag(LaunchArgs a) {
     row.y = dF.y - am * dLmy - cF * dL.y;
   }
 
-  // 3. parallel cyclic reduction over the P lanes of the column
-  for (int h = 1; h < P; h *= 2) {
-    const bool hasl = q - h >= 0, hasr = q + h < P;
-    const Row5 lo = shfl_row(row, hasl ? lane - h : lane);
-    const Row5 hi = shfl_row(row, hasr ? lane + h : lane);
-    const double k1 = hasl ? row.a * rcp64(lo.b) : 0.0;
-    const double k2 = hasr ? row.c * rcp64(hi.b) : 0.0;
-    Row5 nr;
-    nr.a = hasl ? -lo.a * k1 : 0.0;
-    nr.c = hasr ? -hi.c * k2 : 0.0;
-    nr.b = row.b - (hasl ? lo.c * k1 : 0.0) - (hasr ? hi.a * k2 : 0.0);
-    nr.x = row.x - (hasl ? lo.x * k1 : 0.0) - (hasr ? hi.x * k2 : 0.0);
-    nr.y = row.y - (hasl ? lo.y * k1 : 0.0) - (hasr ? hi.y * k2 : 0.0);
-    row = nr;
+  // 3. parallel cyclic reduction over the P lanes of the column, on rows
+  //    scaled to a unit diagonal (four values travel per neighbour, one
+  //    reciprocal per step). A lane without a partner at distance h already
+  //    has a zero coupling on that side (the first lane's a and the last
+  //    lane's c are zero, and each step keeps them zero out to distance 2h),
+  //    so it reads its own row and every product with it vanishes.
+  {
+    const double ib = rcp64(row.b);
+    row.a *= ib;
+    row.c *= ib;
+    row.x *= ib;
+    row.y *= ib;
   }
-  const double rb = rcp64(row.b);
-  const double2 F = make_double2(row.x * rb, row.y * rb);
+  for (int h = 1; h < P; h *= 2) {
+    const int sl = (q >= h) ? lane - h : lane, sr = (q + h < P) ? lane + h : lane;
+    const double la = shfl_d(row.a, sl), lc = shfl_d(row.c, sl), lx = shfl_d(row.x, sl), ly = shfl_d(row.y, sl);
+    const double ha = shfl_d(row.a, sr), hc = shfl_d(row.c, sr), hx = shfl_d(row.x, sr), hy = shfl_d(row.y, sr);
+    const double nb = 1.0 - lc * row.a - ha * row.c;
+    const double ib = rcp64(nb);
+    const double na = -la * row.a, nc = -hc * row.c;
+    const double nx = row.x - lx * row.a - hx * row.c;
+    const double ny = row.y - ly * row.a - hy * row.c;
+    row.a = na * ib;
+    row.c = nc * ib;
+    row.x = nx * ib;
+    row.y = ny * ib;
+  }
+  const double2 F = make_double2(row.x, row.y);
 
   // 4. L_q = dL - aL F_q - cL F_{q+1}, then the chunk's interior rows
   const double Fnx = shfl_d(F.x, dn), Fny = shfl_d(F.y, dn);
@@ -861,15 +868,19 @@ __global__ void __launch_bounds__(MAXT) k_tridiag(LaunchArgs a) {
   for (int r = 0; r < S; ++r) {
     if (r == 0) X[r] = F;
     else if (r == S - 1) X[r] = L;
-    else X[r] = make_double2(de[r].x - al[r] * F.x - ga[r] * L.x, de[r].y - al[r] * F.y - ga[r] * L.y);
+    else {
+      const double2 e = scol[q * SP + r];
+      X[r] = make_double2(e.x - al[r] * F.x - ga[r] * L.x, e.y - al[r] * F.y - ga[r] * L.y);
+    }
   }
   // (0,0) column: gauge sum_k dz_k P_k = 0
   if (singular) {
     double2 sum = make_double2(0.0, 0.0);
 #pragma unroll
     for (int r = 0; r < S; ++r) {
-      sum.x += DZ[r] * X[r].x;
-      sum.y += DZ[r] * X[r].y;
+      const double dzr = (k0 + r < nz) ? ldg(d.dz + (k0 + r)) : 0.0;
+      sum.x += dzr * X[r].x;
+      sum.y += dzr * X[r].y;
     }
     sum = column_sum(sum, P);
 #pragma unroll
