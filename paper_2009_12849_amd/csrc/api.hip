@@ -273,6 +273,9 @@ extern "C" monc_plan* monc_plan_create(int nx, int ny, int nz, double dx, double
   h.rdx = 1.0 / dx;
   h.rdy = 1.0 / dy;
   h.inv_nxny = 1.0 / ((double)nx * (double)ny);
+  // stencil kernels walk (8 level x 8 row pair) tiles once a level of one
+  // field outgrows an XCD's L2 share (4 MB); smaller grids stay in row order
+  h.ptk = ((double)nx * ny * elem_bytes(dtype) >= 4.0 * (1 << 20)) ? 8 : 1;
   h.rdxf = (float)h.rdx;
   h.rdyf = (float)h.rdy;
   // tile parameters (cached tuning first)

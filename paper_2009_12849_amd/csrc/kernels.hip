@@ -262,6 +262,30 @@ __device__ __forceinline__ long long spec_row(const MemberDesc& d, long long r) 
   return (long long)k * d.plane + (r - (long long)k * d.ny) * d.nxp;
 }
 
+// Row pairs of the stencil kernels in (level, pair) tiles: consecutive
+// pair slots walk TJ pairs of d.ptk consecutive levels before moving on, so
+// the rows a stencil re-reads (levels k +- 1, rows j +- 1) are read by
+// workgroups that run at about the same time on the same XCD and meet in its
+// L2. A bijection of [0, nz * ny/2) for even ny; ptk = 1 or odd ny (pairs
+// straddle levels) keeps the linear order.
+__device__ __forceinline__ long long tiled_pair(const MemberDesc& d, long long p) {
+  constexpr int TJ = 8;
+  const int TK = d.ptk;
+  if ((d.ny & 1) || TK <= 1) return p;
+  const long long pl = d.ny / 2;                 // pairs per level
+  if (p >= (long long)d.nz * pl) return p;       // beyond the grid: unchanged
+  const long long blk = (long long)TK * pl;
+  const int kb = (int)(p / blk);
+  const long long rem = p - kb * blk;
+  const int tk = min(TK, d.nz - kb * TK);        // levels in this block
+  const long long jt = rem / ((long long)tk * TJ);
+  const int tj = (int)min((long long)TJ, pl - jt * TJ);
+  const int in = (int)(rem - jt * tk * TJ);
+  const int k = kb * TK + in / tj;
+  const long long jp = jt * TJ + in % tj;
+  return (long long)k * pl + jp;
+}
+
 // ---------------------------------------------------------------------------
 // x-direction forward real FFT, compile-time length N (NT = N/8 threads per
 // transform, blockDim = transforms per workgroup * NT)
@@ -279,7 +303,7 @@ __global__ void __launch_bounds__(512) k_xfwd_ct(LaunchArgs a) {
   const int inst = threadIdx.x / NT;
   const int q = threadIdx.x - inst * NT;
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw) + inst * xpad_len<T>(N);
-  const long long pair = (long long)lb * ipw + inst;
+  const long long pair = tiled_pair(d, (long long)lb * ipw + inst);
   const long long r0 = 2 * pair, r1 = 2 * pair + 1;
   const bool v0 = r0 < d.nrow, v1 = r1 < d.nrow;
   const RowCtx c0 = make_row(d, r0, v0), c1 = make_row(d, r1, v1);
@@ -346,7 +370,7 @@ __global__ void __launch_bounds__(1024) k_xfwd_gen(LaunchArgs a) {
   const bool active = inst < ipw;
   const int q = active ? (int)(threadIdx.x - inst * nt) : kBig;
   cx<T>* buf = smem + (active ? inst : 0) * N;
-  const long long pair = (long long)lb * ipw + inst;
+  const long long pair = tiled_pair(d, (long long)lb * ipw + inst);
   const long long r0 = 2 * pair, r1 = 2 * pair + 1;
   const bool v0 = active && r0 < d.nrow, v1 = active && r1 < d.nrow;
   const RowCtx c0 = make_row(d, r0, v0), c1 = make_row(d, r1, v1);

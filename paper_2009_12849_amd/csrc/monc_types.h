@@ -60,6 +60,7 @@ struct MemberDesc {
   int triP;               // tridiagonal lanes per column (power of 2)
   int tris;               // rows per lane (>= 2)
   int tricw;              // columns per workgroup (blockDim / triP)
+  int ptk;                // levels per (level, row pair) tile of the stencil kernels (1 = row order)
   void* spec;             // spectral workspace (nz, ny, nxp) complex
   double* wbuf;           // mixed path: p1 + delta in FP64, (nz, ny, nx)
 };

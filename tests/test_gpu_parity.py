@@ -174,6 +174,19 @@ def test_fp64_c1_full_size():
     print("c1 fp64 errors u,v,w,p:", errs)
 
 
+@pytest.mark.parametrize("shape,dtype", [((1024, 648, 11), "f64"), ((864, 648, 9), "f64"), ((1536, 864, 5), "mixed")])
+def test_large_levels_tiled_stencil_order(shape, dtype):
+    # a level of one field above 4 MB switches the stencil kernels to
+    # (8 level x 8 row pair) tiles; ragged in both (324 / 432 pairs per
+    # level, 5..11 levels), compile-time (1024, 1536) and runtime (864) x FFTs
+    g, u, v, w = _case(shape, 21)
+    if dtype == "f64":
+        check_fp64(g, u, v, w)
+    else:
+        errs, out, ref = mixed_case(g, u, v, w)
+        assert max(errs) <= TOL_MIXED, errs
+
+
 def test_fp64_deterministic_and_bitwise_repeatable():
     g, u, v, w = _case((96, 72, 33), 9)
     plan = monc.Plan.from_grid(g, "f64")
