@@ -1,6 +1,6 @@
 """Benchmark of the MI355X pressure projection (one GPU).
 
-    python bench.py [--steps K] [--warmup W] [--workload c1|c2|c3|c4] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu]
 
 A step is one whole projection (divergence, forward FFTs, FP64 tridiagonal
 solves, inverse FFTs, gradient correction) of the workload's fields, already
@@ -9,12 +9,13 @@ costs exactly the same kernels and bytes as the first pass.
 
 Workloads (seeded synthetic stand-ins for the paper's dry boundary-layer
 case, see synth/):
-  c1  256^2 x 128 stretched anelastic grid; headline = plain FP64 path, the
-      mixed FP32/FP64 path (one FP64 refinement step) timed beside it (default)
-  c2  1024^2 x 256, c1's profiles; headline = mixed path, FP64 beside it
-  c3  48-member ensemble of uneven grids, one batched call (HIP graph);
-      headline = mixed, FP64 beside it
-  c4  2048^2 x 160, k^-5/3 spectra; headline = mixed, FP64 beside it
+  256x256x128    stretched anelastic grid; headline = plain FP64 path, the
+                 mixed FP32/FP64 path (one FP64 refinement step) timed
+                 beside it (default)
+  1024x1024x256  same vertical profiles; headline = mixed, FP64 beside it
+  ensemble48     48-member ensemble of uneven grids, one batched call (HIP
+                 graph); headline = mixed, FP64 beside it
+  2048x2048x160  k^-5/3 spectra; headline = mixed, FP64 beside it
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -35,7 +36,7 @@ sys.path.insert(0, ROOT)
 METRIC = "grid-points/s full projection (mixed vs FP64 GPU) at rel err ≤1e-6, %HBM roofline"
 HBM_PEAK_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_2009_12849_amd", "csrc", "kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+WORKLOADS = ["256x256x128", "1024x1024x256", "ensemble48", "2048x2048x160"]
 KERNELS = ["div_fftx", "ffty_fwd", "tridiag", "ffty_inv", "ifftx", "grad", "resid_fftx", "grad_final"]
 
 
@@ -75,13 +76,19 @@ def kernel_source_hash():
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
+def traffic_file(workload):
+    return os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.txt")
+
+
 def read_traffic(workload, kernel, mixed):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None if it is missing or was taken on another version of the kernels."""
-    if not os.path.exists(TRAFFIC_FILE):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    the workload, or None if it is missing or was taken on another version of
+    the kernels."""
+    path = traffic_file(workload)
+    if not os.path.exists(path):
         return None
     vals = {}
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             line = line.split("#", 1)[0].strip()
             if ":" in line:
@@ -89,7 +96,7 @@ def read_traffic(workload, kernel, mixed):
                 vals[k.strip()] = v.strip()
     if vals.get("kernels_sha256_16") != kernel_source_hash():
         return None
-    key = f"{workload}.{'mixed' if mixed else 'fp64'}.{kernel}.bytes_per_launch"
+    key = f"{'mixed' if mixed else 'fp64'}.{kernel}.bytes_per_launch"
     return float(vals[key]) if key in vals else None
 
 
@@ -254,7 +261,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="256x256x128", choices=WORKLOADS)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline leg")
     ap.add_argument("--no-other", action="store_true", help="time only the headline path")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile parameters")
@@ -272,16 +279,16 @@ def main():
 
     wl = synth.make_workload(args.workload)
     members = wl.members
-    head = "f64" if args.workload == "c1" else "mixed"
+    head = "f64" if args.workload == "256x256x128" else "mixed"
     other = "mixed" if head == "f64" else "f64"
     g = members[0].grid
     desc = {
-        "c1": f"c1: plain FP64 projection {g.nx}x{g.ny}x{g.nz}, dx=dy=25 m, dz=min(10*1.015^k,60) m, "
+        "256x256x128": f"plain FP64 projection {g.nx}x{g.ny}x{g.nz}, dx=dy=25 m, dz=min(10*1.015^k,60) m, "
               f"rho0=1.2exp(-z/8 km), periodic x,y, rigid lids",
-        "c2": f"c2: mixed FP32/FP64 projection with one FP64 refinement step, {g.nx}x{g.ny}x{g.nz}, "
+        "1024x1024x256": f"mixed FP32/FP64 projection with one FP64 refinement step, {g.nx}x{g.ny}x{g.nz}, "
               f"dz=min(10*1.015^k,60) m, rho0=1.2exp(-z/8 km)",
-        "c3": f"c3: batched ensemble of {len(members)} uneven grids (64^2x64..256^2x128), one graph launch, mixed",
-        "c4": f"c4: mixed projection {g.nx}x{g.ny}x{g.nz}, dz=5*20^(k/159) m, rho0=1.2exp(-z/8 km), "
+        "ensemble48": f"batched ensemble of {len(members)} uneven grids (64^2x64..256^2x128), one graph launch, mixed",
+        "2048x2048x160": f"mixed projection {g.nx}x{g.ny}x{g.nz}, dz=5*20^(k/159) m, rho0=1.2exp(-z/8 km), "
               f"k^-5/3 horizontal spectra",
     }[args.workload]
 

@@ -10,15 +10,16 @@ and scaling": z = 64 levels, horizontal grids of n^2 points, 32 x 32 x 64 points
 per process in the weak-scaling runs). Its inputs need the whole model and are
 not available, so the configurations below stand in for it:
 
-  c0  32^3, dx = dy = 50 m, uniform dz = 20 m, rho0 = 1
-  c1  256^2 x 128, dx = dy = 25 m, dz_k = min(10 * 1.015^k, 60) m,
-      rho0 = 1.2 exp(-zc / 8000 m)
-  c2  1024^2 x 256 with c1's vertical profiles (stored FP32)
-  c3  48-member ensemble, grids drawn from {64^2x64, 128^2x96, 192^2x128,
-      256^2x128}, per member dz_k = 10 r^k (r ~ U(1.00, 1.02)) and
-      rho0 = 1.2 exp(-zc / H) (H ~ U(6, 10) km) (stored FP32)
-  c4  2048^2 x 160, dz_k = 5 * 20^(k/159) m, rho0 as c1, horizontal k^-5/3
-      spectrum (stored FP32)
+  "32x32x32"       32^3, dx = dy = 50 m, uniform dz = 20 m, rho0 = 1
+  "256x256x128"    256^2 x 128, dx = dy = 25 m, dz_k = min(10 * 1.015^k, 60) m,
+                   rho0 = 1.2 exp(-zc / 8000 m)
+  "1024x1024x256"  1024^2 x 256 with the same vertical profiles (stored FP32)
+  "ensemble48"     48-member ensemble, grids drawn from {64^2x64, 128^2x96,
+                   192^2x128, 256^2x128}, per member dz_k = 10 r^k
+                   (r ~ U(1.00, 1.02)) and rho0 = 1.2 exp(-zc / H)
+                   (H ~ U(6, 10) km) (stored FP32)
+  "2048x2048x160"  2048^2 x 160, dz_k = 5 * 20^(k/159) m, rho0 as above,
+                   horizontal k^-5/3 spectrum (stored FP32)
 
 Field conventions (C-order arrays (nz, ny, nx), x fastest):
   u[k, j, i] sits at x = (i + 1) dx, y = (j + 1/2) dy  (east face)
@@ -35,7 +36,7 @@ from typing import List, Optional
 import numpy as np
 
 __all__ = ["Grid", "Member", "Workload", "CONFIGS", "make_workload",
-           "make_grid", "c1_fields", "random_grid", "random_fields"]
+           "make_grid", "mode_fields", "random_grid", "random_fields"]
 
 
 @dataclasses.dataclass
@@ -77,11 +78,12 @@ class Workload:
 
 
 CONFIGS = {
-    "c0": "FP64, 32x32x32, dx=dy=50 m, dz=20 m, rho0=1; u,v,w ~ N(0,1) + 2cos(2pi x/Lx)cos(2pi y/Ly)",
-    "c1": "FP64, 256x256x128, dx=dy=25 m, dz=min(10*1.015^k,60) m, rho0=1.2exp(-z/8 km); u,v ~ N(0,4)+8 modes, w ~ N(0,0.25)",
-    "c2": "mixed (FP32 storage), 1024x1024x256, c1's vertical profiles and field recipe",
-    "c3": "mixed, 48-member ensemble of uneven grids, per-member dz stretch and rho0 scale height",
-    "c4": "mixed, 2048x2048x160, dz=5*20^(k/159) m, rho0 as c1, k^-5/3 horizontal spectra",
+    "32x32x32": "FP64, 32x32x32, dx=dy=50 m, dz=20 m, rho0=1; u,v,w ~ N(0,1) + 2cos(2pi x/Lx)cos(2pi y/Ly)",
+    "256x256x128": "FP64, 256x256x128, dx=dy=25 m, dz=min(10*1.015^k,60) m, rho0=1.2exp(-z/8 km); "
+                   "u,v ~ N(0,4)+8 modes, w ~ N(0,0.25)",
+    "1024x1024x256": "mixed (FP32 storage), 1024x1024x256, the 256x256x128 vertical profiles and field recipe",
+    "ensemble48": "mixed, 48-member ensemble of uneven grids, per-member dz stretch and rho0 scale height",
+    "2048x2048x160": "mixed, 2048x2048x160, dz=5*20^(k/159) m, rho0=1.2exp(-z/8 km), k^-5/3 horizontal spectra",
 }
 
 
@@ -102,15 +104,15 @@ def exp_rho0(dz: np.ndarray, scale_height: float = 8000.0) -> np.ndarray:
 
 
 def make_grid(name: str) -> Grid:
-    if name == "c0":
+    if name == "32x32x32":
         return Grid(32, 32, 32, 50.0, 50.0, np.full(32, 20.0), np.ones(32))
-    if name == "c1":
+    if name == "256x256x128":
         dz = capped_geometric_dz(128)
         return Grid(256, 256, 128, 25.0, 25.0, dz, exp_rho0(dz))
-    if name == "c2":
+    if name == "1024x1024x256":
         dz = capped_geometric_dz(256)
         return Grid(1024, 1024, 256, 25.0, 25.0, dz, exp_rho0(dz))
-    if name == "c4":
+    if name == "2048x2048x160":
         dz = 5.0 * 20.0 ** (np.arange(160, dtype=np.float64) / 159.0)
         return Grid(2048, 2048, 160, 25.0, 25.0, dz, exp_rho0(dz))
     raise KeyError(name)
@@ -146,7 +148,7 @@ def _mode_sum(rng, g: Grid, x: np.ndarray, y: np.ndarray, count: int = 8):
     return out
 
 
-def c1_fields(rng, g: Grid):
+def mode_fields(rng, g: Grid):
     """u, v ~ N(0, variance 4) + 8 low-wavenumber modes each; w ~ N(0, variance
     0.25); rigid lid w[nz-1] = 0."""
     xc, xf, yc, yf = _staggered_coords(g)
@@ -160,7 +162,7 @@ def c1_fields(rng, g: Grid):
     return u, v, w
 
 
-def _c0_fields(rng, g: Grid):
+def _small_fields(rng, g: Grid):
     xc, xf, yc, yf = _staggered_coords(g)
     Lx, Ly = g.nx * g.dx, g.ny * g.dy
     shape = (g.nz, g.ny, g.nx)
@@ -195,7 +197,7 @@ def _spectral_field(rng, g: Grid, std: float, chunk: int = 8):
     return out
 
 
-def _c4_fields(rng, g: Grid):
+def _spectral_fields(rng, g: Grid):
     u = _spectral_field(rng, g, 2.0)
     v = _spectral_field(rng, g, 2.0)
     w = _spectral_field(rng, g, 0.5)
@@ -206,7 +208,7 @@ def _c4_fields(rng, g: Grid):
 C3_SHAPES = [(64, 64, 64), (128, 128, 96), (192, 192, 128), (256, 256, 128)]
 
 
-def c3_members(count: int = 48, shapes=None, seed: int = 4000):
+def ensemble_members(count: int = 48, shapes=None, seed: int = 4000):
     """Member grids of the ensemble: sizes drawn with `seed`, member m uses
     seed + 1 + m for its dz ratio, rho0 scale height and fields."""
     shapes = C3_SHAPES if shapes is None else shapes
@@ -226,21 +228,21 @@ def c3_members(count: int = 48, shapes=None, seed: int = 4000):
 def make_workload(name: str, members: Optional[int] = None) -> Workload:
     """Build one named configuration. Fields are drawn in FP64; the mixed
     configurations are meant to be rounded to FP32 by the caller."""
-    if name == "c3":
+    if name == "ensemble48":
         mem = []
-        for g, rng in c3_members(48 if members is None else members):
-            mem.append(Member(g, *c1_fields(rng, g)))
+        for g, rng in ensemble_members(48 if members is None else members):
+            mem.append(Member(g, *mode_fields(rng, g)))
         return Workload(name, "mixed", mem, CONFIGS[name])
     g = make_grid(name)
-    seed = {"c0": 1000, "c1": 2000, "c2": 3000, "c4": 5000}[name]
+    seed = {"32x32x32": 1000, "256x256x128": 2000, "1024x1024x256": 3000, "2048x2048x160": 5000}[name]
     rng = np.random.default_rng(seed)
-    if name == "c0":
-        fields = _c0_fields(rng, g)
-    elif name == "c4":
-        fields = _c4_fields(rng, g)
+    if name == "32x32x32":
+        fields = _small_fields(rng, g)
+    elif name == "2048x2048x160":
+        fields = _spectral_fields(rng, g)
     else:
-        fields = c1_fields(rng, g)
-    dtype = "f64" if name in ("c0", "c1") else "mixed"
+        fields = mode_fields(rng, g)
+    dtype = "f64" if name in ("32x32x32", "256x256x128") else "mixed"
     return Workload(name, dtype, [Member(g, *fields)], CONFIGS[name])
 
 

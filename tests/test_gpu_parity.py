@@ -163,15 +163,15 @@ def test_fp64_ragged_and_extreme_shapes(shape):
     check_fp64(g, u, v, w)
 
 
-def test_fp64_c0():
-    m = synth.make_workload("c0").members[0]
+def test_fp64_32x32x32():
+    m = synth.make_workload("32x32x32").members[0]
     check_fp64(m.grid, m.u, m.v, m.w)
 
 
-def test_fp64_c1_full_size():
-    m = synth.make_workload("c1").members[0]
+def test_fp64_256x256x128_full_size():
+    m = synth.make_workload("256x256x128").members[0]
     errs = check_fp64(m.grid, m.u, m.v, m.w)
-    print("c1 fp64 errors u,v,w,p:", errs)
+    print("256x256x128 fp64 errors u,v,w,p:", errs)
 
 
 @pytest.mark.parametrize("shape,dtype", [((1024, 648, 11), "f64"), ((864, 648, 9), "f64"), ((1536, 864, 5), "mixed")])
@@ -227,11 +227,11 @@ def test_mixed_small(shape):
     assert np.all(out[2][-1] == 0.0)
 
 
-def test_mixed_c1_grid_with_ir_gain():
-    m = synth.make_workload("c1").members[0]
+def test_mixed_256x256x128_with_ir_gain():
+    m = synth.make_workload("256x256x128").members[0]
     g = m.grid
     errs, out, ref = mixed_case(g, m.u, m.v, m.w)
-    print("c1 mixed errors u,v,w,p:", errs)
+    print("256x256x128 mixed errors u,v,w,p:", errs)
     assert max(errs) <= TOL_MIXED, errs
     # first pass alone (forward, solve, inverse stages) is clearly worse
     plan = monc.Plan.from_grid(g, "mixed")
@@ -243,7 +243,7 @@ def test_mixed_c1_grid_with_ir_gain():
     plan.debug_stage(monc.STAGE_INVERSE, [spec, p1])
     torch.cuda.synchronize()
     e1 = relerr(p1.cpu().numpy().astype(np.float64), ref[3])
-    print("c1 mixed p error before refinement:", e1, "after:", errs[3])
+    print("256x256x128 mixed p error before refinement:", e1, "after:", errs[3])
     assert errs[3] < e1
 
 

@@ -142,8 +142,8 @@ def dct_solve(b, dx, dy, dz, rho):
     return np.fft.irfft2(sfft.idct(spec, type=2, axis=0, norm="ortho"), s=(ny, nx), axes=(1, 2))
 
 
-def test_dct_closed_form_at_c0():
-    wl = synth.make_workload("c0")
+def test_dct_closed_form_at_32x32x32():
+    wl = synth.make_workload("32x32x32")
     m = wl.members[0]
     g = m.grid
     out = oracle.project(m.u, m.v, m.w, g.dx, g.dy, g.dz, g.rho0, intermediates=True)
@@ -187,8 +187,8 @@ def manufactured(g, m0, n0, seed, mean_mode=False):
 
 
 @pytest.mark.parametrize("m0,n0", [(1, 0), (3, 2), (0, 5)])
-def test_manufactured_c1_vertical_grid(m0, n0):
-    base = synth.make_grid("c1")
+def test_manufactured_stretched_vertical_grid(m0, n0):
+    base = synth.make_grid("256x256x128")
     g = synth.Grid(32, 24, base.nz, 40.0, 30.0, base.dz, base.rho0)
     p_true, us, vs, u, v, w = manufactured(g, m0, n0, seed=m0 * 10 + n0)
     uo, vo, wo, p = oracle.project(u, v, w, g.dx, g.dy, g.dz, g.rho0)
@@ -198,7 +198,7 @@ def test_manufactured_c1_vertical_grid(m0, n0):
 
 
 def test_manufactured_mean_mode():
-    base = synth.make_grid("c1")
+    base = synth.make_grid("256x256x128")
     g = synth.Grid(16, 16, base.nz, 25.0, 25.0, base.dz, base.rho0)
     p_true, us, vs, u, v, w = manufactured(g, 0, 0, seed=3, mean_mode=True)
     uo, vo, wo, p = oracle.project(u, v, w, g.dx, g.dy, g.dz, g.rho0)
@@ -207,11 +207,11 @@ def test_manufactured_mean_mode():
     assert np.max(np.abs(wo)) <= 1e-12 * np.max(np.abs(w))
 
 
-def test_manufactured_c4_worst_conditioned_column():
-    # c4's vertical grid (5 m -> 100 m over 160 levels) and horizontal
-    # length (2048 x 25 m), coarsely sampled in x and y: the (1, 0) and (0, 1)
-    # columns have the same smallest lambda as at full size.
-    base = synth.make_grid("c4")
+def test_manufactured_2048_grid_worst_conditioned_column():
+    # the 2048^2 x 160 vertical grid (5 m -> 100 m over 160 levels) and
+    # horizontal length (2048 x 25 m), coarsely sampled in x and y: the (1, 0)
+    # and (0, 1) columns have the same smallest lambda as at full size.
+    base = synth.make_grid("2048x2048x160")
     g = synth.Grid(32, 32, base.nz, 2048 * 25.0 / 32, 2048 * 25.0 / 32, base.dz, base.rho0)
     for (m0, n0) in [(1, 0), (1, 1)]:
         p_true, us, vs, u, v, w = manufactured(g, m0, n0, seed=5)
@@ -224,18 +224,15 @@ def test_manufactured_c4_worst_conditioned_column():
 # Invariants
 # ----------------------------------------------------------------------------
 def _inv_case(name):
-    if name == "c0":
-        m = synth.make_workload("c0").members[0]
-        return m.grid, m.u, m.v, m.w
-    if name == "c1":
-        m = synth.make_workload("c1").members[0]
+    if name in ("32x32x32", "256x256x128"):
+        m = synth.make_workload(name).members[0]
         return m.grid, m.u, m.v, m.w
     rng = np.random.default_rng(99)
     g = synth.random_grid(rng, 27, 12, 9, stretch=(1.0, 1.2))
     return (g,) + synth.random_fields(rng, g)
 
 
-@pytest.mark.parametrize("case", ["c0", "c1", "odd"])
+@pytest.mark.parametrize("case", ["32x32x32", "256x256x128", "odd"])
 def test_invariants(case):
     g, u, v, w = _inv_case(case)
     uo, vo, wo, p = oracle.project(u, v, w, g.dx, g.dy, g.dz, g.rho0)
