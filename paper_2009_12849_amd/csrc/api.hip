@@ -107,10 +107,11 @@ static int pow2_floor(int x) {
 }
 
 // Rows per lane of the tridiagonal kernel for nz rows on P lanes: the
-// smallest compiled row count (2..8, 12, 16) that covers them, 0 if none.
+// smallest compiled row count (2..8, 10, 12, 16) that covers them, 0 if none.
 static int tri_rows(int nz, int P) {
   const int s = std::max(2, (nz + P - 1) / P);
   if (s <= 8) return s;
+  if (s <= 10) return 10;
   if (s <= 12) return 12;
   if (s <= kTriSmax) return kTriSmax;
   return 0;
@@ -261,6 +262,7 @@ extern "C" monc_plan* monc_plan_create(int nx, int ny, int nz, double dx, double
   h.nz = nz;
   h.nxh = nx / 2 + 1;
   h.nxp = (h.nxh + 7) / 8 * 8;
+  div_magic((unsigned)h.nxp, h.nxp_mul, h.nxp_shift);
   h.dtype = dtype;
   h.nrow = (long long)nz * ny;
   // spectral level stride: an odd multiple of 256 bytes, so that the

@@ -39,6 +39,15 @@ __device__ __forceinline__ T ldg(const T* p) {
   return *(const __attribute__((address_space(1))) T*)p;
 }
 
+// x / d for 0 <= x < 2^31 with a precomputed multiplier: q = (umulhi(x, mul)
+// + x) >> shift, where shift = ceil(log2 d) and mul = floor(2^32 (2^shift -
+// d) / d) + 1 (division by invariant integers by multiplication, the variant
+// with the extra addition, valid for every 31-bit dividend).
+__device__ __forceinline__ unsigned fast_div(int x, unsigned mul, int shift) {
+  const unsigned long long t = __umulhi((unsigned)x, mul);
+  return (unsigned)((t + (unsigned)x) >> shift);
+}
+
 // Workgroups go to the 8 XCDs round-robin (XCD = blockIdx mod 8), each XCD
 // with its own L2. Remap a member's local block index so that every XCD
 // works through one contiguous range of tiles: neighbouring rows and levels,
@@ -705,6 +714,7 @@ __global__ void __launch_bounds__(MAXT) k_tridiag(LaunchArgs a) {
   const IoPtrs io = a.io[mi];
   const int lb = xcd_local_block(a, mi);
   const int P = d.triP, CW = d.tricw, nz = d.nz, nxh = d.nxh, nxp = d.nxp;
+  const int lp = __builtin_ctz(P), lcw = __builtin_ctz(CW);  // both powers of two
   constexpr int SP = S + 1;                  // padded chunk length in LDS
   const int lrow = P * SP + 1;               // odd stride: columns start in different banks
   // columns run linearly over the padded level plane (index n nxp + m), so a
@@ -720,53 +730,57 @@ __global__ void __launch_bounds__(MAXT) k_tridiag(LaunchArgs a) {
   //    thread (cc, kq) = (tid mod CW, tid / CW) stages rows kq S .. kq S + S-1
   //    of column cc, i.e. exactly the rows that lane kq of that column will
   //    eliminate; a wave's load touches CW consecutive columns of each of its
-  //    levels. Every load is issued before the first LDS write.
-  const int cc = threadIdx.x % CW, kq = threadIdx.x / CW;
+  //    levels. The loads are unconditional (clamped address, zero selected
+  //    afterwards) so that all of them are in flight before the first wait.
+  const int tid = threadIdx.x;
+  const int cc = tid & (CW - 1), kq = tid >> lcw;
   const int ks = kq * S;
   double2* sst = stage + cc * lrow + kq * SP;
   const int scol_g = col0 + cc;
-  const bool sok = scol_g < ncolp && scol_g - (scol_g / nxp) * nxp < nxh;
-  {
-    const CS* src = Sg + (sok ? scol_g : 0) + (long long)ks * plane;
-    CS ld[S];
+  const int sn = (int)fast_div(scol_g, d.nxp_mul, d.nxp_shift);
+  const bool sok = scol_g < ncolp && scol_g - sn * nxp < nxh;
+  const CS* src = Sg + (sok ? scol_g : 0) + (long long)ks * plane;
+  const long long last = (long long)(nz - 1 - ks) * plane;  // offset of level nz-1 from src
+  CS ld[S];
 #pragma unroll
-    for (int j = 0; j < S; ++j) ld[j] = (sok && ks + j < nz) ? src[j * plane] : CS{0, 0};
-#pragma unroll
-    for (int j = 0; j < S; ++j)
-      if (ks + j < nz) sst[j] = make_double2((double)ld[j].x, (double)ld[j].y);
+  for (int j = 0; j < S; ++j) {
+    const long long o = (long long)j * plane;
+    ld[j] = src[o < last ? o : last];
   }
 
-  const int tid = threadIdx.x;
-  const int c = tid / P, q = tid - c * P;
+  const int c = tid >> lp, q = tid & (P - 1);
   const int col = col0 + c;
-  const int ncol = col / nxp, mcol = col - ncol * nxp;
+  const int ncol = (int)fast_div(col, d.nxp_mul, d.nxp_shift), mcol = col - ncol * nxp;
   const bool valid = col < ncolp && mcol < nxh;
   const bool singular = valid && (col == 0);
   double2* scol = stage + c * lrow;
   const int k0 = q * S;
 
-  // coefficients of the lane's rows (identity outside the system), fetched
-  // while the column data is still arriving
-  double lam = 0.0;
-  if (valid) lam = d.lamy[ncol] + d.lamx[mcol];
+  // coefficients of the lane's rows (identity outside the system): all loads
+  // unconditional and issued while the column data is still arriving
+  const double lamv = ldg(d.lamy + min(ncol, d.ny - 1)) + ldg(d.lamx + min(mcol, nxh - 1));
   double A[S], B[S], C[S], R0[S];
 #pragma unroll
-  for (int r = 0; r < S; ++r) {  // unconditional loads (clamped level), selected below
+  for (int r = 0; r < S; ++r) {  // clamped level, selected below
     const int k = min(k0 + r, nz - 1);
     A[r] = ldg(d.ta + k);
     C[r] = ldg(d.tc + k);
     R0[r] = ldg(d.rho0 + k);
   }
+  // column data into LDS (zero outside the grid)
+#pragma unroll
+  for (int j = 0; j < S; ++j) {
+    const bool in = sok && ks + j < nz;  // every slot exists; rows >= nz are never read
+    sst[j] = make_double2(in ? (double)ld[j].x : 0.0, in ? (double)ld[j].y : 0.0);
+  }
+  const double lam = valid ? lamv : 0.0;
 #pragma unroll
   for (int r = 0; r < S; ++r) {
     const int k = k0 + r;
-    if (valid && k < nz && !(singular && k == nz - 1)) {
-      B[r] = -(A[r] + C[r]) - R0[r] * lam;
-    } else {
-      A[r] = 0.0;
-      B[r] = 1.0;
-      C[r] = 0.0;
-    }
+    const bool in = valid && k < nz && !(singular && k == nz - 1);
+    B[r] = in ? -(A[r] + C[r]) - R0[r] * lam : 1.0;
+    A[r] = in ? A[r] : 0.0;
+    C[r] = in ? C[r] : 0.0;
   }
   __syncthreads();
 
@@ -924,8 +938,7 @@ __global__ void __launch_bounds__(MAXT) k_tridiag(LaunchArgs a) {
     CS* dst = Sg + scol_g + (long long)ks * plane;
     double2 x[S];
 #pragma unroll
-    for (int j = 0; j < S; ++j)
-      if (ks + j < nz) x[j] = sst[j];
+    for (int j = 0; j < S; ++j) x[j] = sst[j];
 #pragma unroll
     for (int j = 0; j < S; ++j)
       if (ks + j < nz) dst[j * plane] = CS{(TS)(x[j].x * sc), (TS)(x[j].y * sc)};
@@ -991,7 +1004,7 @@ static void set_lds_limit(K kern) {
                             160 * 1024);
 }
 
-#define MONC_TRI_ROWS(X) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(12) X(16)
+#define MONC_TRI_ROWS(X) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(10) X(12) X(16)
 #define MONC_CT_SIZES(X) X(16) X(32) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(1536) X(2048) X(4096)
 
 bool ct_supported(int n) {

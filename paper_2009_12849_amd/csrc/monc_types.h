@@ -61,6 +61,8 @@ struct MemberDesc {
   int tris;               // rows per lane (>= 2)
   int tricw;              // columns per workgroup (blockDim / triP)
   int ptk;                // levels per (level, row pair) tile of the stencil kernels (1 = row order)
+  unsigned nxp_mul;       // x / nxp = (umulhi(x, nxp_mul) + x) >> nxp_shift for 31-bit x
+  int nxp_shift;
   void* spec;             // spectral workspace (nz, ny, nxp) complex
   double* wbuf;           // mixed path: p1 + delta in FP64, (nz, ny, nx)
 };

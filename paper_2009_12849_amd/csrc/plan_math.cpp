@@ -163,4 +163,11 @@ std::vector<double> twiddles(int n) {
   return tw;
 }
 
+void div_magic(unsigned d, unsigned& mul, int& shift) {
+  int l = 0;
+  while ((1ull << l) < d) ++l;
+  shift = l;
+  mul = (unsigned)((((1ull << l) - d) << 32) / d + 1);
+}
+
 }  // namespace monc

@@ -33,6 +33,11 @@ struct VerticalTables {
 // off-diagonals a_k = rhow_{k-1}/(dz_k dzc_{k-1}), c_k = rhow_k/(dz_k dzc_k).
 VerticalTables vertical_tables(int nz, const double* dz, const double* rho0);
 
+// Multiplier and shift for x / d by multiplication, 0 <= x < 2^31, d >= 1:
+// shift = ceil(log2 d), mul = floor(2^32 (2^shift - d) / d) + 1, and then
+// x / d = (umulhi(x, mul) + x) >> shift.
+void div_magic(unsigned d, unsigned& mul, int& shift);
+
 // lam(m) = (4/h^2) sin^2(pi m / n), m = 0 .. count-1.
 std::vector<double> modified_wavenumbers(int n, int count, double h);
 
