@@ -21,6 +21,16 @@ template <> struct V2<float> { using t = float2; };
 template <> struct V2<double> { using t = double2; };
 template <typename T> using cx = typename V2<T>::t;
 
+// Twiddle table read through a global-address-space pointer: the table
+// pointer sits in a member descriptor, where it is a generic pointer that
+// would otherwise become a flat load (which also holds up LDS waits).
+template <typename C> __device__ __forceinline__ C load_tw(const C* p) {
+  using E = decltype(C{}.x);
+  typedef E pair __attribute__((ext_vector_type(2)));
+  const pair v = *(const __attribute__((address_space(1))) pair*)p;
+  return C{v.x, v.y};
+}
+
 template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
 template <typename C> __device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
 template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
@@ -183,7 +193,7 @@ struct CtFft {
           const int kk = b % NS;
 #pragma unroll
           for (int r = 1; r < Rr; ++r) {
-            const cx<T> w = tw[kk * r * TSTEP];
+            const cx<T> w = load_tw(tw + kk * r * TSTEP);
             v[t * Rr + r] = INV ? cmulconj(v[t * Rr + r], w) : cmul(v[t * Rr + r], w);
           }
         }
@@ -270,7 +280,7 @@ __device__ __forceinline__ void stockham_pass(cx<T>* buf, int stride, int N, int
       if (Ns > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          const cx<T> w = tw[kk * r * tstep];
+          const cx<T> w = load_tw(tw + kk * r * tstep);
           v[t * R + r] = INV ? cmulconj(v[t * R + r], w) : cmul(v[t * R + r], w);
         }
       }

@@ -196,12 +196,18 @@ def test_fp64_deterministic_and_bitwise_repeatable():
         assert np.array_equal(x, y)
 
 
-def test_lid_input_ignored():
+@pytest.mark.parametrize("dtype", ["f64", "mixed"])
+@pytest.mark.parametrize("lid", [123.0, np.nan, np.inf])
+def test_lid_input_ignored(dtype, lid):
+    # w[nz-1] is documented as ignored on input: no value there, not even a
+    # NaN or an infinity, may reach any output
     g, u, v, w = _case((32, 24, 10), 10)
+    cast = np.float64 if dtype == "f64" else np.float32
+    u, v, w = (x.astype(cast).astype(np.float64) for x in (u, v, w))
     w2 = w.copy()
-    w2[-1] = 123.0
-    a = run_gpu(g, u, v, w)
-    b = run_gpu(g, u, v, w2)
+    w2[-1] = lid
+    a = run_gpu(g, u, v, w, dtype)
+    b = run_gpu(g, u, v, w2, dtype)
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
 
