@@ -18,7 +18,8 @@ Grid and staggering (arrays are C-order (nz, ny, nx), periodic in x and y):
   w[k,j,i]   top face   z = zw_{k+1};  w[nz-1] is the rigid lid (0), and the
              bottom lid w = 0 at z = 0 is implicit.
   dz[k]      cell thickness; zw_0 = 0, zw_{k+1} = zw_k + dz_k,
-             zc_k = zw_k + dz_k/2, dzc_k = zc_{k+1} - zc_k.
+             zc_k = zw_k + dz_k/2, dzc_k = zc_{k+1} - zc_k = (dz_k + dz_{k+1})/2
+             (evaluated in that last form).
   rho0[k]    anelastic reference density at cell centres; on the face
              zw_{k+1} it is interpolated linearly in z (rhow_k).
 
@@ -54,10 +55,13 @@ def vertical_grid(dz, rho0):
     rho0 = np.asarray(rho0, dtype=_F64)
     zw = np.concatenate([[0.0], np.cumsum(dz)])
     zc = zw[:-1] + 0.5 * dz
-    dzc = zc[1:] - zc[:-1]
-    # linear interpolation of rho0 from zc_k, zc_{k+1} to the face zw_{k+1}
-    t = (zw[1:-1] - zc[:-1]) / dzc
-    rhow = rho0[:-1] + t * (rho0[1:] - rho0[:-1])
+    # centre spacing straight from the thicknesses (dzc_k = (dz_k + dz_{k+1})/2),
+    # not as a difference of accumulated heights, which cancels at the top
+    # of a tall column
+    dzc = 0.5 * (dz[:-1] + dz[1:])
+    # linear interpolation of rho0 from zc_k, zc_{k+1} to the face zw_{k+1},
+    # which lies dz_k/2 above zc_k and dz_{k+1}/2 below zc_{k+1}
+    rhow = (dz[1:] * rho0[:-1] + dz[:-1] * rho0[1:]) / (dz[:-1] + dz[1:])
     return {"zw": zw, "zc": zc, "dzc": dzc, "rhow": rhow, "dz": dz, "rho0": rho0}
 
 
@@ -76,8 +80,7 @@ def gradient(p, dx, dy, dz):
     """Staggered gradient G(p) on the u, v, w points; the lid row of the
     vertical component is 0."""
     dz = np.asarray(dz, dtype=_F64)
-    zc = np.concatenate([[0.0], np.cumsum(dz)])[:-1] + 0.5 * dz
-    dzc = zc[1:] - zc[:-1]
+    dzc = 0.5 * (dz[:-1] + dz[1:])                 # zc_{k+1} - zc_k, as in vertical_grid
     gx = (np.roll(p, -1, axis=2) - p) / dx
     gy = (np.roll(p, -1, axis=1) - p) / dy
     gz = np.zeros_like(p)
