@@ -55,10 +55,13 @@ def kernel_bytes_per_point(kernel, nx, mixed):
         "ffty_fwd": 2 * f * wb,                 # read + write spectrum
         "tridiag": 2 * f * wb,
         "ffty_inv": 2 * f * wb,
-        "ifftx": (f + 1) * wb,                  # read spectrum; write p
+        # read spectrum, write p; on the mixed path the mean of its two
+        # launches: p1 (f + 1 words), then the correction (read spectrum and
+        # p1, write p and the remainder: f + 3 words)
+        "ifftx": (f + 2) * wb if mixed else (f + 1) * wb,
         "grad": 7 * wb,                         # read p, u, v, w; write u, v, w
         "resid_fftx": (4 + f) * wb,             # read u, v, w, p1; write spectrum
-        "grad_final": 8 + 6 * wb,               # read FP64 p; read/write u, v, w
+        "grad_final": 8 * wb,                   # read p and remainder; read/write u, v, w
     }
     return table[kernel]
 

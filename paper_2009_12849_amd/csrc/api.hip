@@ -92,7 +92,7 @@ struct monc_plan {
   MemberDesc* d_desc = nullptr;            // device copy
   void* d_tables = nullptr;
   void* d_spec = nullptr;
-  double* d_wbuf = nullptr;
+  float* d_prem = nullptr;
   size_t spec_elems = 0;
   Profiler prof;
 };
@@ -350,14 +350,14 @@ extern "C" monc_plan* monc_plan_create(int nx, int ny, int nz, double dx, double
   auto release = [&]() {
     if (pl->d_tables) (void)hipFree(pl->d_tables);
     if (pl->d_spec) (void)hipFree(pl->d_spec);
-    if (pl->d_wbuf) (void)hipFree(pl->d_wbuf);
+    if (pl->d_prem) (void)hipFree(pl->d_prem);
     if (pl->d_desc) (void)hipFree(pl->d_desc);
   };
   if (hipMalloc(&pl->d_tables, tables_bytes) != hipSuccess ||
       hipMalloc(&pl->d_spec, pl->spec_elems * cplx_bytes(dtype)) != hipSuccess ||
       hipMalloc((void**)&pl->d_desc, sizeof(MemberDesc)) != hipSuccess ||
       (dtype == MONC_MIXED &&
-       hipMalloc((void**)&pl->d_wbuf, (size_t)nx * ny * nz * sizeof(double)) != hipSuccess)) {
+       hipMalloc((void**)&pl->d_prem, (size_t)nx * ny * nz * sizeof(float)) != hipSuccess)) {
     (void)hipGetLastError();
     release();
     fail(MONC_ENOMEM, "device allocation failed for a %dx%dx%d plan", nx, ny, nz);
@@ -386,7 +386,7 @@ extern "C" monc_plan* monc_plan_create(int nx, int ny, int nz, double dx, double
   h.twx = base + o_tx;
   h.twy = base + o_ty;
   h.spec = pl->d_spec;
-  h.wbuf = pl->d_wbuf;
+  h.prem = pl->d_prem;
   if (upload_desc(pl.get()) != MONC_OK) {
     release();
     return nullptr;
@@ -402,7 +402,7 @@ extern "C" void monc_plan_destroy(monc_plan* pl) {
   drop_batch_cache_for(pl->id);
   if (pl->d_tables) (void)hipFree(pl->d_tables);
   if (pl->d_spec) (void)hipFree(pl->d_spec);
-  if (pl->d_wbuf) (void)hipFree(pl->d_wbuf);
+  if (pl->d_prem) (void)hipFree(pl->d_prem);
   if (pl->d_desc) (void)hipFree(pl->d_desc);
   delete pl;
 }
@@ -506,7 +506,10 @@ static Shape member_shape(const MemberDesc& d, Phase ph, bool fp64) {
     s.lds = (size_t)d.tricw * (d.triP * (d.tris + 1) + 1) * 16;  // matches the kernel's column stride
     s.blocks = ((long long)d.ny * d.nxp + d.tricw - 1) / d.tricw;  // over the padded plane
   } else {
-    const int vec = (d.nx % 2 == 0) ? 2 : 1;
+    // points per thread: 16-byte field accesses on the mixed path (4 floats),
+    // 2 doubles on the FP64 path; fewer when nx does not divide
+    const int want = (ph == PH_GRAD_MIXED) ? 4 : 2;
+    const int vec = (d.nx % want == 0) ? want : (d.nx % 2 == 0) ? 2 : 1;
     const long long nvec = (long long)d.nx * d.ny * d.nz / vec;
     s.variant = vec;
     s.blocks = (nvec + 255) / 256;
@@ -556,8 +559,8 @@ static int launch_one(const Group& g, const std::vector<int>& idx, Phase ph, con
     case PH_TRI: launch_tridiag(a, grid, block, lds, g.fp64, v, stream); break;
     case PH_XINV: launch_xinv(a, grid, block, lds, g.fp64, 0, v, stream); break;
     case PH_XINV_CORR: launch_xinv(a, grid, block, lds, false, 1, v, stream); break;
-    case PH_GRAD: launch_grad(a, grid, g.fp64, 0, v, stream); break;
-    case PH_GRAD_MIXED: launch_grad(a, grid, false, 1, v, stream); break;
+    case PH_GRAD: launch_grad(a, grid, g.fp64, v, stream); break;
+    case PH_GRAD_MIXED: launch_grad(a, grid, false, v, stream); break;
   }
   hipError_t le = hipGetLastError();
   if (timed) {

@@ -25,10 +25,12 @@ void launch_ffty(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64
                  void* stream);
 // rows: rows per lane, one of kTriRows (the member's tris)
 void launch_tridiag(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, int rows, void* stream);
-// mode 0: write p; mode 1 (float only): p = p1 + delta (float) and wbuf (FP64)
+// mode 0: write p; mode 1 (float only): p = fl32(p1 + delta) and its FP32
+// remainder in MemberDesc::prem
 void launch_xinv(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, int mode, int ct_n, void* stream);
-// mixed = 0: pressure from io.p (FP64); mixed = 1: from MemberDesc::wbuf.
-// vec: points per thread (2 needs an even nx, else 1)
-void launch_grad(const LaunchArgs& a, int grid, bool fp64, int mixed, int vec, void* stream);
+// fp64: pressure from io.p (FP64); else (mixed path) p1 + delta from the
+// float pair io.p + MemberDesc::prem. vec: points per thread (2 needs an even
+// nx, 4 a multiple of 4; else 1)
+void launch_grad(const LaunchArgs& a, int grid, bool fp64, int vec, void* stream);
 
 }  // namespace monc

@@ -558,7 +558,7 @@ __global__ void __launch_bounds__(1024) k_ffty_gen(LaunchArgs a) {
 // x-direction inverse (complex-to-real) FFT of row pairs.
 // MODE 0: write p (storage type T).
 // MODE 1 (mixed, T = float): the transform is the correction delta; read p1
-//         from p, write p1 + delta to p (float) and to wbuf (FP64).
+//         from p, write p1 + delta to p (float) and its remainder to prem.
 // Z[m] = X_a[m] + i X_b[m], Z[N-m] = conj X_a[m] + i conj X_b[m]; the
 // imaginary parts of the self-conjugate bins (m = 0, m = N/2) are dropped.
 // ---------------------------------------------------------------------------
@@ -598,13 +598,15 @@ __device__ __forceinline__ void store_rows(const MemberDesc& d, const IoPtrs& io
   } else {
     if (v0) {
       const double s = (double)p[r0 * N + i] + (double)z.x;
-      d.wbuf[r0 * N + i] = s;
-      p[r0 * N + i] = (T)s;
+      const float f = (float)s;
+      d.prem[r0 * N + i] = (float)(s - (double)f);
+      p[r0 * N + i] = f;
     }
     if (v1) {
       const double s = (double)p[r1 * N + i] + (double)z.y;
-      d.wbuf[r1 * N + i] = s;
-      p[r1 * N + i] = (T)s;
+      const float f = (float)s;
+      d.prem[r1 * N + i] = (float)(s - (double)f);
+      p[r1 * N + i] = f;
     }
   }
 }
@@ -684,7 +686,9 @@ __global__ void __launch_bounds__(512) k_xinv_ct(LaunchArgs a) {
       if (v0) stv(p + r0 * N + i0, a0);
       if (v1) stv(p + r1 * N + i0, a1);
     } else {
-      // p1 + delta in FP64: to the FP64 buffer, rounded to p
+      // p1 + delta formed in FP64 and kept as a float pair: p = fl32(sum)
+      // and the remainder sum - p (exact in FP64, rounded to FP32: the pair
+      // carries the sum to about 2^-48 relative)
 #pragma unroll
       for (int row = 0; row < 2; ++row) {
         const bool ok = row ? v1 : v0;
@@ -692,17 +696,14 @@ __global__ void __launch_bounds__(512) k_xinv_ct(LaunchArgs a) {
         const long long o = (row ? r1 : r0) * N + i0;
         const vt p1 = ldv(p + o);
         const vt dl = row ? a1 : a0;
-        double2 sv[V / 2];
-        vt pf;
+        vt pf, pr;
 #pragma unroll
         for (int e = 0; e < V; ++e) {
           const double sum = (double)p1[e] + (double)dl[e];
-          if (e & 1) sv[e / 2].y = sum;
-          else sv[e / 2].x = sum;
           pf[e] = (T)sum;
+          pr[e] = (T)(sum - (double)pf[e]);
         }
-#pragma unroll
-        for (int h = 0; h < V / 2; ++h) stg(d.wbuf + o + 2 * h, sv[h].x, sv[h].y);
+        *(__attribute__((address_space(1))) vt*)(d.prem + o) = pr;
         stv(p + o, pf);
       }
     }
@@ -1026,12 +1027,13 @@ __global__ void __launch_bounds__(MAXT) k_tridiag(LaunchArgs a) {
 
 // ---------------------------------------------------------------------------
 // Pressure-gradient correction u -= G p, evaluated in FP64 from an FP64
-// pressure (p itself on the FP64 path, p1 + delta on the mixed path); the
+// pressure (p itself on the FP64 path, p1 + delta rebuilt from the float
+// pair p + remainder on the mixed path); the
 // fields are T. A thread owns VEC consecutive points of one row of one
 // level (vector loads and stores need nx % VEC == 0); w[nz-1] = 0.
 // ---------------------------------------------------------------------------
 template <typename T, int VEC>
-__global__ void __launch_bounds__(256) k_grad(LaunchArgs a, int mixed) {
+__global__ void __launch_bounds__(256) k_grad(LaunchArgs a) {
   typedef T tv __attribute__((ext_vector_type(VEC)));
   typedef double dv __attribute__((ext_vector_type(VEC)));
   const int mi = find_member(a, blockIdx.x);
@@ -1048,21 +1050,38 @@ __global__ void __launch_bounds__(256) k_grad(LaunchArgs a, int mixed) {
   const long long base = (long long)k * nh;
   const long long he = base + (long long)j * nx + ((i + VEC == nx) ? 0 : i + VEC);  // east of the last point
   const long long hn = base + (long long)((j == ny - 1) ? 0 : j + 1) * nx + i;
-  const double* __restrict__ p = mixed ? d.wbuf : reinterpret_cast<const double*>(io.p);
   T* __restrict__ u = reinterpret_cast<T*>(io.u);
   T* __restrict__ v = reinterpret_cast<T*>(io.v);
   T* __restrict__ w = reinterpret_cast<T*>(io.w);
   const bool top = k == nz - 1;
-  // p through global-address-space loads (the FP64 sum of the mixed path
-  // comes from the descriptor, a generic pointer); on the FP64 path p one
-  // level up is read unconditionally (clamped on the lid row) so that all
-  // loads issue together
-  const dv pc = ldg(reinterpret_cast<const dv*>(p + g));
-  const dv pn = ldg(reinterpret_cast<const dv*>(p + hn));
-  const double pel = ldg(p + he);
+  // p in FP64: the FP64 path's p, or on the mixed path the float pair
+  // (p, remainder) = p1 + delta written by the correction pass. Loads go
+  // through global-address-space pointers (the remainder buffer comes from
+  // the descriptor, a generic pointer).
+  auto ldp = [&](long long o) -> dv {
+    if constexpr (sizeof(T) == 8) {
+      return ldg(reinterpret_cast<const dv*>(reinterpret_cast<const double*>(io.p) + o));
+    } else {
+      const tv hi = ldg(reinterpret_cast<const tv*>(reinterpret_cast<const float*>(io.p) + o));
+      const tv lo = ldg(reinterpret_cast<const tv*>(d.prem + o));
+      dv r;
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) r[e] = (double)hi[e] + (double)lo[e];
+      return r;
+    }
+  };
+  auto ldp1 = [&](long long o) -> double {
+    if constexpr (sizeof(T) == 8) return ldg(reinterpret_cast<const double*>(io.p) + o);
+    else return (double)ldg(reinterpret_cast<const float*>(io.p) + o) + (double)ldg(d.prem + o);
+  };
+  const dv pc = ldp(g);
+  const dv pn = ldp(hn);
+  const double pel = ldp1(he);
+  // on the FP64 path p one level up is read unconditionally (clamped on the
+  // lid row) so that all loads issue together
   dv pu;
-  if constexpr (sizeof(T) == 8) pu = ldg(reinterpret_cast<const dv*>(p + (top ? g : g + nh)));
-  else pu = top ? pc : ldg(reinterpret_cast<const dv*>(p + g + nh));
+  if constexpr (sizeof(T) == 8) pu = ldp(top ? g : g + nh);
+  else pu = top ? pc : ldp(g + nh);
   tv uu = *reinterpret_cast<const tv*>(u + g);
   tv vv = *reinterpret_cast<const tv*>(v + g);
   tv ww = *reinterpret_cast<const tv*>(w + g);
@@ -1215,15 +1234,18 @@ void launch_tridiag(const LaunchArgs& a, int grid, int block, size_t lds, bool f
   }
 }
 
-void launch_grad(const LaunchArgs& a, int grid, bool fp64, int mixed, int vec, void* stream) {
+void launch_grad(const LaunchArgs& a, int grid, bool fp64, int vec, void* stream) {
   const dim3 g(grid), b(256);
   hipStream_t st = (hipStream_t)stream;
-  if (vec == 2) {
-    if (fp64) hipLaunchKernelGGL((k_grad<double, 2>), g, b, 0, st, a, mixed);
-    else hipLaunchKernelGGL((k_grad<float, 2>), g, b, 0, st, a, mixed);
+  if (vec == 4) {
+    if (fp64) hipLaunchKernelGGL((k_grad<double, 4>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((k_grad<float, 4>), g, b, 0, st, a);
+  } else if (vec == 2) {
+    if (fp64) hipLaunchKernelGGL((k_grad<double, 2>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((k_grad<float, 2>), g, b, 0, st, a);
   } else {
-    if (fp64) hipLaunchKernelGGL((k_grad<double, 1>), g, b, 0, st, a, mixed);
-    else hipLaunchKernelGGL((k_grad<float, 1>), g, b, 0, st, a, mixed);
+    if (fp64) hipLaunchKernelGGL((k_grad<double, 1>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((k_grad<float, 1>), g, b, 0, st, a);
   }
 }
 

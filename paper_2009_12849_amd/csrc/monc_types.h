@@ -64,7 +64,7 @@ struct MemberDesc {
   unsigned nxp_mul;       // x / nxp = (umulhi(x, nxp_mul) + x) >> nxp_shift for 31-bit x
   int nxp_shift;
   void* spec;             // spectral workspace (nz, ny, nxp) complex
-  double* wbuf;           // mixed path: p1 + delta in FP64, (nz, ny, nx)
+  float* prem;            // mixed path: remainder (p1 + delta) - fl32(p1 + delta) in FP32, (nz, ny, nx)
 };
 
 struct IoPtrs {

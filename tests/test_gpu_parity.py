@@ -224,8 +224,10 @@ def mixed_case(g, u, v, w):
     return errs, out, ref
 
 
-@pytest.mark.parametrize("shape", [(32, 32, 32), (48, 27, 13), (192, 96, 40), (1, 1, 4), (64, 64, 130)])
+@pytest.mark.parametrize("shape", [(32, 32, 32), (48, 27, 13), (192, 96, 40), (1, 1, 4), (64, 64, 130),
+                                   (18, 12, 7), (27, 9, 6)])
 def test_mixed_small(shape):
+    # nx = 18 and 27 take the 2- and 1-point gradient variants (4 otherwise)
     g, u, v, w = _case(shape, 11)
     errs, out, ref = mixed_case(g, u, v, w)
     print(f"mixed {shape}: {errs}")
