@@ -48,15 +48,6 @@ __device__ __forceinline__ unsigned fast_div(int x, unsigned mul, int shift) {
   return (unsigned)((t + (unsigned)x) >> shift);
 }
 
-// Store two doubles (16-byte aligned) through a global-address-space pointer.
-__device__ __forceinline__ void stg(double* p, double a, double b) {
-  typedef double d2 __attribute__((ext_vector_type(2)));
-  d2 v;
-  v.x = a;
-  v.y = b;
-  *(__attribute__((address_space(1))) d2*)p = v;
-}
-
 // Workgroups go to the 8 XCDs round-robin (XCD = blockIdx mod 8), each XCD
 // with its own L2. Remap a member's local block index so that every XCD
 // works through one contiguous range of tiles: neighbouring rows and levels,
@@ -113,6 +104,40 @@ __device__ __forceinline__ RowCtx make_row(const MemberDesc& d, long long row, b
   c.rhowf = ldg(d.rhowf + k);
   c.rhowmf = c.bot ? ldg(d.rhowf + km) : 0.0f;
   return c;
+}
+
+// Values known to be equal on every lane of a wave, moved to scalar
+// registers (readfirstlane): a row context is per transform, and a transform
+// of N >= 512 points spans whole waves, so vector registers would hold the
+// same value 64 times.
+__device__ __forceinline__ int wuni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ long long wuni(long long x) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)x);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)((unsigned long long)x >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ double wuni(double x) { return __longlong_as_double(wuni(__double_as_longlong(x))); }
+__device__ __forceinline__ float wuni(float x) { return __int_as_float(wuni(__float_as_int(x))); }
+__device__ __forceinline__ RowCtx wuni(const RowCtx& c) {
+  RowCtx r;
+  r.off = wuni(c.off);
+  r.soff = wuni(c.soff);
+  r.noff = wuni(c.noff);
+  r.plane = wuni(c.plane);
+  r.k = wuni(c.k);
+  r.top = wuni((int)c.top) != 0;
+  r.bot = wuni((int)c.bot) != 0;
+  r.rho0 = wuni(c.rho0);
+  r.rhow = wuni(c.rhow);
+  r.rhowm = wuni(c.rhowm);
+  r.rdz = wuni(c.rdz);
+  r.rdzc = wuni(c.rdzc);
+  r.rdzcm = wuni(c.rdzcm);
+  r.rho0f = wuni(c.rho0f);
+  r.rhowf = wuni(c.rhowf);
+  r.rhowmf = wuni(c.rhowmf);
+  r.rdzf = wuni(c.rdzf);
+  return r;
 }
 
 template <typename T>
@@ -373,13 +398,21 @@ __global__ void __launch_bounds__(512) k_xfwd_ct(LaunchArgs a) {
   const IoPtrs io = a.io[mi];
   const int lb = xcd_local_block(a, mi);
   const int ipw = blockDim.x / NT;
-  const int inst = threadIdx.x / NT;
+  // scalar row contexts for the residual only (one transform spans whole
+  // waves): its occupancy rises from 3 to 5 waves per SIMD and it gains; the
+  // divergence variants measure slower at the higher occupancy
+  constexpr bool UNI = NT >= 64 && MODE == 1;
+  const int inst = UNI ? wuni((int)(threadIdx.x / NT)) : (int)(threadIdx.x / NT);
   const int q = threadIdx.x - inst * NT;
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw) + inst * xpad_len<T>(N);
   const long long pair = tiled_pair(d, (long long)lb * ipw + inst);
   const long long r0 = 2 * pair, r1 = 2 * pair + 1;
   const bool v0 = r0 < d.nrow, v1 = r1 < d.nrow;
-  const RowCtx c0 = make_row(d, r0, v0), c1 = make_row(d, r1, v1);
+  RowCtx c0 = make_row(d, r0, v0), c1 = make_row(d, r1, v1);
+  if constexpr (UNI) {
+    c0 = wuni(c0);
+    c1 = wuni(c1);
+  }
   // 1. vector phase: the stencil on 16-byte chunks of both rows, packed as
   //    z = row0 + i row1 into LDS in natural order
   constexpr int V = Vec<T>::n;
