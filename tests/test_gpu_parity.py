@@ -163,6 +163,25 @@ def test_fp64_ragged_and_extreme_shapes(shape):
     check_fp64(g, u, v, w)
 
 
+@pytest.mark.parametrize("shape", [(8192, 2, 3), (2, 8192, 2), (6561, 3, 2), (4, 6561, 3)])
+@pytest.mark.parametrize("dtype", ["f64", "mixed"])
+def test_size_limits(shape, dtype):
+    # nx or ny = 8192 (the limit) and 3^8 take the runtime-length FFT kernels at
+    # their largest LDS footprint. The layers are 1 km thick: with the ~10 m
+    # layers of the other cases a 400 km long, 20 m deep domain has a longest
+    # mode with kappa ~ 1e8, and the flat velocity tolerance would then test
+    # the conditioning rather than the kernels.
+    rng = np.random.default_rng(24)
+    nx, ny, nz = shape
+    g = synth.Grid(nx, ny, nz, 50.0, 40.0, 1000.0 * rng.uniform(0.8, 1.2, nz), rng.uniform(0.5, 1.5, nz))
+    u, v, w = synth.random_fields(rng, g)
+    if dtype == "f64":
+        check_fp64(g, u, v, w)
+    else:
+        errs, out, ref = mixed_case(g, u, v, w)
+        assert max(errs) <= TOL_MIXED, errs
+
+
 def test_fp64_32x32x32():
     m = synth.make_workload("32x32x32").members[0]
     check_fp64(m.grid, m.u, m.v, m.w)
@@ -403,3 +422,48 @@ def test_autotune_keeps_results():
     out = run_gpu(g, u, v, w, plan=plan)
     errs = field_errors(out, ref, u, v, w)
     assert max(errs[:3]) <= TOL64 and errs[3] <= p_tolerance(g), errs
+
+
+def test_autotune_cache_round_trip(tmp_path, monkeypatch):
+    # the tuned parameters land in the JSON file named by MONC_TUNE_CACHE and
+    # a later plan of the same grid and dtype starts from them
+    import json
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("MONC_TUNE_CACHE", str(cache))
+    g, u, v, w = _case((48, 32, 24), 22)
+    plan = monc.Plan.from_grid(g, "mixed")
+    plan.autotune()
+    tuned = plan.params
+    data = json.loads(cache.read_text())
+    key = f"gfx950:{g.nx},{g.ny},{g.nz}:mixed"
+    assert key in data and len(data[key]) == monc.NPARAMS, data
+    assert data[key][2:] == tuned[2:], (data[key], tuned)
+    # a different value in the cache is picked up by a new plan
+    other = list(data[key])
+    other[3] = 8 if tuned[3] != 8 else 16
+    other[4] = 0
+    data[key] = other
+    cache.write_text(json.dumps(data))
+    plan2 = monc.Plan.from_grid(g, "mixed")
+    assert plan2.params[3] == other[3], (plan2.params, other)
+    errs, out, ref = mixed_case(g, u, v, w)
+    assert max(errs) <= TOL_MIXED, errs
+
+
+def test_profiler_counts_every_kernel_launch():
+    g, u, v, w = _case((64, 32, 16), 23)
+    for dtype, kernels in (("f64", {"div_fftx": 1, "ffty_fwd": 1, "tridiag": 1, "ffty_inv": 1, "ifftx": 1, "grad": 1}),
+                           ("mixed", {"div_fftx": 1, "ffty_fwd": 2, "tridiag": 2, "ffty_inv": 2, "ifftx": 2,
+                                      "resid_fftx": 1, "grad_final": 1})):
+        plan = monc.Plan.from_grid(g, dtype)
+        tdt = plan.torch_dtype
+        f = [to_dev(x, tdt) for x in (u, v, w)] + [torch.empty((g.nz, g.ny, g.nx), dtype=tdt, device=DEV)]
+        plan.profile_enable((1 << len(monc.KERNELS)) - 1)
+        for _ in range(3):
+            plan.project(*f)
+        torch.cuda.synchronize()
+        rec = plan.profile_read()
+        plan.profile_enable(0)
+        assert {k: n for k, (ms, n) in rec.items()} == {k: 3 * n for k, n in kernels.items()}, rec
+        assert all(ms > 0 for ms, _ in rec.values()), rec
+        assert plan.profile_read() == {}
