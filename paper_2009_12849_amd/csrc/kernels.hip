@@ -809,6 +809,36 @@ __device__ __forceinline__ double rcp64(double x) {
   return r;
 }
 
+// Value of lane q - H (FROM_BELOW) or q + H of the same 16-lane row, moved
+// with DPP (row_shr / row_shl) on the vector ALU instead of the LDS
+// crossbar; a lane whose source lies outside its row keeps its own value.
+// With P = 16 lanes per column, a row is a column, which is exactly the
+// clamping the cyclic reduction wants.
+template <int H, bool FROM_BELOW>
+__device__ __forceinline__ double dpp_shift(double v) {
+  constexpr int ctrl = FROM_BELOW ? 0x110 + H : 0x100 + H;
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int l2 = __builtin_amdgcn_update_dpp(lo, lo, ctrl, 0xF, 0xF, false);
+  const int h2 = __builtin_amdgcn_update_dpp(hi, hi, ctrl, 0xF, 0xF, false);
+  return __hiloint2double(h2, l2);
+}
+
+// One cyclic-reduction step at distance H on unit-diagonal rows (a, c, x, y).
+template <int H>
+__device__ __forceinline__ void pcr_step16(double& a, double& c, double& x, double& y) {
+  const double la = dpp_shift<H, true>(a), lc = dpp_shift<H, true>(c);
+  const double lx = dpp_shift<H, true>(x), ly = dpp_shift<H, true>(y);
+  const double ha = dpp_shift<H, false>(a), hc = dpp_shift<H, false>(c);
+  const double hx = dpp_shift<H, false>(x), hy = dpp_shift<H, false>(y);
+  const double ib = rcp64(1.0 - lc * a - ha * c);
+  const double na = -la * a, nc = -hc * c;
+  const double nx = x - lx * a - hx * c, ny = y - ly * a - hy * c;
+  a = na * ib;
+  c = nc * ib;
+  x = nx * ib;
+  y = ny * ib;
+}
+
 // sum over the P lanes of a column (aligned power-of-two lane group)
 __device__ __forceinline__ double2 column_sum(double2 v, int P) {
   for (int o = P / 2; o > 0; o /= 2) {
@@ -969,8 +999,11 @@ __global__ void __launch_bounds__(MAXT) k_tridiag(LaunchArgs a) {
   // 2. substitute L_{q-1} (from lane q-1) and L_q into the F_q row
   const int lane = __lane_id();
   const int up = (q > 0) ? lane - 1 : lane, dn = (q < P - 1) ? lane + 1 : lane;
-  const double aLm = shfl_d(aL, up), cLm = shfl_d(cL, up);
-  const double dLmx = shfl_d(dL.x, up), dLmy = shfl_d(dL.y, up);
+  const bool row16 = P == 16;  // a column is one DPP row: shifts on the vector ALU
+  const double aLm = row16 ? dpp_shift<1, true>(aL) : shfl_d(aL, up);
+  const double cLm = row16 ? dpp_shift<1, true>(cL) : shfl_d(cL, up);
+  const double dLmx = row16 ? dpp_shift<1, true>(dL.x) : shfl_d(dL.x, up);
+  const double dLmy = row16 ? dpp_shift<1, true>(dL.y) : shfl_d(dL.y, up);
   Row5 row;
   {
     const double am = (q > 0) ? aF : 0.0;  // coupling to L_{q-1}
@@ -994,6 +1027,12 @@ __global__ void __launch_bounds__(MAXT) k_tridiag(LaunchArgs a) {
     row.x *= ib;
     row.y *= ib;
   }
+  if (row16) {
+    pcr_step16<1>(row.a, row.c, row.x, row.y);
+    pcr_step16<2>(row.a, row.c, row.x, row.y);
+    pcr_step16<4>(row.a, row.c, row.x, row.y);
+    pcr_step16<8>(row.a, row.c, row.x, row.y);
+  } else
   for (int h = 1; h < P; h *= 2) {
     const int sl = (q >= h) ? lane - h : lane, sr = (q + h < P) ? lane + h : lane;
     const double la = shfl_d(row.a, sl), lc = shfl_d(row.c, sl), lx = shfl_d(row.x, sl), ly = shfl_d(row.y, sl);
@@ -1011,7 +1050,8 @@ __global__ void __launch_bounds__(MAXT) k_tridiag(LaunchArgs a) {
   const double2 F = make_double2(row.x, row.y);
 
   // 4. L_q = dL - aL F_q - cL F_{q+1}, then the chunk's interior rows
-  const double Fnx = shfl_d(F.x, dn), Fny = shfl_d(F.y, dn);
+  const double Fnx = row16 ? dpp_shift<1, false>(F.x) : shfl_d(F.x, dn);
+  const double Fny = row16 ? dpp_shift<1, false>(F.y) : shfl_d(F.y, dn);
   const double2 Fn = (q < P - 1) ? make_double2(Fnx, Fny) : make_double2(0.0, 0.0);
   const double2 L = make_double2(dL.x - aL * F.x - cL * Fn.x, dL.y - aL * F.y - cL * Fn.y);
   double2 X[S];
