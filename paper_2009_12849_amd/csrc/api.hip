@@ -467,7 +467,9 @@ struct Shape {
   long long blocks = 0;
 };
 
-static size_t xpad_len_host(int n, size_t cb) { return (size_t)n + (size_t)(n >> (cb == 16 ? 3 : 4)) + 1; }
+static size_t xpad_len_host(int n, size_t cb) {
+  return (size_t)n + (size_t)(n >> (cb == 16 ? kXpadShift64 : kXpadShift32)) + 1;
+}
 
 static Shape member_shape(const MemberDesc& d, Phase ph, bool fp64) {
   const size_t cb = fp64 ? 16 : 8;

@@ -156,9 +156,11 @@ constexpr int ct_threads_y(int n) { return n >= 2048 ? n / 16 : ct_threads(n); }
 // LDS index of element i of an x-direction transform: one pad slot per 128
 // bytes, so the stride-R writes of the first passes spread over all banks.
 template <typename T> __device__ __forceinline__ int xpad(int i) {
-  return i + (i >> (sizeof(T) == 8 ? 3 : 4));
+  return i + (i >> (sizeof(T) == 8 ? kXpadShift64 : kXpadShift32));
 }
-template <typename T> constexpr int xpad_len(int n) { return n + (n >> (sizeof(T) == 8 ? 3 : 4)) + 1; }
+template <typename T> constexpr int xpad_len(int n) {
+  return n + (n >> (sizeof(T) == 8 ? kXpadShift64 : kXpadShift32)) + 1;
+}
 
 // Compile-time Stockham transform. Thread q (0 <= q < NT) owns butterflies
 // b = q + t NT of every pass. Pass p (radix R, Ns = product of the earlier

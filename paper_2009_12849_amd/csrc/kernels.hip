@@ -536,12 +536,21 @@ __global__ void __launch_bounds__(1024) k_ffty_ct(LaunchArgs a) {
   cx<T>* S = reinterpret_cast<cx<T>*>(io.spec) + (long long)k * d.plane + (valid ? m : 0);
   const int nxp = d.nxp;
   cx<T> v[F::VMAX];
+  // FP32: unconditional loads (an invalid column reads column 0), zeroed
+  // after; FP64 keeps the guarded loads, which measure faster there
 #pragma unroll
   for (int t = 0; t < F::BT0; ++t) {
     const int b = q + t * NT;
     if (F::valid_first(b)) {
 #pragma unroll
-      for (int r = 0; r < F::R0; ++r) v[t * F::R0 + r] = valid ? S[(b + r * F::NB0) * nxp] : cx<T>{0, 0};
+      for (int r = 0; r < F::R0; ++r) {
+        if constexpr (sizeof(T) == 4) {
+          const cx<T> x = S[(b + r * F::NB0) * nxp];
+          v[t * F::R0 + r] = valid ? x : cx<T>{0, 0};
+        } else {
+          v[t * F::R0 + r] = valid ? S[(b + r * F::NB0) * nxp] : cx<T>{0, 0};
+        }
+      }
     }
   }
   auto li = [mt, c](int i) { return i * mt + c; };

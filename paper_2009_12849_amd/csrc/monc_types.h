@@ -18,6 +18,10 @@ constexpr int kTriSmax = 16;            // rows per lane in the tridiagonal solv
 constexpr int kTriPmax = 64;            // lanes per column (one wave)
 constexpr int kBig = 1 << 30;           // "inactive" lane index
 constexpr int kGenericElems = 8;        // max elements per thread of the runtime-length FFT
+// x-FFT LDS layout (shared by the kernels and the host's LDS sizes): one pad
+// slot after every 2^shift complex elements, i.e. every 128 bytes
+constexpr int kXpadShift32 = 4;  // FP32 complex (8 B)
+constexpr int kXpadShift64 = 3;  // FP64 complex (16 B)
 
 struct FftPlan {
   int n;                  // transform length (2^a 3^b)
