@@ -361,27 +361,30 @@ __device__ __forceinline__ long long spec_row(const MemberDesc& d, long long r) 
 }
 
 // Row pairs of the stencil kernels in (level, pair) tiles: consecutive
-// pair slots walk TJ pairs of d.ptk consecutive levels before moving on, so
+// pair slots walk 8 pairs of d.ptk consecutive levels before moving on, so
 // the rows a stencil re-reads (levels k +- 1, rows j +- 1) are read by
 // workgroups that run at about the same time on the same XCD and meet in its
-// L2. A bijection of [0, nz * ny/2) for even ny; ptk = 1 or odd ny (pairs
-// straddle levels) keeps the linear order.
-__device__ __forceinline__ long long tiled_pair(const MemberDesc& d, long long p) {
-  constexpr int TJ = 8;
-  const int TK = d.ptk;
-  if ((d.ny & 1) || TK <= 1) return p;
-  const long long pl = d.ny / 2;                 // pairs per level
-  if (p >= (long long)d.nz * pl) return p;       // beyond the grid: unchanged
-  const long long blk = (long long)TK * pl;
+// L2. ptk = 1 or odd ny (pairs straddle levels) keeps the linear order.
+// Bijection of [0, nz * per) that walks tiles of TJ consecutive items of TK
+// consecutive levels (per items per level), ragged tiles at the edges;
+// identity for TK <= 1 and beyond the grid.
+__device__ __forceinline__ long long tiled_index(long long p, long long per, int nz, int TK, int TJ) {
+  if (TK <= 1 || p >= (long long)nz * per) return p;
+  const long long blk = (long long)TK * per;
   const int kb = (int)(p / blk);
   const long long rem = p - kb * blk;
-  const int tk = min(TK, d.nz - kb * TK);        // levels in this block
+  const int tk = min(TK, nz - kb * TK);          // levels in this block
   const long long jt = rem / ((long long)tk * TJ);
-  const int tj = (int)min((long long)TJ, pl - jt * TJ);
+  const int tj = (int)min((long long)TJ, per - jt * TJ);
   const int in = (int)(rem - jt * tk * TJ);
   const int k = kb * TK + in / tj;
   const long long jp = jt * TJ + in % tj;
-  return (long long)k * pl + jp;
+  return (long long)k * per + jp;
+}
+
+__device__ __forceinline__ long long tiled_pair(const MemberDesc& d, long long p) {
+  if (d.ny & 1) return p;
+  return tiled_index(p, d.ny / 2, d.nz, d.ptk, 8);
 }
 
 // ---------------------------------------------------------------------------
@@ -1124,7 +1127,16 @@ __global__ void __launch_bounds__(256) k_grad(LaunchArgs a) {
   const int lb = xcd_local_block(a, mi);
   const int nx = d.nx, ny = d.ny, nz = d.nz;
   const long long nh = (long long)nx * ny;
-  const long long g = ((long long)lb * blockDim.x + threadIdx.x) * VEC;  // first point
+  // blocks walk (level, row) tiles like the stencil kernels when a row is a
+  // whole number of blocks: p one level up is then read by a block of the
+  // same tile, close in time, and hits the XCD's L2
+  long long blk = lb;
+  const int bpr = d.nx / (int)(blockDim.x * VEC);  // blocks per row
+  if (d.ptk > 1 && bpr >= 1 && bpr * (int)blockDim.x * VEC == d.nx) {
+    const long long row = tiled_index(lb / bpr, d.ny, d.nz, d.ptk, 8);
+    blk = row * bpr + lb % bpr;
+  }
+  const long long g = (blk * blockDim.x + threadIdx.x) * VEC;  // first point
   if (g >= nh * nz) return;
   const int k = (int)(g / nh);
   const long long h = g - (long long)k * nh;
