@@ -100,16 +100,67 @@ template <bool INV, typename C> __device__ __forceinline__ void dft3(C* v) {
   v[2] = csub(t, jsd);
 }
 
+// a * W16^E (forward: exp(-2 pi i E/16); inverse: its conjugate), E = 0..15
+template <int E, bool INV, typename C> __device__ __forceinline__ C w16(C a) {
+  using T = decltype(a.x);
+  constexpr double c1 = 0.92387953251128675613, s1 = 0.38268343236508977173;  // cos, sin(pi/8)
+  constexpr double h = 0.70710678118654752440;
+  constexpr double cs[16] = {1, c1, h, s1, 0, -s1, -h, -c1, -1, -c1, -h, -s1, 0, s1, h, c1};
+  constexpr double sn[16] = {0, s1, h, c1, 1, c1, h, s1, 0, -s1, -h, -c1, -1, -c1, -h, -s1};
+  if constexpr (E == 0) return a;
+  else if constexpr (E == 4) return INV ? mul_pi(a) : mul_mi(a);
+  else if constexpr (E == 8) return C{-a.x, -a.y};
+  else {
+    const T c = (T)cs[E], sv = INV ? (T)sn[E] : -(T)sn[E];  // multiply by c + i sv
+    return C{a.x * c - a.y * sv, a.x * sv + a.y * c};
+  }
+}
+
+// 16-point DFT as 4 x 4: DFT4 over n1 of x[4 n1 + n2], twiddle W16^(n2 k1),
+// DFT4 over n2; output k1 + 4 k2 in natural order.
+template <bool INV, typename C> __device__ __forceinline__ void dft16(C* v) {
+  C y[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    C a = v[n2], b = v[4 + n2], c = v[8 + n2], d = v[12 + n2];
+    dft4<INV>(a, b, c, d);
+    y[n2][0] = a;
+    y[n2][1] = b;
+    y[n2][2] = c;
+    y[n2][3] = d;
+  }
+  y[1][1] = w16<1, INV>(y[1][1]);
+  y[1][2] = w16<2, INV>(y[1][2]);
+  y[1][3] = w16<3, INV>(y[1][3]);
+  y[2][1] = w16<2, INV>(y[2][1]);
+  y[2][2] = w16<4, INV>(y[2][2]);
+  y[2][3] = w16<6, INV>(y[2][3]);
+  y[3][1] = w16<3, INV>(y[3][1]);
+  y[3][2] = w16<6, INV>(y[3][2]);
+  y[3][3] = w16<9, INV>(y[3][3]);
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    C a = y[0][k1], b = y[1][k1], c = y[2][k1], d = y[3][k1];
+    dft4<INV>(a, b, c, d);
+    v[k1] = a;
+    v[k1 + 4] = b;
+    v[k1 + 8] = c;
+    v[k1 + 12] = d;
+  }
+}
+
 template <int R, bool INV, typename C> __device__ __forceinline__ void dft_small(C* v) {
   if constexpr (R == 2) dft2<INV>(v);
   else if constexpr (R == 3) dft3<INV>(v);
   else if constexpr (R == 4) dft4<INV>(v[0], v[1], v[2], v[3]);
-  else dft8<INV>(v);
+  else if constexpr (R == 8) dft8<INV>(v);
+  else dft16<INV>(v);
 }
 
 // ---------------------------------------------------------------------------
-// compile-time radix plan: radix 8 as often as the power of two allows, then
-// one 4 or 2, then the 3s
+// compile-time radix plan. With at least 16 elements per thread (r16): radix
+// 16 as often as the power of two allows, then one 8, 4 or 2, then the 3s;
+// otherwise radix 8 as often as it allows, then one 4 or 2, then the 3s.
 // ---------------------------------------------------------------------------
 constexpr int ct_exp2(int n) {
   int a = 0;
@@ -121,27 +172,31 @@ constexpr int ct_exp3(int n) {
   while (n > 1 && n % 3 == 0) { n /= 3; ++b; }
   return b;
 }
-constexpr int ct_npass(int n) { return ct_exp2(n) / 3 + (ct_exp2(n) % 3 ? 1 : 0) + ct_exp3(n); }
-constexpr int ct_radix(int n, int p) {
-  const int a = ct_exp2(n), n8 = a / 3, rem = a % 3;
-  if (p < n8) return 8;
-  p -= n8;
+constexpr bool ct_r16(int n, int nt) { return nt >= 1 && n / nt >= 16 && ct_exp2(n) >= 4; }
+constexpr int ct_npass(int n, bool r16) {
+  const int a = ct_exp2(n), w = r16 ? 4 : 3;
+  return a / w + (a % w ? 1 : 0) + ct_exp3(n);
+}
+constexpr int ct_radix(int n, bool r16, int p) {
+  const int a = ct_exp2(n), w = r16 ? 4 : 3, nb = a / w, rem = a % w;
+  if (p < nb) return r16 ? 16 : 8;
+  p -= nb;
   if (rem) {
-    if (p == 0) return rem == 2 ? 4 : 2;
+    if (p == 0) return 1 << rem;
     p -= 1;
   }
   return 3;
 }
-constexpr int ct_ns(int n, int p) {
+constexpr int ct_ns(int n, bool r16, int p) {
   int ns = 1;
-  for (int i = 0; i < p; ++i) ns *= ct_radix(n, i);
+  for (int i = 0; i < p; ++i) ns *= ct_radix(n, r16, i);
   return ns;
 }
-constexpr int ct_bt(int n, int nt, int p) { return (n / ct_radix(n, p) + nt - 1) / nt; }
-constexpr int ct_vmax(int n, int nt) {
+constexpr int ct_bt(int n, int nt, bool r16, int p) { return (n / ct_radix(n, r16, p) + nt - 1) / nt; }
+constexpr int ct_vmax(int n, int nt, bool r16) {
   int m = 0;
-  for (int p = 0; p < ct_npass(n); ++p) {
-    const int x = ct_bt(n, nt, p) * ct_radix(n, p);
+  for (int p = 0; p < ct_npass(n, r16); ++p) {
+    const int x = ct_bt(n, nt, r16, p) * ct_radix(n, r16, p);
     m = x > m ? x : m;
   }
   return m;
@@ -169,12 +224,13 @@ template <typename T> constexpr int xpad_len(int n) {
 // x[b + r N/R] again.
 template <typename T, int N, int NT, bool INV>
 struct CtFft {
-  static constexpr int NP = ct_npass(N);
-  static constexpr int VMAX = ct_vmax(N, NT);
+  static constexpr bool R16 = ct_r16(N, NT);
+  static constexpr int NP = ct_npass(N, R16);
+  static constexpr int VMAX = ct_vmax(N, NT, R16);
 
-  template <int P> static constexpr int R() { return ct_radix(N, P); }
-  template <int P> static constexpr int NB() { return N / ct_radix(N, P); }
-  template <int P> static constexpr int BT() { return ct_bt(N, NT, P); }
+  template <int P> static constexpr int R() { return ct_radix(N, R16, P); }
+  template <int P> static constexpr int NB() { return N / ct_radix(N, R16, P); }
+  template <int P> static constexpr int BT() { return ct_bt(N, NT, R16, P); }
   template <int P> __device__ static __forceinline__ bool valid(int b) {
     return (NB<P>() % NT == 0) || b < NB<P>();
   }
@@ -186,7 +242,7 @@ struct CtFft {
 
   template <int P>
   __device__ static __forceinline__ void butterflies(cx<T>* v, int q, const cx<T>* __restrict__ tw) {
-    constexpr int Rr = R<P>(), NS = ct_ns(N, P), TSTEP = N / (NS * Rr);
+    constexpr int Rr = R<P>(), NS = ct_ns(N, R16, P), TSTEP = N / (NS * Rr);
 #pragma unroll
     for (int t = 0; t < BT<P>(); ++t) {
       const int b = q + t * NT;
@@ -207,7 +263,7 @@ struct CtFft {
   // outputs of pass P -> LDS -> inputs of pass P + 1
   template <int P, class Idx>
   __device__ static __forceinline__ void exchange(cx<T>* v, cx<T>* lds, const Idx& li, int q) {
-    constexpr int Rr = R<P>(), NS = ct_ns(N, P);
+    constexpr int Rr = R<P>(), NS = ct_ns(N, R16, P);
 #pragma unroll
     for (int t = 0; t < BT<P>(); ++t) {
       const int b = q + t * NT;
@@ -249,16 +305,16 @@ struct CtFft {
     run_from<0>(v, lds, li, q, tw);
   }
 
-  static constexpr int RL = ct_radix(N, NP - 1);
-  static constexpr int BTL = ct_bt(N, NT, NP - 1);
-  static constexpr int NBL = N / ct_radix(N, NP - 1);
+  static constexpr int RL = ct_radix(N, R16, NP - 1);
+  static constexpr int BTL = ct_bt(N, NT, R16, NP - 1);
+  static constexpr int NBL = N / ct_radix(N, R16, NP - 1);
   __device__ static __forceinline__ bool valid_last(int b) { return (NBL % NT == 0) || b < NBL; }
   // element index of value v[t RL + r] at the output of the last pass
   __device__ static __forceinline__ int out_index(int q, int t, int r) { return q + t * NT + r * NBL; }
 
-  static constexpr int R0 = ct_radix(N, 0);
-  static constexpr int BT0 = ct_bt(N, NT, 0);
-  static constexpr int NB0 = N / ct_radix(N, 0);
+  static constexpr int R0 = ct_radix(N, R16, 0);
+  static constexpr int BT0 = ct_bt(N, NT, R16, 0);
+  static constexpr int NB0 = N / ct_radix(N, R16, 0);
   __device__ static __forceinline__ bool valid_first(int b) { return (NB0 % NT == 0) || b < NB0; }
 };
 
