@@ -202,11 +202,10 @@ constexpr int ct_vmax(int n, int nt, bool r16) {
   return m;
 }
 
-// threads per compile-time transform: eight elements each along x; along
-// y sixteen from length 2048 on, so that a 1024-thread workgroup still holds
-// several columns of the longest transforms
-constexpr int ct_threads(int n) { return n >= 8 ? n / 8 : 1; }
-constexpr int ct_threads_y(int n) { return n >= 2048 ? n / 16 : ct_threads(n); }
+// threads per compile-time transform: ct_threads / ct_threads_y (shared
+// with the host, in monc_types.h)
+constexpr int ct_threads(int n) { return ct_threads_x_n(n); }
+constexpr int ct_threads_y(int n) { return ct_threads_y_n(n); }
 
 // LDS index of element i of an x-direction transform: one pad slot per 128
 // bytes, so the stride-R writes of the first passes spread over all banks.

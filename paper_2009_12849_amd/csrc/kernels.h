@@ -14,8 +14,8 @@ void init_kernel_attributes();
 // n < 8; along y n/16 from n = 2048 on) and need blockDim = (transforms or
 // columns per workgroup) * that.
 bool ct_supported(int n);
-inline int ct_threads_host(int n) { return n >= 8 ? n / 8 : 1; }
-inline int ct_threads_y_host(int n) { return n >= 2048 ? n / 16 : ct_threads_host(n); }
+inline int ct_threads_host(int n) { return ct_threads_x_n(n); }
+inline int ct_threads_y_host(int n) { return ct_threads_y_n(n); }
 
 // ct_n: the compile-time length, or 0 for the runtime-length kernel.
 // mode 0: divergence of (u, v, w); mode 1 (float only): FP64 residual

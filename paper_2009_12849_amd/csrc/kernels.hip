@@ -107,9 +107,9 @@ __device__ __forceinline__ RowCtx make_row(const MemberDesc& d, long long row, b
 }
 
 // Values known to be equal on every lane of a wave, moved to scalar
-// registers (readfirstlane): a row context is per transform, and a transform
-// of N >= 512 points spans whole waves, so vector registers would hold the
-// same value 64 times.
+// registers (readfirstlane): a row context is per transform, and when a
+// transform's thread count is a multiple of 64 it spans whole waves, so
+// vector registers would hold the same value 64 times.
 __device__ __forceinline__ int wuni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 __device__ __forceinline__ long long wuni(long long x) {
   const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)x);
@@ -401,10 +401,11 @@ __global__ void __launch_bounds__(512) k_xfwd_ct(LaunchArgs a) {
   const IoPtrs io = a.io[mi];
   const int lb = xcd_local_block(a, mi);
   const int ipw = blockDim.x / NT;
-  // scalar row contexts for the residual only (one transform spans whole
-  // waves): its occupancy rises from 3 to 5 waves per SIMD and it gains; the
-  // divergence variants measure slower at the higher occupancy
-  constexpr bool UNI = NT >= 64 && MODE == 1;
+  // scalar row contexts for the residual only, and only where a transform
+  // spans whole waves (NT a multiple of 64: then no wave holds lanes of two
+  // transforms): its occupancy rises from 3 to 5 waves per SIMD and it gains;
+  // the divergence variants measure slower at the higher occupancy
+  constexpr bool UNI = NT % 64 == 0 && MODE == 1;
   const int inst = UNI ? wuni((int)(threadIdx.x / NT)) : (int)(threadIdx.x / NT);
   const int q = threadIdx.x - inst * NT;
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw) + inst * xpad_len<T>(N);

@@ -18,6 +18,14 @@ constexpr int kTriSmax = 16;            // rows per lane in the tridiagonal solv
 constexpr int kTriPmax = 64;            // lanes per column (one wave)
 constexpr int kBig = 1 << 30;           // "inactive" lane index
 constexpr int kGenericElems = 8;        // max elements per thread of the runtime-length FFT
+// Threads per compile-time transform (shared by the kernels and the host's
+// launch shapes), and so the radix plan (16 elements per thread take radix-16
+// passes): along x sixteen elements each from length 512 on, eight below;
+// along y sixteen from length 2048 on, so that a 1024-thread workgroup still
+// holds several columns of the longest transforms, eight below.
+constexpr int ct_threads_x_n(int n) { return n >= 512 ? n / 16 : (n >= 8 ? n / 8 : 1); }
+constexpr int ct_threads_y_n(int n) { return n >= 2048 ? n / 16 : (n >= 8 ? n / 8 : 1); }
+
 // x-FFT LDS layout (shared by the kernels and the host's LDS sizes): one pad
 // slot after every 2^shift complex elements, i.e. every 128 bytes
 constexpr int kXpadShift32 = 4;  // FP32 complex (8 B)

@@ -157,7 +157,8 @@ def test_fp64_tiny_grids(shape):
 
 
 @pytest.mark.parametrize("shape", [(48, 27, 13), (192, 96, 40), (64, 1, 8), (3, 64, 7), (96, 72, 33),
-                                   (256, 8, 17), (16, 16, 700), (8, 6, 1024), (2048, 4, 3), (6, 1536, 2)])
+                                   (256, 8, 17), (16, 16, 700), (8, 6, 1024), (2048, 4, 3), (6, 1536, 2),
+                                   (768, 6, 4), (1536, 4, 3), (4096, 2, 3), (512, 6, 4)])
 def test_fp64_ragged_and_extreme_shapes(shape):
     g, u, v, w = _case(shape, 7)
     check_fp64(g, u, v, w)
@@ -247,9 +248,11 @@ def mixed_case(g, u, v, w):
 
 
 @pytest.mark.parametrize("shape", [(32, 32, 32), (48, 27, 13), (192, 96, 40), (1, 1, 4), (64, 64, 130),
-                                   (18, 12, 7), (27, 9, 6)])
+                                   (18, 12, 7), (27, 9, 6), (768, 12, 5), (1536, 9, 3), (3072, 4, 3)])
 def test_mixed_small(shape):
-    # nx = 18 and 27 take the 2- and 1-point gradient variants (4 otherwise)
+    # nx = 18 and 27 take the 2- and 1-point gradient variants (4 otherwise);
+    # nx = 768 and 1536 x-transforms have thread counts that are not
+    # multiples of the wave size, so two transforms share a wave
     g, u, v, w = _case(shape, 11)
     errs, out, ref = mixed_case(g, u, v, w)
     print(f"mixed {shape}: {errs}")
