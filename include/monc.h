@@ -122,13 +122,20 @@ const char* monc_last_error(void);
  * and the benchmark; not needed for ordinary use).
  * ------------------------------------------------------------------- */
 
-/* Geometry of the spectral workspace: value (k, n, m) of the half spectrum
- * (m = 0..nx/2) sits at element k * (*plane_len) + n * (*row_len) + m, with
- * row_len >= nx/2+1 and plane_len >= ny * row_len (both padded);
+/* Geometry of the spectral workspace. Value (k, n, m) of the half spectrum
+ * (m = 0..nx/2) sits at element
+ *   k * (*plane_len) + (m / B) * ny * B + n * B + (m % B),   B = *col_block:
+ * each level holds its columns in blocks of B consecutive m (B a power of
+ * two, 1..8, the width of the plan's y-FFT tiles), each block stored row by
+ * row, so that a y-FFT tile reads one contiguous run. *row_len >= nx/2+1 is
+ * the padded count of m slots (a multiple of 8) and *plane_len >= ny *
+ * (*row_len). The layout can change when the plan's tile parameters change
+ * (monc_plan_set_params, monc_autotune); query it after those calls.
  * *elem_bytes is 16 (FP64) or 8 (MIXED). Any output pointer may be NULL.
  * Returns the number of complex elements (nz * plane_len), or 0 for a NULL
  * plan. */
-size_t monc_spectral_layout(const monc_plan* plan, int* row_len, long long* plane_len, int* elem_bytes);
+size_t monc_spectral_layout(const monc_plan* plan, int* row_len, int* col_block, long long* plane_len,
+                            int* elem_bytes);
 
 /* Stage-wise execution on caller buffers (all device pointers, sizes as in
  * monc_project; `spec` holds monc_spectral_layout() complex elements):

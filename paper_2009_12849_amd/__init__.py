@@ -59,7 +59,8 @@ def lib() -> ctypes.CDLL:
     L.monc_last_error.restype = ctypes.c_char_p
     L.monc_last_error.argtypes = []
     L.monc_spectral_layout.restype = ctypes.c_size_t
-    L.monc_spectral_layout.argtypes = [vp, ctypes.POINTER(ip), ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ip)]
+    L.monc_spectral_layout.argtypes = [vp, ctypes.POINTER(ip), ctypes.POINTER(ip), ctypes.POINTER(ctypes.c_longlong),
+                                       ctypes.POINTER(ip)]
     L.monc_debug_stage.restype = ip
     L.monc_debug_stage.argtypes = [vp, ip, ctypes.POINTER(vp), ip, vp]
     L.monc_kernel_name.restype = ctypes.c_char_p
@@ -161,22 +162,39 @@ class Plan:
 
     # -- introspection / stages / profiling / tuning ---------------------
     def spectral_layout(self):
-        """(elements, row length, plane length, bytes per complex value)."""
-        row, plane, eb = ctypes.c_int(), ctypes.c_longlong(), ctypes.c_int()
-        n = lib().monc_spectral_layout(self._h, ctypes.byref(row), ctypes.byref(plane), ctypes.byref(eb))
-        return int(n), row.value, plane.value, eb.value
+        """(elements, padded row length, column block width, plane length,
+        bytes per complex value); see monc_spectral_layout."""
+        row, blk, plane, eb = ctypes.c_int(), ctypes.c_int(), ctypes.c_longlong(), ctypes.c_int()
+        n = lib().monc_spectral_layout(self._h, ctypes.byref(row), ctypes.byref(blk), ctypes.byref(plane),
+                                       ctypes.byref(eb))
+        return int(n), row.value, blk.value, plane.value, eb.value
 
     def spectral_buffer(self):
         """A zeroed device buffer with the spectral layout, shape (nz, plane)."""
         import torch
-        n, row, plane, eb = self.spectral_layout()
+        n, row, blk, plane, eb = self.spectral_layout()
         dt = torch.complex128 if self.dtype == FP64 else torch.complex64
         return torch.zeros((self.nz, plane), dtype=dt, device="cuda")
 
-    def spectral_view(self, buf):
-        """The (nz, ny, nx/2+1) half spectrum inside a spectral buffer."""
-        n, row, plane, eb = self.spectral_layout()
-        return buf[:, : self.ny * row].reshape(self.nz, self.ny, row)[:, :, : self.nx // 2 + 1]
+    def _blocks(self, buf):
+        # (nz, ny, row/blk, blk) strided view of the column blocks
+        import torch
+        n, row, blk, plane, eb = self.spectral_layout()
+        return torch.as_strided(buf, (self.nz, self.ny, row // blk, blk),
+                                (plane, blk, self.ny * blk, 1), buf.storage_offset())
+
+    def spectral_get(self, buf):
+        """Copy of the (nz, ny, nx/2+1) half spectrum held in a spectral buffer."""
+        v = self._blocks(buf)
+        return v.reshape(self.nz, self.ny, -1)[:, :, : self.nx // 2 + 1]
+
+    def spectral_set(self, buf, values):
+        """Write a (nz, ny, nx/2+1) half spectrum into a spectral buffer."""
+        import torch
+        v = self._blocks(buf)
+        full = torch.zeros((self.nz, self.ny, v.shape[2] * v.shape[3]), dtype=buf.dtype, device=buf.device)
+        full[:, :, : self.nx // 2 + 1] = torch.as_tensor(values).to(device=buf.device, dtype=buf.dtype)
+        v.copy_(full.view(v.shape))
 
     def debug_stage(self, stage: int, bufs, stream=None):
         arr = (ctypes.c_void_p * len(bufs))(*[ctypes.c_void_p(b.data_ptr()) for b in bufs])

@@ -160,6 +160,13 @@ static int configure_tiles(monc_plan* pl, int ex, int ey, int ymt, int triP, int
   pl->ex = ex;
   pl->ey = ey;
   pl->ymt = ymt;
+  // spectral column blocks as wide as a y-FFT tile (up to kSpecBlockMax), so
+  // that the tile is one contiguous run of each level
+  h.sbw = std::min(kSpecBlockMax, pow2_floor(ymt));
+  h.lbw = 0;
+  while ((1 << h.lbw) < h.sbw) ++h.lbw;
+  h.bst = pl->ny * h.sbw;
+  div_magic((unsigned)h.bst, h.bst_mul, h.bst_shift);
   pl->triP = triP;
   pl->tricw = tricw;
   h.fx = fx;
@@ -261,8 +268,7 @@ extern "C" monc_plan* monc_plan_create(int nx, int ny, int nz, double dx, double
   h.ny = ny;
   h.nz = nz;
   h.nxh = nx / 2 + 1;
-  h.nxp = (h.nxh + 7) / 8 * 8;
-  div_magic((unsigned)h.nxp, h.nxp_mul, h.nxp_shift);
+  h.nxp = (h.nxh + kSpecBlockMax - 1) / kSpecBlockMax * kSpecBlockMax;
   h.dtype = dtype;
   h.nrow = (long long)nz * ny;
   // spectral level stride: an odd multiple of 256 bytes, so that the
@@ -409,9 +415,11 @@ extern "C" void monc_plan_destroy(monc_plan* pl) {
 
 extern "C" const char* monc_last_error(void) { return g_err.c_str(); }
 
-extern "C" size_t monc_spectral_layout(const monc_plan* pl, int* row_len, long long* plane_len, int* eb) {
+extern "C" size_t monc_spectral_layout(const monc_plan* pl, int* row_len, int* col_block, long long* plane_len,
+                                       int* eb) {
   if (!pl) return 0;
   if (row_len) *row_len = pl->h.nxp;
+  if (col_block) *col_block = pl->h.sbw;
   if (plane_len) *plane_len = pl->h.plane;
   if (eb) *eb = (int)cplx_bytes(pl->dtype);
   return pl->spec_elems;
@@ -505,7 +513,7 @@ static Shape member_shape(const MemberDesc& d, Phase ph, bool fp64) {
   } else if (ph == PH_TRI) {
     s.variant = d.tris;
     s.block = d.tricw * d.triP;
-    s.lds = (size_t)d.tricw * (d.triP * (d.tris + 1) + 1) * 16;  // matches the kernel's column stride
+    s.lds = (size_t)d.tricw * (d.triP * tri_chunk_slots(d.tris) + 1) * 16;  // matches the kernel's column stride
     s.blocks = ((long long)d.ny * d.nxp + d.tricw - 1) / d.tricw;  // over the padded plane
   } else {
     // points per thread: 16-byte field accesses on the mixed path (4 floats),
@@ -964,7 +972,9 @@ extern "C" int monc_autotune(monc_plan* pl, void* stream) {
   std::vector<Axis> axes;
   if (!ct_supported(pl->nx)) axes.push_back({0, {2, 4, 8}, xmask});
   if (!ct_supported(pl->ny)) axes.push_back({1, {2, 4, 8}, ymask});
-  axes.push_back({2, {1, 2, 4, 8, 16, 32}, ymask});
+  // the y tile width also sets the spectral column blocks, which shape the
+  // x kernels' spectral traffic: timed over both
+  axes.push_back({2, {1, 2, 4, 8, 16, 32}, ymask | xmask});
   axes.push_back({3, pvals, tmask});
   axes.push_back({4, {4, 8, 16, 32}, tmask});
   for (const auto& ax : axes) {

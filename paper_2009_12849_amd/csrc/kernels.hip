@@ -345,19 +345,47 @@ __device__ __forceinline__ void source_vec(const MemberDesc& d, const RowCtx& c,
 
 // Separate two real rows packed as z = a + i b:
 // A[m] = (Z[m] + conj Z[N-m])/2, B[m] = (Z[m] - conj Z[N-m])/(2i).
+// (row 0 gives A[m], row 1 gives B[m]; zr = Z[N-m])
 template <typename T>
-__device__ __forceinline__ void split_store(cx<T>* S, long long o0, long long o1, bool v0, bool v1, int m, cx<T> z,
-                                            cx<T> zr) {
+__device__ __forceinline__ cx<T> split_bin(cx<T> z, cx<T> zr, int row) {
   const T h = (T)0.5;
-  if (v0) S[o0 + m] = cx<T>{h * (z.x + zr.x), h * (z.y - zr.y)};
-  if (v1) S[o1 + m] = cx<T>{h * (z.y + zr.y), h * (zr.x - z.x)};
+  return row ? cx<T>{h * (z.y + zr.y), h * (zr.x - z.x)} : cx<T>{h * (z.x + zr.x), h * (z.y - zr.y)};
 }
 
-// Offset of spectral row r = k*ny + j: levels are `plane` apart (padded so
-// that the plane stride is an odd multiple of 256 bytes), rows nxp apart.
+// Spectral layout (column blocks of sbw bins, see MemberDesc): the value of
+// row r = k*ny + j at bin m sits at spec_row(r) + spec_col(m). Levels are
+// `plane` apart (padded so that the plane stride is an odd multiple of 256
+// bytes); inside a block the rows are sbw apart, so a y-FFT tile of sbw
+// columns is one contiguous run and a row pair writes 2 sbw adjacent values.
 __device__ __forceinline__ long long spec_row(const MemberDesc& d, long long r) {
   const int k = (int)(r / d.ny);
-  return (long long)k * d.plane + (r - (long long)k * d.ny) * d.nxp;
+  return (long long)k * d.plane + (r - (long long)k * d.ny) * d.sbw;
+}
+__device__ __forceinline__ long long spec_col(const MemberDesc& d, int m) {
+  return (long long)(m >> d.lbw) * d.bst + (m & (d.sbw - 1));
+}
+// A row pair's spectral values in slot order: slots walk the column blocks,
+// and inside a block first row 0's sbw bins, then row 1's. When the two rows
+// are adjacent (same level) that is their memory order, so consecutive lanes
+// touch consecutive addresses and a store or load covers 2 sbw values at a
+// time. Slot s holds bin m of row `row` at offset `off` from the row start.
+struct PairSlot {
+  int row, m;
+  long long off;
+};
+__device__ __forceinline__ PairSlot pair_slot(const MemberDesc& d, int s) {
+  const int blk = s >> (d.lbw + 1), w = s & (2 * d.sbw - 1);
+  return PairSlot{w >> d.lbw, (blk << d.lbw) | (w & (d.sbw - 1)), (long long)blk * d.bst + (w & (d.sbw - 1))};
+}
+// slots covering bins 0 .. nxh-1 (whole blocks)
+__device__ __forceinline__ int pair_slots(const MemberDesc& d) { return ((d.nxh + d.sbw - 1) >> d.lbw) << (d.lbw + 1); }
+
+// (n, m) of the value at offset x (< ny * nxp) inside a level
+__device__ __forceinline__ void spec_nm(const MemberDesc& d, int x, int& n, int& m) {
+  const int b = (int)fast_div(x, d.bst_mul, d.bst_shift);
+  const int rem = x - b * d.bst;
+  n = rem >> d.lbw;
+  m = (b << d.lbw) | (rem & (d.sbw - 1));
 }
 
 // Row pairs of the stencil kernels in (level, pair) tiles: consecutive
@@ -473,10 +501,14 @@ __global__ void __launch_bounds__(512) k_xfwd_ct(LaunchArgs a) {
   __syncthreads();
   cx<T>* S = reinterpret_cast<cx<T>*>(io.spec);
   const long long so0 = spec_row(d, v0 ? r0 : 0), so1 = spec_row(d, v1 ? r1 : 0);
-  for (int m = q; m < d.nxh; m += NT) {
-    const cx<T> z = lds[xpad<T>(m)];
-    const cx<T> zr = lds[xpad<T>(m == 0 ? 0 : N - m)];
-    split_store<T>(S, so0, so1, v0, v1, m, z, zr);
+  const int ns = pair_slots(d);
+  for (int s = q; s < ns; s += NT) {
+    const PairSlot ps = pair_slot(d, s);
+    if (ps.m < d.nxh && (ps.row ? v1 : v0)) {
+      const cx<T> z = lds[xpad<T>(ps.m)];
+      const cx<T> zr = lds[xpad<T>(ps.m == 0 ? 0 : N - ps.m)];
+      S[(ps.row ? so1 : so0) + ps.off] = split_bin<T>(z, zr, ps.row);
+    }
   }
 }
 
@@ -511,7 +543,12 @@ __global__ void __launch_bounds__(1024) k_xfwd_gen(LaunchArgs a) {
   if (active) {
     cx<T>* S = reinterpret_cast<cx<T>*>(io.spec);
     const long long so0 = spec_row(d, v0 ? r0 : 0), so1 = spec_row(d, v1 ? r1 : 0);
-    for (int m = q; m < d.nxh; m += nt) split_store<T>(S, so0, so1, v0, v1, m, buf[m], buf[m == 0 ? 0 : N - m]);
+    for (int m = q; m < d.nxh; m += nt) {
+      const cx<T> z = buf[m], zr = buf[m == 0 ? 0 : N - m];
+      const long long cm = spec_col(d, m);
+      if (v0) S[so0 + cm] = split_bin<T>(z, zr, 0);
+      if (v1) S[so1 + cm] = split_bin<T>(z, zr, 1);
+    }
   }
 }
 
@@ -537,8 +574,8 @@ __global__ void __launch_bounds__(1024) k_ffty_ct(LaunchArgs a) {
   const int q = threadIdx.x / mt;
   const int m = (lb - k * tiles) * mt + c;
   const bool valid = m < d.nxh;
-  cx<T>* S = reinterpret_cast<cx<T>*>(io.spec) + (long long)k * d.plane + (valid ? m : 0);
-  const int nxp = d.nxp;
+  cx<T>* S = reinterpret_cast<cx<T>*>(io.spec) + (long long)k * d.plane + spec_col(d, valid ? m : 0);
+  const int rs = d.sbw;  // row stride inside a column block
   cx<T> v[F::VMAX];
   // FP32: unconditional loads (an invalid column reads column 0), zeroed
   // after; FP64 keeps the guarded loads, which measure faster there
@@ -549,10 +586,10 @@ __global__ void __launch_bounds__(1024) k_ffty_ct(LaunchArgs a) {
 #pragma unroll
       for (int r = 0; r < F::R0; ++r) {
         if constexpr (sizeof(T) == 4) {
-          const cx<T> x = S[(b + r * F::NB0) * nxp];
+          const cx<T> x = S[(b + r * F::NB0) * rs];
           v[t * F::R0 + r] = valid ? x : cx<T>{0, 0};
         } else {
-          v[t * F::R0 + r] = valid ? S[(b + r * F::NB0) * nxp] : cx<T>{0, 0};
+          v[t * F::R0 + r] = valid ? S[(b + r * F::NB0) * rs] : cx<T>{0, 0};
         }
       }
     }
@@ -565,7 +602,7 @@ __global__ void __launch_bounds__(1024) k_ffty_ct(LaunchArgs a) {
       const int b = q + t * NT;
       if (F::valid_last(b)) {
 #pragma unroll
-        for (int r = 0; r < F::RL; ++r) S[F::out_index(q, t, r) * nxp] = v[t * F::RL + r];
+        for (int r = 0; r < F::RL; ++r) S[F::out_index(q, t, r) * rs] = v[t * F::RL + r];
       }
     }
   }
@@ -590,13 +627,13 @@ __global__ void __launch_bounds__(1024) k_ffty_gen(LaunchArgs a) {
   const int tot = ny * mt;
   for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
     const int j = idx / mt, cc = idx - j * mt, m = m0 + cc;
-    buf[idx] = (m < d.nxh) ? S[(long long)j * d.nxp + m] : cx<T>{0, 0};
+    buf[idx] = (m < d.nxh) ? S[(long long)j * d.sbw + spec_col(d, m)] : cx<T>{0, 0};
   }
   __syncthreads();
   fft_lds<T, INV>(buf + c, mt, d.fy, reinterpret_cast<const cx<T>*>(d.twy), q);
   for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
     const int j = idx / mt, cc = idx - j * mt, m = m0 + cc;
-    if (m < d.nxh) S[(long long)j * d.nxp + m] = buf[idx];
+    if (m < d.nxh) S[(long long)j * d.sbw + spec_col(d, m)] = buf[idx];
   }
 }
 
@@ -621,9 +658,9 @@ __device__ __forceinline__ void pack_bins(cx<T>* buf, const Idx& idx, cx<T> xa, 
 
 template <typename T, class Idx>
 __device__ __forceinline__ void pack_rows(cx<T>* buf, const Idx& idx, const cx<T>* __restrict__ S, long long o0,
-                                          long long o1, bool v0, bool v1, int N, int m) {
-  cx<T> xa = v0 ? S[o0 + m] : cx<T>{0, 0};
-  cx<T> xb = v1 ? S[o1 + m] : cx<T>{0, 0};
+                                          long long o1, bool v0, bool v1, int N, int m, long long cm) {
+  cx<T> xa = v0 ? S[o0 + cm] : cx<T>{0, 0};
+  cx<T> xb = v1 ? S[o1 + cm] : cx<T>{0, 0};
   const bool selfconj = (m == 0) || (2 * m == N);
   if (selfconj) {
     xa.y = 0;
@@ -677,6 +714,7 @@ __global__ void __launch_bounds__(512) k_xinv_ct(LaunchArgs a) {
   auto li = [](int i) { return xpad<T>(i); };
   {
     // nx/2 + 1 bins over NT threads: N/(2 NT) + 1 rounds, loads issued first
+    // and unconditional (clamped bin; a missing row reads row 0), selected after
     constexpr int RND = N / (2 * NT) + 1;
     const long long so0 = spec_row(d, v0 ? r0 : 0), so1 = spec_row(d, v1 ? r1 : 0);
     cx<T> xa[RND], xb[RND];
@@ -684,8 +722,10 @@ __global__ void __launch_bounds__(512) k_xinv_ct(LaunchArgs a) {
     for (int t = 0; t < RND; ++t) {
       const int m = q + t * NT;
       const bool in = m <= N / 2;
-      xa[t] = (in && v0) ? S[so0 + m] : cx<T>{0, 0};
-      xb[t] = (in && v1) ? S[so1 + m] : cx<T>{0, 0};
+      const long long cm = spec_col(d, in ? m : N / 2);
+      const cx<T> a = S[so0 + cm], b = S[so1 + cm];
+      xa[t] = (in && v0) ? a : cx<T>{0, 0};
+      xb[t] = (in && v1) ? b : cx<T>{0, 0};
     }
 #pragma unroll
     for (int t = 0; t < RND; ++t) {
@@ -777,7 +817,7 @@ __global__ void __launch_bounds__(1024) k_xinv_gen(LaunchArgs a) {
   auto ident = [](int i) { return i; };
   const long long so0 = spec_row(d, v0 ? r0 : 0), so1 = spec_row(d, v1 ? r1 : 0);
   if (active)
-    for (int m = q; m < d.nxh; m += nt) pack_rows<T>(buf, ident, S, so0, so1, v0, v1, N, m);
+    for (int m = q; m < d.nxh; m += nt) pack_rows<T>(buf, ident, S, so0, so1, v0, v1, N, m, spec_col(d, m));
   __syncthreads();
   fft_lds<T, true>(buf, 1, d.fx, reinterpret_cast<const cx<T>*>(d.twx), q);
   if (active)
@@ -871,11 +911,12 @@ __global__ void __launch_bounds__(MAXT) k_tridiag(LaunchArgs a) {
   const int lb = xcd_local_block(a, mi);
   const int P = d.triP, CW = d.tricw, nz = d.nz, nxh = d.nxh, nxp = d.nxp;
   const int lp = __builtin_ctz(P), lcw = __builtin_ctz(CW);  // both powers of two
-  constexpr int SP = S + 1;                  // padded chunk length in LDS
+  constexpr int SP = tri_chunk_slots(S);     // padded chunk length in LDS
   const int lrow = P * SP + 1;               // odd stride: columns start in different banks
-  // columns run linearly over the padded level plane (index n nxp + m), so a
-  // tile is one aligned contiguous run of each level; padding columns
-  // (m >= nxh) ride along as identity systems and are neither read nor written
+  // columns run linearly over the padded level plane in memory order (offset
+  // x inside a level holds column (n, m) = spec_nm(x)), so a tile is one
+  // aligned contiguous run of each level; padding columns (m >= nxh) ride
+  // along as identity systems and are neither read nor written
   const int ncolp = d.ny * nxp;
   const int col0 = lb * CW;
   using CS = cx<TS>;
@@ -893,8 +934,9 @@ __global__ void __launch_bounds__(MAXT) k_tridiag(LaunchArgs a) {
   const int ks = kq * S;
   double2* sst = stage + cc * lrow + kq * SP;
   const int scol_g = col0 + cc;
-  const int sn = (int)fast_div(scol_g, d.nxp_mul, d.nxp_shift);
-  const bool sok = scol_g < ncolp && scol_g - sn * nxp < nxh;
+  int sn, sm;
+  spec_nm(d, scol_g, sn, sm);
+  const bool sok = scol_g < ncolp && sm < nxh;
   const CS* src = Sg + (sok ? scol_g : 0) + (long long)ks * plane;
   const long long last = (long long)(nz - 1 - ks) * plane;  // offset of level nz-1 from src
   CS ld[S];
@@ -906,7 +948,8 @@ __global__ void __launch_bounds__(MAXT) k_tridiag(LaunchArgs a) {
 
   const int c = tid >> lp, q = tid & (P - 1);
   const int col = col0 + c;
-  const int ncol = (int)fast_div(col, d.nxp_mul, d.nxp_shift), mcol = col - ncol * nxp;
+  int ncol, mcol;
+  spec_nm(d, col, ncol, mcol);
   const bool valid = col < ncolp && mcol < nxh;
   const bool singular = valid && (col == 0);
   double2* scol = stage + c * lrow;

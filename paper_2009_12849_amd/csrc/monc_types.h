@@ -18,6 +18,11 @@ constexpr int kTriSmax = 16;            // rows per lane in the tridiagonal solv
 constexpr int kTriPmax = 64;            // lanes per column (one wave)
 constexpr int kBig = 1 << 30;           // "inactive" lane index
 constexpr int kGenericElems = 8;        // max elements per thread of the runtime-length FFT
+constexpr int kSpecBlockMax = 8;        // widest spectral column block (nxp is a multiple of it)
+// LDS slots (16 bytes each) per lane chunk of the tridiagonal solver: S rows
+// rounded up to an odd count, so the chunks of consecutive lanes start in
+// different bank groups
+constexpr int tri_chunk_slots(int s) { return s | 1; }
 // Threads per compile-time transform (shared by the kernels and the host's
 // launch shapes), and so the radix plan (16 elements per thread take radix-16
 // passes): along x sixteen elements each from length 512 on, eight below;
@@ -41,10 +46,10 @@ struct FftPlan {
 struct MemberDesc {
   int nx, ny, nz;
   int nxh;                // nx/2 + 1 spectral values per row
-  int nxp;                // padded spectral row length (complex elements)
+  int nxp;                // padded count of m slots per spectral row (multiple of kSpecBlockMax)
   int dtype;              // 0 = FP64, 1 = mixed
   long long nrow;         // nz * ny real rows
-  long long plane;        // ny * nxp complex values per level
+  long long plane;        // complex values per level: ny * nxp, padded
   double rdx, rdy;        // 1/dx, 1/dy
   double inv_nxny;        // 1/(nx ny), the inverse-FFT normalisation
   double rH;              // 1 / sum(dz)
@@ -73,9 +78,15 @@ struct MemberDesc {
   int tris;               // rows per lane (>= 2)
   int tricw;              // columns per workgroup (blockDim / triP)
   int ptk;                // levels per (level, row pair) tile of the stencil kernels (1 = row order)
-  unsigned nxp_mul;       // x / nxp = (umulhi(x, nxp_mul) + x) >> nxp_shift for 31-bit x
-  int nxp_shift;
-  void* spec;             // spectral workspace (nz, ny, nxp) complex
+  // Spectral layout: a level's half spectrum sits in column blocks of sbw
+  // consecutive m (the y-FFT tile width), each block row-major over n:
+  // element (k, n, m) at k*plane + (m >> lbw)*bst + n*sbw + (m & (sbw-1)).
+  int sbw;                // block width, a power of 2 <= kSpecBlockMax (divides nxp)
+  int lbw;                // log2 sbw
+  int bst;                // elements per block of a level: ny * sbw
+  unsigned bst_mul;       // x / bst = (umulhi(x, bst_mul) + x) >> bst_shift for 31-bit x
+  int bst_shift;
+  void* spec;             // spectral workspace, nz levels of `plane` complex values
   float* prem;            // mixed path: remainder (p1 + delta) - fl32(p1 + delta) in FP32, (nz, ny, nx)
 };
 

@@ -91,6 +91,15 @@ def check_fp64(g, u, v, w, tol=TOL64):
 # stage-wise
 # ---------------------------------------------------------------------------
 STAGE_SHAPES = [(32, 32, 32), (48, 27, 13), (24, 18, 9), (1, 6, 5), (12, 1, 3), (64, 64, 130)]
+# y-FFT columns per workgroup; the spectral column blocks follow it (1..8 wide)
+STAGE_YMT = [1, 2, 4, 8]
+
+
+def _with_ymt(plan, ymt):
+    prm = list(plan.params)
+    prm[2] = ymt
+    plan.params = prm
+    return plan
 
 
 def _case(shape, seed):
@@ -100,39 +109,63 @@ def _case(shape, seed):
     return (g,) + synth.random_fields(rng, g)
 
 
+@pytest.mark.parametrize("ymt", STAGE_YMT)
 @pytest.mark.parametrize("shape", STAGE_SHAPES)
-def test_stage_forward_spectrum(shape):
+def test_stage_forward_spectrum(shape, ymt):
     g, u, v, w = _case(shape, 1)
     ref = oracle.project(u, v, w, g.dx, g.dy, g.dz, g.rho0, intermediates=True)
-    plan = monc.Plan.from_grid(g, "f64")
+    plan = _with_ymt(monc.Plan.from_grid(g, "f64"), ymt)
     spec = plan.spectral_buffer()
     bufs = [to_dev(a, torch.float64) for a in (u, v, w)] + [spec]
     plan.debug_stage(monc.STAGE_FORWARD, bufs)
     torch.cuda.synchronize()
-    got = plan.spectral_view(spec).cpu().numpy()
+    got = plan.spectral_get(spec).cpu().numpy()
     assert relerr(got, ref["B"]) <= 1e-13
 
 
+@pytest.mark.parametrize("ymt", STAGE_YMT)
 @pytest.mark.parametrize("shape", STAGE_SHAPES)
-def test_stage_solve_columns(shape):
+def test_stage_solve_columns(shape, ymt):
     g, u, v, w = _case(shape, 2)
     ref = oracle.project(u, v, w, g.dx, g.dy, g.dz, g.rho0, intermediates=True)
-    plan = monc.Plan.from_grid(g, "f64")
+    plan = _with_ymt(monc.Plan.from_grid(g, "f64"), ymt)
     spec = plan.spectral_buffer()
-    plan.spectral_view(spec).copy_(torch.from_numpy(ref["B"]).to(DEV))
+    plan.spectral_set(spec, torch.from_numpy(ref["B"]))
     plan.debug_stage(monc.STAGE_SOLVE, [spec])
     torch.cuda.synchronize()
-    got = plan.spectral_view(spec).cpu().numpy()
+    got = plan.spectral_get(spec).cpu().numpy()
     assert relerr(got, ref["P"] / (g.nx * g.ny)) <= p_tolerance(g)
 
 
+@pytest.mark.parametrize("ymt", [1, 8])
+@pytest.mark.parametrize("shape", [(48, 27, 13), (64, 64, 130)])
+def test_spectral_layout_formula(shape, ymt):
+    # the buffer positions follow the documented formula (column blocks of B)
+    g, u, v, w = _case(shape, 4)
+    plan = _with_ymt(monc.Plan.from_grid(g, "f64"), ymt)
+    n_el, row, blk, plane, eb = plan.spectral_layout()
+    nxh = g.nx // 2 + 1
+    assert eb == 16 and row >= nxh and row % 8 == 0 and blk in (1, 2, 4, 8) and row % blk == 0
+    eff = plan.params[2]  # the tile width the plan kept (clamped to the grid)
+    assert blk == min(8, 1 << (eff.bit_length() - 1)) and plane >= g.ny * row and n_el == g.nz * plane
+    spec = plan.spectral_buffer()
+    vals = np.arange(g.nz * g.ny * nxh, dtype=np.float64).reshape(g.nz, g.ny, nxh) + 1.0
+    plan.spectral_set(spec, torch.from_numpy(vals.astype(np.complex128)))
+    raw = spec.cpu().numpy().reshape(-1)
+    k, n, m = np.meshgrid(np.arange(g.nz), np.arange(g.ny), np.arange(nxh), indexing="ij")
+    pos = k * plane + (m // blk) * g.ny * blk + n * blk + (m % blk)
+    assert np.array_equal(raw[pos].real, vals)
+    assert np.count_nonzero(raw) == vals.size
+
+
+@pytest.mark.parametrize("ymt", STAGE_YMT)
 @pytest.mark.parametrize("shape", STAGE_SHAPES)
-def test_stage_inverse_and_gradient(shape):
+def test_stage_inverse_and_gradient(shape, ymt):
     g, u, v, w = _case(shape, 3)
     ref = oracle.project(u, v, w, g.dx, g.dy, g.dz, g.rho0, intermediates=True)
-    plan = monc.Plan.from_grid(g, "f64")
+    plan = _with_ymt(monc.Plan.from_grid(g, "f64"), ymt)
     spec = plan.spectral_buffer()
-    plan.spectral_view(spec).copy_(torch.from_numpy(ref["P"] / (g.nx * g.ny)).to(DEV))
+    plan.spectral_set(spec, torch.from_numpy(ref["P"] / (g.nx * g.ny)))
     p = torch.empty((g.nz, g.ny, g.nx), dtype=torch.float64, device=DEV)
     plan.debug_stage(monc.STAGE_INVERSE, [spec, p])
     torch.cuda.synchronize()

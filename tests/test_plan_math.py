@@ -44,6 +44,26 @@ int main(int argc, char** argv) {
       if (fast_div(x, mul, sh) != x / d) ++bad;
     }
   }
+  // block strides ny * B of the spectral layout (B = 1..8) for 3-smooth ny up to 8192
+  for (unsigned ny = 1; ny <= 8192; ++ny) {
+    unsigned r = ny;
+    while (r % 2 == 0) r /= 2;
+    while (r % 3 == 0) r /= 3;
+    if (r != 1) continue;
+    for (unsigned bw = 1; bw <= 8; bw *= 2) {
+      const unsigned d = ny * bw;
+      if (d <= 9000) continue;
+      unsigned mul; int sh;
+      div_magic(d, mul, sh);
+      const unsigned edge[4] = {d - 1, d, 2 * d - 1, 0x7fffffffu};
+      for (int t = 0; t < 256; ++t) {
+        s = s * 1664525u + 1013904223u;
+        const unsigned x = (t < 4) ? edge[t] : (s & 0x7fffffffu);
+        ++checked;
+        if (fast_div(x, mul, sh) != x / d) ++bad;
+      }
+    }
+  }
   std::printf("div %llu %llu\n", checked, bad);
   // 2. radix plans
   const int ns[] = {1, 2, 3, 4, 6, 8, 9, 12, 16, 27, 48, 96, 243, 256, 768, 1024, 1536, 2048, 4096, 6561, 8192, 5, 7, 10, 14, 9000};
