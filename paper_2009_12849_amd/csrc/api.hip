@@ -475,9 +475,6 @@ struct Shape {
   long long blocks = 0;
 };
 
-static size_t xpad_len_host(int n, size_t cb) {
-  return (size_t)n + (size_t)(n >> (cb == 16 ? kXpadShift64 : kXpadShift32)) + 1;
-}
 
 static Shape member_shape(const MemberDesc& d, Phase ph, bool fp64) {
   const size_t cb = fp64 ? 16 : 8;
@@ -489,7 +486,7 @@ static Shape member_shape(const MemberDesc& d, Phase ph, bool fp64) {
       const int ipw = std::max(1, 256 / nt);
       s.variant = d.nx;
       s.block = ipw * nt;
-      s.lds = (size_t)ipw * xpad_len_host(d.nx, cb) * cb;
+      s.lds = (size_t)ipw * xlds_len(d.nx, (int)cb) * cb;
       s.blocks = (pairs + ipw - 1) / ipw;
     } else {
       s.block = std::max(256, (d.fx.nt + 63) / 64 * 64);

@@ -207,13 +207,16 @@ constexpr int ct_vmax(int n, int nt, bool r16) {
 constexpr int ct_threads(int n) { return ct_threads_x_n(n); }
 constexpr int ct_threads_y(int n) { return ct_threads_y_n(n); }
 
-// LDS index of element i of an x-direction transform: one pad slot per 128
-// bytes, so the stride-R writes of the first passes spread over all banks.
-template <typename T> __device__ __forceinline__ int xpad(int i) {
-  return i + (i >> (sizeof(T) == 8 ? kXpadShift64 : kXpadShift32));
-}
-template <typename T> constexpr int xpad_len(int n) {
-  return n + (n >> (sizeof(T) == 8 ? kXpadShift64 : kXpadShift32)) + 1;
+// LDS index of element i of an x-direction transform of length N (bank
+// rows permuted by XOR, or padded; see xlds_len)
+template <typename T, int N> __device__ __forceinline__ int xpad(int i) {
+  constexpr int cb = 2 * sizeof(T);
+  if constexpr (xsw_on(N, cb)) {
+    constexpr int B = xsw_bits(cb);
+    return i ^ ((i >> B) & ((1 << B) - 1));
+  } else {
+    return i + (i >> (cb == 16 ? kXpadShift64 : kXpadShift32));
+  }
 }
 
 // Compile-time Stockham transform. Thread q (0 <= q < NT) owns butterflies

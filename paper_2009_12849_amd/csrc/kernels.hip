@@ -436,7 +436,7 @@ __global__ void __launch_bounds__(512) k_xfwd_ct(LaunchArgs a) {
   constexpr bool UNI = NT % 64 == 0 && MODE == 1;
   const int inst = UNI ? wuni((int)(threadIdx.x / NT)) : (int)(threadIdx.x / NT);
   const int q = threadIdx.x - inst * NT;
-  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw) + inst * xpad_len<T>(N);
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw) + inst * xlds_len(N, 2 * sizeof(T));
   const long long pair = tiled_pair(d, (long long)lb * ipw + inst);
   const long long r0 = 2 * pair, r1 = 2 * pair + 1;
   const bool v0 = r0 < d.nrow, v1 = r1 < d.nrow;
@@ -473,7 +473,7 @@ __global__ void __launch_bounds__(512) k_xfwd_ct(LaunchArgs a) {
         for (int e = 0; e < V; ++e) s1[e] = (T)0;
     }
 #pragma unroll
-    for (int e = 0; e < V; ++e) lds[xpad<T>(i0 + e)] = cx<T>{s0[e], s1[e]};
+    for (int e = 0; e < V; ++e) lds[xpad<T, N>(i0 + e)] = cx<T>{s0[e], s1[e]};
   };
 #pragma unroll
   for (int t = 0; t < N / (V * NT); ++t) stencil(t);
@@ -484,18 +484,18 @@ __global__ void __launch_bounds__(512) k_xfwd_ct(LaunchArgs a) {
     const int b = q + t * NT;
     if (F::valid_first(b)) {
 #pragma unroll
-      for (int r = 0; r < F::R0; ++r) v[t * F::R0 + r] = lds[xpad<T>(b + r * F::NB0)];
+      for (int r = 0; r < F::R0; ++r) v[t * F::R0 + r] = lds[xpad<T, N>(b + r * F::NB0)];
     }
   }
   __syncthreads();
-  auto li = [](int i) { return xpad<T>(i); };
+  auto li = [](int i) { return xpad<T, N>(i); };
   F::run(v, lds, li, q, reinterpret_cast<const cx<T>*>(d.twx));
 #pragma unroll
   for (int t = 0; t < F::BTL; ++t) {
     const int b = q + t * NT;
     if (F::valid_last(b)) {
 #pragma unroll
-      for (int r = 0; r < F::RL; ++r) lds[xpad<T>(F::out_index(q, t, r))] = v[t * F::RL + r];
+      for (int r = 0; r < F::RL; ++r) lds[xpad<T, N>(F::out_index(q, t, r))] = v[t * F::RL + r];
     }
   }
   __syncthreads();
@@ -505,8 +505,8 @@ __global__ void __launch_bounds__(512) k_xfwd_ct(LaunchArgs a) {
   for (int s = q; s < ns; s += NT) {
     const PairSlot ps = pair_slot(d, s);
     if (ps.m < d.nxh && (ps.row ? v1 : v0)) {
-      const cx<T> z = lds[xpad<T>(ps.m)];
-      const cx<T> zr = lds[xpad<T>(ps.m == 0 ? 0 : N - ps.m)];
+      const cx<T> z = lds[xpad<T, N>(ps.m)];
+      const cx<T> zr = lds[xpad<T, N>(ps.m == 0 ? 0 : N - ps.m)];
       S[(ps.row ? so1 : so0) + ps.off] = split_bin<T>(z, zr, ps.row);
     }
   }
@@ -706,12 +706,12 @@ __global__ void __launch_bounds__(512) k_xinv_ct(LaunchArgs a) {
   const int ipw = blockDim.x / NT;
   const int inst = threadIdx.x / NT;
   const int q = threadIdx.x - inst * NT;
-  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw) + inst * xpad_len<T>(N);
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw) + inst * xlds_len(N, 2 * sizeof(T));
   const long long pair = (long long)lb * ipw + inst;
   const long long r0 = 2 * pair, r1 = 2 * pair + 1;
   const bool v0 = r0 < d.nrow, v1 = r1 < d.nrow;
   const cx<T>* S = reinterpret_cast<const cx<T>*>(io.spec);
-  auto li = [](int i) { return xpad<T>(i); };
+  auto li = [](int i) { return xpad<T, N>(i); };
   {
     // nx/2 + 1 bins over NT threads: N/(2 NT) + 1 rounds, loads issued first
     // and unconditional (clamped bin; a missing row reads row 0), selected after
@@ -740,7 +740,7 @@ __global__ void __launch_bounds__(512) k_xinv_ct(LaunchArgs a) {
     const int b = q + t * NT;
     if (F::valid_first(b)) {
 #pragma unroll
-      for (int r = 0; r < F::R0; ++r) v[t * F::R0 + r] = lds[xpad<T>(b + r * F::NB0)];
+      for (int r = 0; r < F::R0; ++r) v[t * F::R0 + r] = lds[xpad<T, N>(b + r * F::NB0)];
     }
   }
   __syncthreads();
@@ -750,7 +750,7 @@ __global__ void __launch_bounds__(512) k_xinv_ct(LaunchArgs a) {
     const int b = q + t * NT;
     if (F::valid_last(b)) {
 #pragma unroll
-      for (int r = 0; r < F::RL; ++r) lds[xpad<T>(F::out_index(q, t, r))] = v[t * F::RL + r];
+      for (int r = 0; r < F::RL; ++r) lds[xpad<T, N>(F::out_index(q, t, r))] = v[t * F::RL + r];
     }
   }
   __syncthreads();
@@ -764,7 +764,7 @@ __global__ void __launch_bounds__(512) k_xinv_ct(LaunchArgs a) {
     vt a0, a1;
 #pragma unroll
     for (int e = 0; e < V; ++e) {
-      const cx<T> z = lds[xpad<T>(i0 + e)];
+      const cx<T> z = lds[xpad<T, N>(i0 + e)];
       a0[e] = z.x;
       a1[e] = z.y;
     }

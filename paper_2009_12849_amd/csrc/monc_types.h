@@ -31,10 +31,22 @@ constexpr int tri_chunk_slots(int s) { return s | 1; }
 constexpr int ct_threads_x_n(int n) { return n >= 512 ? n / 16 : (n >= 8 ? n / 8 : 1); }
 constexpr int ct_threads_y_n(int n) { return n >= 2048 ? n / 16 : (n >= 8 ? n / 8 : 1); }
 
-// x-FFT LDS layout (shared by the kernels and the host's LDS sizes): one pad
-// slot after every 2^shift complex elements, i.e. every 128 bytes
-constexpr int kXpadShift32 = 4;  // FP32 complex (8 B)
-constexpr int kXpadShift64 = 3;  // FP64 complex (16 B)
+// x-FFT LDS layout (shared by the kernels and the host's LDS sizes). For
+// transforms with radix-16 passes (16 elements per thread), a bank row (256
+// bytes: 2^bits complex values) is permuted by XOR of the value's index with
+// the row number, which spreads the stride-16 writes over all banks at no LDS
+// cost; other lengths (radix 8 and below, where it measured slower, or not
+// whole bank rows) get one pad slot after every 2^shift values (128 bytes).
+constexpr int kXswBits32 = 5;    // FP32 complex (8 B): 32 values per bank row
+constexpr int kXswBits64 = 4;    // FP64 complex (16 B): 16 values per bank row
+constexpr int kXpadShift32 = 4;
+constexpr int kXpadShift64 = 3;
+constexpr int xsw_bits(int cb) { return cb == 16 ? kXswBits64 : kXswBits32; }
+constexpr bool xsw_on(int n, int cb) { return ct_threads_x_n(n) * 16 == n && n % (1 << xsw_bits(cb)) == 0; }
+// LDS slots of one x transform of length n (complex values of cb bytes)
+constexpr int xlds_len(int n, int cb) {
+  return xsw_on(n, cb) ? n : n + (n >> (cb == 16 ? kXpadShift64 : kXpadShift32)) + 1;
+}
 
 struct FftPlan {
   int n;                  // transform length (2^a 3^b)
