@@ -322,6 +322,7 @@ extern "C" monc_plan* monc_plan_create(int nx, int ny, int nz, double dx, double
   const size_t o_ly = off; off += al((size_t)ny * 8);
   const size_t o_tx = off; off += al((size_t)nx * 2 * eb);
   const size_t o_ty = off; off += al((size_t)ny * 2 * eb);
+  const size_t o_tr = off; off += al(3 * (size_t)(nz + kTriPmax) * 8);
   const size_t tables_bytes = off;
   std::vector<unsigned char> blob(tables_bytes, 0);
   double* v64 = reinterpret_cast<double*>(blob.data() + o_v64);
@@ -345,6 +346,16 @@ extern "C" monc_plan* monc_plan_create(int nx, int ny, int nz, double dx, double
   };
   put_tw(o_tx, twx);
   put_tw(o_ty, twy);
+  {
+    const size_t nt = (size_t)nz + kTriPmax;
+    double* tr = reinterpret_cast<double*>(blob.data() + o_tr);
+    for (size_t k = 0; k < nt; ++k) {
+      const bool in = k < (size_t)nz;
+      tr[k] = in ? vt.ta[k] : 1.0;
+      tr[nt + k] = in ? vt.tc[k] : 0.0;
+      tr[2 * nt + k] = in ? vt.rho0[k] : 0.0;
+    }
+  }
 
   // device side
   std::call_once(g_attr_once, [] { init_kernel_attributes(); });
@@ -383,6 +394,9 @@ extern "C" monc_plan* monc_plan_create(int nx, int ny, int nz, double dx, double
   h.dz = d64 + 4 * (size_t)nz;
   h.ta = d64 + 5 * (size_t)nz;
   h.tc = d64 + 6 * (size_t)nz;
+  h.tra = reinterpret_cast<const double*>(base + o_tr);
+  h.trc = h.tra + nz + kTriPmax;
+  h.trr = h.trc + nz + kTriPmax;
   const float* d32 = reinterpret_cast<const float*>(base + o_v32);
   h.rho0f = d32;
   h.rhowf = d32 + nz;

@@ -864,15 +864,15 @@ __device__ __forceinline__ double rcp64(double x) {
 
 // Value of lane q - H (FROM_BELOW) or q + H of the same 16-lane row, moved
 // with DPP (row_shr / row_shl) on the vector ALU instead of the LDS
-// crossbar; a lane whose source lies outside its row keeps its own value.
-// With P = 16 lanes per column, a row is a column, which is exactly the
-// clamping the cyclic reduction wants.
+// crossbar; a lane whose source lies outside its row reads 0. With P = 16
+// lanes per column, a row is a column; every use multiplies such a value by
+// a coupling that is already zero at the column's ends.
 template <int H, bool FROM_BELOW>
 __device__ __forceinline__ double dpp_shift(double v) {
   constexpr int ctrl = FROM_BELOW ? 0x110 + H : 0x100 + H;
   const int lo = __double2loint(v), hi = __double2hiint(v);
-  const int l2 = __builtin_amdgcn_update_dpp(lo, lo, ctrl, 0xF, 0xF, false);
-  const int h2 = __builtin_amdgcn_update_dpp(hi, hi, ctrl, 0xF, 0xF, false);
+  const int l2 = __builtin_amdgcn_mov_dpp(lo, ctrl, 0xF, 0xF, true);
+  const int h2 = __builtin_amdgcn_mov_dpp(hi, ctrl, 0xF, 0xF, true);
   return __hiloint2double(h2, l2);
 }
 
@@ -937,13 +937,15 @@ __global__ void __launch_bounds__(MAXT) k_tridiag(LaunchArgs a) {
   int sn, sm;
   spec_nm(d, scol_g, sn, sm);
   const bool sok = scol_g < ncolp && sm < nxh;
-  const CS* src = Sg + (sok ? scol_g : 0) + (long long)ks * plane;
-  const long long last = (long long)(nz - 1 - ks) * plane;  // offset of level nz-1 from src
   CS ld[S];
+  {
+    // levels ks .. ks+S-1, clamped to nz-1 (those rows are zeroed below)
+    const CS* src = Sg + (sok ? scol_g : 0) + (long long)min(ks, nz - 1) * plane;
 #pragma unroll
-  for (int j = 0; j < S; ++j) {
-    const long long o = (long long)j * plane;
-    ld[j] = src[o < last ? o : last];
+    for (int j = 0; j < S; ++j) {
+      ld[j] = src[0];
+      if (j + 1 < S) src += (ks + j + 1 < nz) ? plane : 0;
+    }
   }
 
   const int c = tid >> lp, q = tid & (P - 1);
@@ -955,16 +957,16 @@ __global__ void __launch_bounds__(MAXT) k_tridiag(LaunchArgs a) {
   double2* scol = stage + c * lrow;
   const int k0 = q * S;
 
-  // coefficients of the lane's rows (identity outside the system): all loads
-  // unconditional and issued while the column data is still arriving
+  // coefficients of the lane's rows (the tables run past nz with rows that
+  // are decoupled from the system): loads issued while the column data is
+  // still arriving
   const double lamv = ldg(d.lamy + min(ncol, d.ny - 1)) + ldg(d.lamx + min(mcol, nxh - 1));
   double A[S], B[S], C[S], R0[S];
 #pragma unroll
-  for (int r = 0; r < S; ++r) {  // clamped level, selected below
-    const int k = min(k0 + r, nz - 1);
-    A[r] = ldg(d.ta + k);
-    C[r] = ldg(d.tc + k);
-    R0[r] = ldg(d.rho0 + k);
+  for (int r = 0; r < S; ++r) {
+    A[r] = ldg(d.tra + k0 + r);
+    C[r] = ldg(d.trc + k0 + r);
+    R0[r] = ldg(d.trr + k0 + r);
   }
   // column data into LDS (zero outside the grid)
 #pragma unroll
@@ -972,23 +974,27 @@ __global__ void __launch_bounds__(MAXT) k_tridiag(LaunchArgs a) {
     const bool in = sok && ks + j < nz;  // every slot exists; rows >= nz are never read
     sst[j] = make_double2(in ? (double)ld[j].x : 0.0, in ? (double)ld[j].y : 0.0);
   }
-  const double lam = valid ? lamv : 0.0;
+  // padding columns (m >= nxh) solve a well-conditioned dummy system with a
+  // zero right-hand side and are never stored
+  const double lam = valid ? lamv : 1.0;
 #pragma unroll
-  for (int r = 0; r < S; ++r) {
-    const int k = k0 + r;
-    const bool in = valid && k < nz && !(singular && k == nz - 1);
-    B[r] = in ? -(A[r] + C[r]) - R0[r] * lam : 1.0;
-    A[r] = in ? A[r] : 0.0;
-    C[r] = in ? C[r] : 0.0;
+  for (int r = 0; r < S; ++r) B[r] = -(A[r] + C[r]) - R0[r] * lam;
+  if (singular) {  // (0,0) column: its top row is pinned (identity); one wave
+    asm volatile("" ::: "memory");  // a real branch, not selects in every column
+#pragma unroll
+    for (int r = 0; r < S; ++r)
+      if (k0 + r == nz - 1) {
+        A[r] = 0.0;
+        B[r] = 1.0;
+        C[r] = 0.0;
+      }
   }
   __syncthreads();
 
+  // staged data: zero for rows >= nz and for padding columns
   double2 D[S];
 #pragma unroll
-  for (int r = 0; r < S; ++r) {
-    const int k = k0 + r;
-    D[r] = (valid && k < nz) ? scol[q * SP + r] : make_double2(0.0, 0.0);
-  }
+  for (int r = 0; r < S; ++r) D[r] = scol[q * SP + r];
   // (0,0) column (one per member, lanes of one wave): remove the dz-weighted
   // mean of the right-hand side, then pin the top row (identity, rhs 0)
   if (singular) {
@@ -1137,8 +1143,7 @@ __global__ void __launch_bounds__(MAXT) k_tridiag(LaunchArgs a) {
     }
   }
 #pragma unroll
-  for (int r = 0; r < S; ++r)
-    if (k0 + r < nz) scol[q * SP + r] = X[r];
+  for (int r = 0; r < S; ++r) scol[q * SP + r] = X[r];  // rows >= nz are never stored
   __syncthreads();
 
   // coalesced store (the staging thread's rows), scaled by 1/(nx ny)

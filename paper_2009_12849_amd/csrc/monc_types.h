@@ -74,6 +74,14 @@ struct MemberDesc {
   const double* dz;       // dz_k (gauge weights)
   const double* ta;       // tridiagonal sub-diagonal a_k (a_0 = 0)
   const double* tc;       // tridiagonal super-diagonal c_k (c_{nz-1} = 0)
+  // The tridiagonal solver's rows, kTriPmax past nz: row k of the column with
+  // eigenvalue lam reads tra_k P_{k-1} - (tra_k + trc_k + trr_k lam) P_k +
+  // trc_k P_{k+1}. Rows past nz read P_k - P_{k-1} = 0 (tra 1, trc 0, trr 0):
+  // nonsingular for every lam, and the lid (c_{nz-1} = 0) keeps them out of
+  // the real rows, so a lane's rows need no range checks.
+  const double* tra;
+  const double* trc;
+  const double* trr;
   // FP32 copies for the FP32 stencil
   const float* rho0f;
   const float* rhowf;
