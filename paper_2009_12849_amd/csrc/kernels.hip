@@ -901,14 +901,10 @@ __device__ __forceinline__ double2 column_sum(double2 v, int P) {
   return v;
 }
 
-template <typename TS, int S, int MAXT>
-__global__ void __launch_bounds__(MAXT) k_tridiag(LaunchArgs a) {
-  extern __shared__ unsigned char smem_raw[];
-  double2* stage = reinterpret_cast<double2*>(smem_raw);
-  const int mi = find_member(a, blockIdx.x);
-  const MemberDesc& d = *a.mem[mi];
-  const IoPtrs io = a.io[mi];
-  const int lb = xcd_local_block(a, mi);
+// One tile of columns; SING: the tile holds the (0,0) column (tile 0), so
+// the mean removal, the pinned top row and the gauge are compiled in.
+template <typename TS, int S, bool SING>
+__device__ __forceinline__ void tri_tile(const MemberDesc& d, const IoPtrs& io, int lb, double2* stage) {
   const int P = d.triP, CW = d.tricw, nz = d.nz, nxh = d.nxh, nxp = d.nxp;
   const int lp = __builtin_ctz(P), lcw = __builtin_ctz(CW);  // both powers of two
   constexpr int SP = tri_chunk_slots(S);     // padded chunk length in LDS
@@ -953,7 +949,7 @@ __global__ void __launch_bounds__(MAXT) k_tridiag(LaunchArgs a) {
   int ncol, mcol;
   spec_nm(d, col, ncol, mcol);
   const bool valid = col < ncolp && mcol < nxh;
-  const bool singular = valid && (col == 0);
+  const bool singular = SING && valid && (col == 0);
   double2* scol = stage + c * lrow;
   const int k0 = q * S;
 
@@ -979,8 +975,7 @@ __global__ void __launch_bounds__(MAXT) k_tridiag(LaunchArgs a) {
   const double lam = valid ? lamv : 1.0;
 #pragma unroll
   for (int r = 0; r < S; ++r) B[r] = -(A[r] + C[r]) - R0[r] * lam;
-  if (singular) {  // (0,0) column: its top row is pinned (identity); one wave
-    asm volatile("" ::: "memory");  // a real branch, not selects in every column
+  if (singular) {  // (0,0) column: its top row is pinned (identity)
 #pragma unroll
     for (int r = 0; r < S; ++r)
       if (k0 + r == nz - 1) {
@@ -1157,6 +1152,20 @@ __global__ void __launch_bounds__(MAXT) k_tridiag(LaunchArgs a) {
     for (int j = 0; j < S; ++j)
       if (ks + j < nz) dst[j * plane] = CS{(TS)(x[j].x * sc), (TS)(x[j].y * sc)};
   }
+}
+
+template <typename TS, int S, int MAXT>
+__global__ void __launch_bounds__(MAXT) k_tridiag(LaunchArgs a) {
+  extern __shared__ unsigned char smem_raw[];
+  double2* stage = reinterpret_cast<double2*>(smem_raw);
+  const int mi = find_member(a, blockIdx.x);
+  const MemberDesc& d = *a.mem[mi];
+  const IoPtrs io = a.io[mi];
+  const int lb = xcd_local_block(a, mi);
+  if (lb == 0)
+    tri_tile<TS, S, true>(d, io, lb, stage);
+  else
+    tri_tile<TS, S, false>(d, io, lb, stage);
 }
 
 // ---------------------------------------------------------------------------
