@@ -950,7 +950,10 @@ extern "C" int monc_autotune(monc_plan* pl, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   const unsigned saved_mask = pl->prof.mask;
   // time every candidate value of one parameter, all else fixed; the cost of
-  // a candidate is the summed time of the kernels that parameter shapes
+  // a candidate is the summed time of the kernels that parameter shapes over
+  // `reps` projections (enough for a few milliseconds of kernel time, so that
+  // small grids are not ranked on noise)
+  int reps = 4;
   auto measure = [&](const int* prm, unsigned kmask, double& cost) -> int {
     int r = monc_plan_set_params(pl, prm);
     if (r != MONC_OK) return r;
@@ -960,7 +963,7 @@ extern "C" int monc_autotune(monc_plan* pl, void* stream) {
     double ms[MONC_K_COUNT] = {0};
     int cnt[MONC_K_COUNT] = {0};
     monc_profile_read(pl, nullptr, nullptr);  // drop warm-up records
-    for (int it = 0; it < 4; ++it)
+    for (int it = 0; it < reps; ++it)
       if ((r = monc_project(pl, buf[0], buf[1], buf[2], buf[3], st)) != MONC_OK) return r;
     if ((r = monc_profile_read(pl, ms, cnt)) != MONC_OK) return r;
     cost = 0.0;
@@ -968,6 +971,17 @@ extern "C" int monc_autotune(monc_plan* pl, void* stream) {
     return MONC_OK;
   };
   int best[MONC_NPARAMS] = {pl->ex, pl->ey, pl->ymt, pl->triP, pl->tricw};
+  {
+    double whole = 0.0;
+    const int r = measure(best, (1u << MONC_K_COUNT) - 1, whole);
+    if (r != MONC_OK) {
+      pl->prof.mask = saved_mask;
+      for (auto& b : buf) (void)hipFree(b);
+      return r;
+    }
+    const double per = whole / reps;  // ms per projection
+    reps = per > 0.0 ? (int)std::min(64.0, std::max(4.0, std::ceil(3.0 / per))) : 4;
+  }
   const unsigned xmask = (1u << MONC_K_DIV_FFTX) | (1u << MONC_K_IFFTX) | (1u << MONC_K_RESID_FFTX);
   const unsigned ymask = (1u << MONC_K_FFTY_FWD) | (1u << MONC_K_FFTY_INV);
   const unsigned tmask = 1u << MONC_K_TRIDIAG;
