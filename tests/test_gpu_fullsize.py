@@ -1,0 +1,158 @@
+"""Full-size parity in the launch configuration the benchmark times: the
+256^2 x 128, 1024^2 x 256 and 2048^2 x 160 grids and the 48-member ensemble,
+with tile parameters picked by the library's autotuner once per distinct grid,
+as bench.py does.
+
+At these sizes the expected values come from a manufactured solution whose
+discrete answer is known in closed form at every point (the oracle's
+manufactured-eigenfunction pin, at full size):
+
+  p_true = X(i) Y(j) Z1(k) + Z2(k),  X = cos(2 pi m0 (i+1/2)/nx),
+           Y = cos(2 pi n0 (j+1/2)/ny), (m0, n0) != (0, 0), sum_k dz_k Z2_k = 0,
+  u* = G p_true + u_sol, with u_sol = (dy psi, -dx psi, 0) Zs(k) from a random
+       corner streamfunction psi, so that D u_sol = 0 exactly.
+
+The projection of u* is u_sol and its pressure is p_true (whose gauge sum is
+zero), so every output point has a closed-form expected value. The fields are
+built on the GPU in FP64 from 1-D and 2-D factors; the mixed path gets them
+rounded to FP32 and is held to the mixed tolerance against the unrounded
+closed form."""
+import numpy as np
+import pytest
+
+import synth
+from tests.tolerances import TOL64, TOL_MIXED, p_tolerance
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2009_12849_amd as monc  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _vertical(g):
+    dz = np.asarray(g.dz, dtype=np.float64)
+    zc = np.cumsum(dz) - 0.5 * dz
+    dzc = 0.5 * (dz[:-1] + dz[1:])
+    return dz, zc, dzc
+
+
+class Manufactured:
+    """Inputs and closed-form outputs of one member, as GPU FP64 factors."""
+
+    def __init__(self, g, seed, m0=3, n0=2):
+        rng = np.random.default_rng(seed)
+        nx, ny, nz = g.nx, g.ny, g.nz
+        dz, zc, dzc = _vertical(g)
+        H = dz.sum()
+        i, j = np.arange(nx), np.arange(ny)
+        X = np.cos(2 * np.pi * (m0 % nx) * (i + 0.5) / nx)
+        Y = np.cos(2 * np.pi * (n0 % ny) * (j + 0.5) / ny)
+        Z1 = np.cos(np.pi * zc / H) + 0.3 * rng.standard_normal(nz)
+        Z2 = (zc - np.sum(dz * zc) / H) / H            # dz-weighted mean zero, O(1)
+        Zs = 1.0 + 0.5 * rng.uniform(-1.0, 1.0, nz)
+        psi = rng.standard_normal((ny, nx))        # at the corners ((i+1) dx, (j+1) dy)
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(DEV, torch.float64)
+        self.g = g
+        self.X, self.Y, self.Z1, self.Z2, self.Zs = t(X), t(Y), t(Z1), t(Z2), t(Zs)
+        self.gx = t((np.roll(X, -1) - X) / g.dx)   # (X_{i+1} - X_i)/dx
+        self.gy = t((np.roll(Y, -1) - Y) / g.dy)
+        dZ1 = np.zeros(nz)
+        dZ2 = np.zeros(nz)
+        dZ1[:-1] = (Z1[1:] - Z1[:-1]) / dzc
+        dZ2[:-1] = (Z2[1:] - Z2[:-1]) / dzc
+        self.dZ1, self.dZ2 = t(dZ1), t(dZ2)
+        # u_sol on the east faces, v_sol on the north faces (D u_sol = 0)
+        self.us = t((psi - np.roll(psi, 1, axis=0)) / g.dy)
+        self.vs = t(-(psi - np.roll(psi, 1, axis=1)) / g.dx)
+
+    def inputs(self):
+        X, Y, Z1 = self.X, self.Y, self.Z1
+        u = self.gx[None, None, :] * Y[None, :, None] * Z1[:, None, None] + self.us[None] * self.Zs[:, None, None]
+        v = X[None, None, :] * self.gy[None, :, None] * Z1[:, None, None] + self.vs[None] * self.Zs[:, None, None]
+        w = (Y[:, None] * X[None, :])[None] * self.dZ1[:, None, None] + self.dZ2[:, None, None]
+        w[-1] = 0.0
+        return u, v, w
+
+    def errors(self, u, v, w, p, scale):
+        """Normwise max errors of u, v, w (over the input scale) and p."""
+        X, Y = self.X, self.Y
+        mx = lambda a: float(a.abs().max())
+        eu = mx(u.double() - self.us[None] * self.Zs[:, None, None]) / scale
+        ev = mx(v.double() - self.vs[None] * self.Zs[:, None, None]) / scale
+        ew = mx(w.double()) / scale
+        pe = (Y[:, None] * X[None, :])[None] * self.Z1[:, None, None] + self.Z2[:, None, None]
+        ep = mx(p.double() - pe) / mx(pe)
+        return [eu, ev, ew, ep]
+
+
+def _tune(plans):
+    tuned = {}
+    for pl in plans:
+        key = (pl.nx, pl.ny, pl.nz)
+        if key not in tuned:
+            pl.autotune()
+            tuned[key] = pl.params
+        else:
+            pl.params = tuned[key]
+    return tuned
+
+
+def _check(errs, g, dtype, tag):
+    print(tag, dtype, "errors u, v, w, p:", errs, flush=True)
+    if dtype == "f64":
+        assert max(errs[:3]) <= TOL64, (tag, errs)
+        assert errs[3] <= p_tolerance(g), (tag, errs, p_tolerance(g))
+    else:
+        assert max(errs) <= TOL_MIXED, (tag, errs)
+
+
+SEEDS = {"256x256x128": 7101, "1024x1024x256": 7102, "2048x2048x160": 7103}
+
+
+@pytest.mark.parametrize("dtype", ["f64", "mixed"])
+@pytest.mark.parametrize("name", ["256x256x128", "1024x1024x256", "2048x2048x160"])
+def test_full_size_manufactured(name, dtype):
+    g = synth.make_grid(name)
+    print(f"case {name} {dtype}: build", flush=True)
+    mf = Manufactured(g, seed=SEEDS[name])
+    u, v, w = mf.inputs()
+    scale = max(float(u.abs().max()), float(v.abs().max()), float(w.abs().max()))
+    plan = monc.Plan.from_grid(g, dtype)
+    print(f"case {name} {dtype}: autotune", flush=True)
+    tuned = _tune([plan])
+    if dtype == "mixed":
+        u, v, w = u.float(), v.float(), w.float()
+    p = torch.empty_like(u)
+    print(f"case {name} {dtype}: project with {tuned}", flush=True)
+    plan.project(u, v, w, p)
+    torch.cuda.synchronize()
+    assert float(w[-1].abs().max()) == 0.0
+    _check(mf.errors(u, v, w, p, scale), g, dtype, name)
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "mixed"])
+def test_full_ensemble_batched_manufactured(dtype):
+    members = synth.ensemble_members(48)
+    print(f"case ensemble48 {dtype}: build", flush=True)
+    mfs = [Manufactured(g, seed=4001 + mi, m0=1 + mi % 5, n0=mi % 3) for mi, (g, _) in enumerate(members)]
+    plans = [monc.Plan.from_grid(mf.g, dtype) for mf in mfs]
+    print(f"case ensemble48 {dtype}: autotune", flush=True)
+    _tune(plans)
+    fields, scales = [], []
+    for mf in mfs:
+        u, v, w = mf.inputs()
+        scales.append(max(float(u.abs().max()), float(v.abs().max()), float(w.abs().max())))
+        if dtype == "mixed":
+            u, v, w = u.float(), v.float(), w.float()
+        fields.append([u, v, w, torch.empty_like(u)])
+    print(f"case ensemble48 {dtype}: project_batched", flush=True)
+    monc.project_batched(plans, *[[f[t] for f in fields] for t in range(4)])
+    torch.cuda.synchronize()
+    for mi, (mf, f, s) in enumerate(zip(mfs, fields, scales)):
+        assert float(f[2][-1].abs().max()) == 0.0
+        _check(mf.errors(*f, s), mf.g, dtype, f"member {mi} {mf.g.nx}x{mf.g.ny}x{mf.g.nz}")
+    for pl in plans:
+        pl.close()

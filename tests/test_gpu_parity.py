@@ -18,6 +18,7 @@ import pytest
 import oracle
 import synth
 from tests.helpers import relerr
+from tests.tolerances import TOL64, TOL_MIXED, p_tolerance, worst_column_condition  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 
@@ -25,8 +26,6 @@ torch = pytest.importorskip("torch")
 import paper_2009_12849_amd as monc  # noqa: E402
 
 DEV = "cuda:0"
-TOL64 = 1e-12
-TOL_MIXED = 1e-6
 
 
 def to_dev(a, dtype):
@@ -41,30 +40,6 @@ def run_gpu(g, u, v, w, dtype="f64", plan=None):
     plan.project(tu, tv, tw, tp)
     torch.cuda.synchronize()
     return [t.cpu().numpy().astype(np.float64) for t in (tu, tv, tw, tp)]
-
-
-def worst_column_condition(g):
-    """kappa_inf of the worst-conditioned column system: the tridiagonal of
-    the smallest nonzero horizontal eigenvalue, or the (0,0) column's system
-    with the top unknown pinned (rows 0..nz-2)."""
-    a, c = oracle.tridiag_coefficients(g.dz, g.rho0)
-    cond = lambda T: float(np.linalg.norm(T, np.inf) * np.linalg.norm(np.linalg.inv(T), np.inf))
-    kappa = 1.0
-    if g.nz > 1:
-        m = g.nz - 1
-        T0 = np.diag(-(a[:m] + c[:m])) + np.diag(a[1:m], -1) + np.diag(c[:m - 1], 1)
-        kappa = cond(T0)
-    lamx, lamy = oracle.modified_wavenumbers(g.nx, g.ny, g.dx, g.dy)
-    lam = (lamy[:, None] + lamx[None, :]).ravel()
-    lam = lam[lam > 0]
-    if lam.size:
-        T = np.diag(-(a + c) - g.rho0 * lam.min()) + np.diag(a[1:], -1) + np.diag(c[:-1], 1)
-        kappa = max(kappa, cond(T))
-    return kappa
-
-
-def p_tolerance(g):
-    return max(TOL64, 4 * 2.0 ** -53 * worst_column_condition(g))
 
 
 def field_errors(out, ref, u, v, w):
