@@ -36,7 +36,7 @@ sys.path.insert(0, ROOT)
 METRIC = "grid-points/s full projection (mixed vs FP64 GPU) at rel err ≤1e-6, %HBM roofline"
 HBM_PEAK_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_2009_12849_amd", "csrc", "kernels.hip")
-WORKLOADS = ["256x256x128", "1024x1024x256", "ensemble48", "2048x2048x160"]
+WORKLOADS = ["256x256x128", "1024x1024x256", "ensemble48", "2048x2048x160", "4096x4096x64"]
 KERNELS = ["div_fftx", "ffty_fwd", "tridiag", "ffty_inv", "ifftx", "grad", "resid_fftx", "grad_final"]
 
 
@@ -302,6 +302,8 @@ def main():
         "ensemble48": f"batched ensemble of {len(members)} uneven grids (64^2x64..256^2x128), one graph launch, mixed",
         "2048x2048x160": f"mixed projection {g.nx}x{g.ny}x{g.nz}, dz=5*20^(k/159) m, rho0=1.2exp(-z/8 km), "
               f"k^-5/3 horizontal spectra",
+        "4096x4096x64": f"mixed projection {g.nx}x{g.ny}x{g.nz} (the paper's 1.07e9-point global problem on one "
+              f"GPU), dz=min(10*1.015^k,60) m, rho0=1.2exp(-z/8 km)",
     }[args.workload]
 
     copy_gbps = device_copy_gbps(torch)

@@ -84,6 +84,8 @@ CONFIGS = {
     "1024x1024x256": "mixed (FP32 storage), 1024x1024x256, the 256x256x128 vertical profiles and field recipe",
     "ensemble48": "mixed, 48-member ensemble of uneven grids, per-member dz stretch and rho0 scale height",
     "2048x2048x160": "mixed, 2048x2048x160, dz=5*20^(k/159) m, rho0=1.2exp(-z/8 km), k^-5/3 horizontal spectra",
+    "4096x4096x64": "mixed, 4096x4096x64 (the paper's 1.07e9-point global problem on one GPU), "
+                    "dx=dy=25 m, dz=min(10*1.015^k,60) m, rho0=1.2exp(-z/8 km), the 256x256x128 field recipe",
 }
 
 
@@ -115,6 +117,9 @@ def make_grid(name: str) -> Grid:
     if name == "2048x2048x160":
         dz = 5.0 * 20.0 ** (np.arange(160, dtype=np.float64) / 159.0)
         return Grid(2048, 2048, 160, 25.0, 25.0, dz, exp_rho0(dz))
+    if name == "4096x4096x64":
+        dz = capped_geometric_dz(64)
+        return Grid(4096, 4096, 64, 25.0, 25.0, dz, exp_rho0(dz))
     raise KeyError(name)
 
 
@@ -234,7 +239,8 @@ def make_workload(name: str, members: Optional[int] = None) -> Workload:
             mem.append(Member(g, *mode_fields(rng, g)))
         return Workload(name, "mixed", mem, CONFIGS[name])
     g = make_grid(name)
-    seed = {"32x32x32": 1000, "256x256x128": 2000, "1024x1024x256": 3000, "2048x2048x160": 5000}[name]
+    seed = {"32x32x32": 1000, "256x256x128": 2000, "1024x1024x256": 3000, "2048x2048x160": 5000,
+            "4096x4096x64": 6000}[name]
     rng = np.random.default_rng(seed)
     if name == "32x32x32":
         fields = _small_fields(rng, g)

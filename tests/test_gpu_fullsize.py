@@ -1,5 +1,6 @@
 """Full-size parity in the launch configuration the benchmark times: the
-256^2 x 128, 1024^2 x 256 and 2048^2 x 160 grids and the 48-member ensemble,
+256^2 x 128, 1024^2 x 256 and 2048^2 x 160 grids, the 48-member ensemble and
+the paper-scale 4096^2 x 64 grid (1.07e9 points),
 with tile parameters picked by the library's autotuner once per distinct grid,
 as bench.py does.
 
@@ -108,11 +109,11 @@ def _check(errs, g, dtype, tag):
         assert max(errs) <= TOL_MIXED, (tag, errs)
 
 
-SEEDS = {"256x256x128": 7101, "1024x1024x256": 7102, "2048x2048x160": 7103}
+SEEDS = {"256x256x128": 7101, "1024x1024x256": 7102, "2048x2048x160": 7103, "4096x4096x64": 7104}
 
 
 @pytest.mark.parametrize("dtype", ["f64", "mixed"])
-@pytest.mark.parametrize("name", ["256x256x128", "1024x1024x256", "2048x2048x160"])
+@pytest.mark.parametrize("name", ["256x256x128", "1024x1024x256", "2048x2048x160", "4096x4096x64"])
 def test_full_size_manufactured(name, dtype):
     g = synth.make_grid(name)
     print(f"case {name} {dtype}: build", flush=True)
