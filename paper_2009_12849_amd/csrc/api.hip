@@ -524,7 +524,7 @@ static Shape member_shape(const MemberDesc& d, Phase ph, bool fp64) {
   } else if (ph == PH_TRI) {
     s.variant = d.tris;
     s.block = d.tricw * d.triP;
-    s.lds = (size_t)d.tricw * (d.triP * tri_chunk_slots(d.tris) + 1) * 16;  // matches the kernel's column stride
+    s.lds = (size_t)d.tricw * (d.triP * tri_lane_slots(d.tris, !fp64) + 1) * 16;  // matches the kernel's column stride
     s.blocks = ((long long)d.ny * d.nxp + d.tricw - 1) / d.tricw;  // over the padded plane
   } else {
     // points per thread: 16-byte field accesses on the mixed path (4 floats),

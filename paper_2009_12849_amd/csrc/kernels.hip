@@ -907,7 +907,10 @@ template <typename TS, int S, bool SING>
 __device__ __forceinline__ void tri_tile(const MemberDesc& d, const IoPtrs& io, int lb, double2* stage) {
   const int P = d.triP, CW = d.tricw, nz = d.nz, nxh = d.nxh, nxp = d.nxp;
   const int lp = __builtin_ctz(P), lcw = __builtin_ctz(CW);  // both powers of two
-  constexpr int SP = tri_chunk_slots(S);     // padded chunk length in LDS
+  constexpr bool F32 = sizeof(TS) == 4;      // FP32 storage: rows staged as FP32
+  constexpr int SP = tri_lane_slots(S, F32); // padded chunk length in LDS (16-byte slots)
+  // slot of the parked right-hand side of row r (1 <= r <= S-2)
+  constexpr int PK0 = F32 ? 1 : 0;
   const int lrow = P * SP + 1;               // odd stride: columns start in different banks
   // columns run linearly over the padded level plane in memory order (offset
   // x inside a level holds column (n, m) = spec_nm(x)), so a tile is one
@@ -968,7 +971,10 @@ __device__ __forceinline__ void tri_tile(const MemberDesc& d, const IoPtrs& io, 
 #pragma unroll
   for (int j = 0; j < S; ++j) {
     const bool in = sok && ks + j < nz;  // every slot exists; rows >= nz are never read
-    sst[j] = make_double2(in ? (double)ld[j].x : 0.0, in ? (double)ld[j].y : 0.0);
+    if constexpr (F32)
+      reinterpret_cast<float2*>(sst)[j] = in ? make_float2(ld[j].x, ld[j].y) : make_float2(0.0f, 0.0f);
+    else
+      sst[j] = make_double2(in ? (double)ld[j].x : 0.0, in ? (double)ld[j].y : 0.0);
   }
   // padding columns (m >= nxh) solve a well-conditioned dummy system with a
   // zero right-hand side and are never stored
@@ -989,7 +995,15 @@ __device__ __forceinline__ void tri_tile(const MemberDesc& d, const IoPtrs& io, 
   // staged data: zero for rows >= nz and for padding columns
   double2 D[S];
 #pragma unroll
-  for (int r = 0; r < S; ++r) D[r] = scol[q * SP + r];
+  for (int r = 0; r < S; ++r) {
+    if constexpr (F32) {
+      const float2 t = reinterpret_cast<const float2*>(scol + q * SP)[r];
+      D[r] = make_double2(t.x, t.y);
+    } else {
+      D[r] = scol[q * SP + r];
+    }
+  }
+  asm volatile("" ::: "memory");  // the slots are reused as FP64 below
   // (0,0) column (one per member, lanes of one wave): remove the dz-weighted
   // mean of the right-hand side, then pin the top row (identity, rhs 0)
   if (singular) {
@@ -1050,7 +1064,7 @@ __device__ __forceinline__ void tri_tile(const MemberDesc& d, const IoPtrs& io, 
   // park e_r in the lane's own LDS slots (their right-hand sides are
   // consumed) while the interface system is solved: fewer live registers
 #pragma unroll
-  for (int r = 1; r < S - 1; ++r) scol[q * SP + r] = de[r];
+  for (int r = 1; r < S - 1; ++r) scol[q * SP + r - PK0] = de[r];
   asm volatile("" ::: "memory");
 
   // 2. substitute L_{q-1} (from lane q-1) and L_q into the F_q row
@@ -1117,7 +1131,7 @@ __device__ __forceinline__ void tri_tile(const MemberDesc& d, const IoPtrs& io, 
     if (r == 0) X[r] = F;
     else if (r == S - 1) X[r] = L;
     else {
-      const double2 e = scol[q * SP + r];
+      const double2 e = scol[q * SP + r - PK0];
       X[r] = make_double2(e.x - al[r] * F.x - ga[r] * L.x, e.y - al[r] * F.y - ga[r] * L.y);
     }
   }
@@ -1137,25 +1151,49 @@ __device__ __forceinline__ void tri_tile(const MemberDesc& d, const IoPtrs& io, 
       X[r].y -= sum.y * d.rH;
     }
   }
+  // the solution back into the chunk (rows >= nz are never stored); FP32
+  // storage writes it scaled by 1/(nx ny) and rounded, over the parked values
+  asm volatile("" ::: "memory");
+  if constexpr (F32) {
+    const double sc = d.inv_nxny;
+    float2* out = reinterpret_cast<float2*>(scol + q * SP);
 #pragma unroll
-  for (int r = 0; r < S; ++r) scol[q * SP + r] = X[r];  // rows >= nz are never stored
+    for (int r = 0; r < S; ++r) out[r] = make_float2((float)(X[r].x * sc), (float)(X[r].y * sc));
+  } else {
+#pragma unroll
+    for (int r = 0; r < S; ++r) scol[q * SP + r] = X[r];
+  }
   __syncthreads();
 
   // coalesced store (the staging thread's rows), scaled by 1/(nx ny)
   if (sok) {
-    const double sc = d.inv_nxny;
     CS* dst = Sg + scol_g + (long long)ks * plane;
-    double2 x[S];
+    if constexpr (F32) {
+      float2 x[S];
 #pragma unroll
-    for (int j = 0; j < S; ++j) x[j] = sst[j];
+      for (int j = 0; j < S; ++j) x[j] = reinterpret_cast<const float2*>(sst)[j];
 #pragma unroll
-    for (int j = 0; j < S; ++j)
-      if (ks + j < nz) dst[j * plane] = CS{(TS)(x[j].x * sc), (TS)(x[j].y * sc)};
+      for (int j = 0; j < S; ++j)
+        if (ks + j < nz) dst[j * plane] = CS{x[j].x, x[j].y};
+    } else {
+      const double sc = d.inv_nxny;
+      double2 x[S];
+#pragma unroll
+      for (int j = 0; j < S; ++j) x[j] = sst[j];
+#pragma unroll
+      for (int j = 0; j < S; ++j)
+        if (ks + j < nz) dst[j * plane] = CS{(TS)(x[j].x * sc), (TS)(x[j].y * sc)};
+    }
   }
 }
 
+// FP32 storage up to 10 rows per lane: a register budget for 4 waves per
+// SIMD (the LDS chunks then fit 4 such workgroups per CU); the solve is
+// latency-bound and gains more from the extra wave than it loses to a
+// 16-byte spill at 10 rows
 template <typename TS, int S, int MAXT>
-__global__ void __launch_bounds__(MAXT) k_tridiag(LaunchArgs a) {
+__global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(S <= 10 && sizeof(TS) == 4 ? 4 : 1, 8)))
+k_tridiag(LaunchArgs a) {
   extern __shared__ unsigned char smem_raw[];
   double2* stage = reinterpret_cast<double2*>(smem_raw);
   const int mi = find_member(a, blockIdx.x);

@@ -19,10 +19,14 @@ constexpr int kTriPmax = 64;            // lanes per column (one wave)
 constexpr int kBig = 1 << 30;           // "inactive" lane index
 constexpr int kGenericElems = 8;        // max elements per thread of the runtime-length FFT
 constexpr int kSpecBlockMax = 8;        // widest spectral column block (nxp is a multiple of it)
-// LDS slots (16 bytes each) per lane chunk of the tridiagonal solver: S rows
-// rounded up to an odd count, so the chunks of consecutive lanes start in
-// different bank groups
-constexpr int tri_chunk_slots(int s) { return s | 1; }
+// LDS slots (16 bytes each) per lane chunk of the tridiagonal solver, an odd
+// count so that the chunks of consecutive lanes start in different bank
+// groups. FP64 storage stages its S rows as FP64; FP32 storage keeps them as
+// FP32 (8 bytes a row) and parks the S-2 eliminated FP64 right-hand sides
+// over them, so the chunk holds the larger of the two.
+constexpr int tri_lane_slots(int s, bool f32) {
+  return f32 ? ((s + 1) / 2 > s - 2 ? (s + 1) / 2 : (s - 2 > 1 ? s - 2 : 1)) | 1 : s | 1;
+}
 // Threads per compile-time transform (shared by the kernels and the host's
 // launch shapes), and so the radix plan (16 elements per thread take radix-16
 // passes): along x sixteen elements each from length 512 on, eight below;
