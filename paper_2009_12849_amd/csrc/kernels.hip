@@ -252,6 +252,56 @@ __device__ __forceinline__ void div_vec(const MemberDesc& d, const RowCtx& c, co
   }
 }
 
+// Both rows of a pair (k, j) and (k, j+1) of one level: row j's v is row j+1's
+// southern neighbour, so 11 loads serve the two rows instead of 12. The
+// arithmetic is div_vec's, term for term.
+template <typename T>
+__device__ __forceinline__ void div_pair_vec(const MemberDesc& d, const RowCtx& c0, const RowCtx& c1,
+                                             const IoPtrs& io, int i0, T* out0, T* out1) {
+  constexpr int V = Vec<T>::n;
+  using vt = typename Vec<T>::type;
+  const T* __restrict__ u = reinterpret_cast<const T*>(io.u);
+  const T* __restrict__ v = reinterpret_cast<const T*>(io.v);
+  const T* __restrict__ w = reinterpret_cast<const T*>(io.w);
+  const bool f64 = sizeof(T) == 8;
+  const T rdx = f64 ? (T)d.rdx : (T)d.rdxf, rdy = f64 ? (T)d.rdy : (T)d.rdyf;
+  // one level: both rows share the vertical coefficients and lid flags
+  const T rho0 = f64 ? (T)c0.rho0 : (T)c0.rho0f, rdz = f64 ? (T)c0.rdz : (T)c0.rdzf;
+  const T rhow = f64 ? (T)c0.rhow : (T)c0.rhowf, rhowm = f64 ? (T)c0.rhowm : (T)c0.rhowmf;
+  const int iw = (i0 == 0) ? d.nx - 1 : i0 - 1;
+  const vt u0 = ldv(u + c0.off + i0), u1 = ldv(u + c1.off + i0);
+  const T um0 = u[c0.off + iw], um1 = u[c1.off + iw];
+  const vt vs = ldv(v + c0.soff + i0), v0 = ldv(v + c0.off + i0), v1 = ldv(v + c1.off + i0);
+  vt wc0 = (vt)(T)0, wb0 = (vt)(T)0, wc1 = (vt)(T)0, wb1 = (vt)(T)0;
+  if constexpr (sizeof(T) == 8) {
+    const long long bo = c0.bot ? c0.plane : 0;
+    const vt a0 = ldv(w + c0.off + i0), a1 = ldv(w + c1.off + i0);
+    const vt b0 = ldv(w + c0.off - bo + i0), b1 = ldv(w + c1.off - bo + i0);
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      wc0[e] = c0.top ? a0[e] : (T)0;
+      wc1[e] = c0.top ? a1[e] : (T)0;
+      wb0[e] = c0.bot ? b0[e] : (T)0;
+      wb1[e] = c0.bot ? b1[e] : (T)0;
+    }
+  } else {
+    if (c0.top) {
+      wc0 = ldv(w + c0.off + i0);
+      wc1 = ldv(w + c1.off + i0);
+    }
+    if (c0.bot) {
+      wb0 = ldv(w + c0.off - c0.plane + i0);
+      wb1 = ldv(w + c1.off - c0.plane + i0);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < V; ++e) {
+    const T uw0 = e ? u0[e - 1] : um0, uw1 = e ? u1[e - 1] : um1;
+    out0[e] = rho0 * ((u0[e] - uw0) * rdx + (v0[e] - vs[e]) * rdy) + (rhow * wc0[e] - rhowm * wb0[e]) * rdz;
+    out1[e] = rho0 * ((u1[e] - uw1) * rdx + (v1[e] - v0[e]) * rdy) + (rhow * wc1[e] - rhowm * wb1[e]) * rdz;
+  }
+}
+
 // FP64 residual D(u* - G p1) at points i0 .. i0+3 of a row (float data)
 typedef float f4v __attribute__((ext_vector_type(4)));
 
@@ -451,7 +501,10 @@ __global__ void __launch_bounds__(512) k_xfwd_ct(LaunchArgs a) {
   auto stencil = [&](int t) {
     const int i0 = (q + t * NT) * V;
     T s0[V], s1[V];
-    if constexpr (sizeof(T) == 8) {
+    if (MODE == 0 && !(d.ny & 1) && v1) {
+      // divergence of a full pair within one level (even ny): shared loads
+      div_pair_vec<T>(d, c0, c1, io, i0, s0, s1);
+    } else if constexpr (sizeof(T) == 8) {
       // FP64: both rows unconditionally (an invalid row's context points at
       // row 0), so all loads of the chunk issue together; invalid rows zeroed
       source_vec<T, MODE>(d, c0, io, i0, s0);
