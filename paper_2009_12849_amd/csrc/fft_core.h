@@ -210,13 +210,7 @@ constexpr int ct_threads_y(int n) { return ct_threads_y_n(n); }
 // LDS index of element i of an x-direction transform of length N (bank
 // rows permuted by XOR, or padded; see xlds_len)
 template <typename T, int N> __device__ __forceinline__ int xpad(int i) {
-  constexpr int cb = 2 * sizeof(T);
-  if constexpr (xsw_on(N, cb)) {
-    constexpr int B = xsw_bits(cb);
-    return i ^ ((i >> B) & ((1 << B) - 1));
-  } else {
-    return i + (i >> (cb == 16 ? kXpadShift64 : kXpadShift32));
-  }
+  return xlds_index(i, N, 2 * (int)sizeof(T));
 }
 
 // Compile-time Stockham transform. Thread q (0 <= q < NT) owns butterflies

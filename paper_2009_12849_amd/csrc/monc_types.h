@@ -51,6 +51,12 @@ constexpr bool xsw_on(int n, int cb) { return ct_threads_x_n(n) * 16 == n && n %
 constexpr int xlds_len(int n, int cb) {
   return xsw_on(n, cb) ? n : n + (n >> (cb == 16 ? kXpadShift64 : kXpadShift32)) + 1;
 }
+// LDS slot of element i of an x transform of length n (a bijection of
+// [0, n) into [0, xlds_len(n, cb)))
+constexpr int xlds_index(int i, int n, int cb) {
+  return xsw_on(n, cb) ? i ^ ((i >> xsw_bits(cb)) & ((1 << xsw_bits(cb)) - 1))
+                       : i + (i >> (cb == 16 ? kXpadShift64 : kXpadShift32));
+}
 
 struct FftPlan {
   int n;                  // transform length (2^a 3^b)

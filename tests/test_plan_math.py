@@ -20,6 +20,7 @@ DRIVER = r"""
 #include <cstdlib>
 #include <vector>
 #include "plan_math.h"
+#include "monc_types.h"
 using namespace monc;
 
 static unsigned fast_div(unsigned x, unsigned mul, int shift) {  // device formula, on the host
@@ -74,7 +75,26 @@ int main(int argc, char** argv) {
     if (ok) for (int p = 0; p < fp.npass; ++p) std::printf(" %d", fp.rad[p]);
     std::printf("\n");
   }
-  // 3. tables from dz, rho0 on stdin
+  // 3. LDS layouts shared by the kernels and the host
+  for (int s = 2; s <= kTriSmax; ++s)
+    std::printf("tri %d %d %d\n", s, tri_lane_slots(s, true), tri_lane_slots(s, false));
+  for (int n = 16; n <= 4096; ++n) {
+    int r = n;
+    while (r % 2 == 0) r /= 2;
+    while (r % 3 == 0) r /= 3;
+    if (r != 1) continue;
+    for (int cb = 8; cb <= 16; cb += 8) {
+      const int len = xlds_len(n, cb);
+      std::vector<int> seen(len, 0);
+      int bad = 0;
+      for (int i = 0; i < n; ++i) {
+        const int j = xlds_index(i, n, cb);
+        if (j < 0 || j >= len || seen[j]++) ++bad;
+      }
+      std::printf("xlds %d %d %d %d %d\n", n, cb, len, xsw_on(n, cb) ? 1 : 0, bad);
+    }
+  }
+  // 4. tables from dz, rho0 on stdin
   int nz; std::scanf("%d", &nz);
   std::vector<double> dz(nz), rho(nz);
   for (int k = 0; k < nz; ++k) std::scanf("%lf", &dz[k]);
@@ -138,6 +158,33 @@ def _prime_factors(n):
     if n > 1:
         out.append(n)
     return out
+
+
+def test_tridiagonal_lds_chunks(driver):
+    """A lane's LDS chunk (16-byte slots, an odd count) holds its S rows in the
+    storage precision, and with FP32 storage also the S-2 parked FP64
+    right-hand sides that go over them."""
+    _, lines = driver
+    rows = [tuple(map(int, l.split()[1:])) for l in lines if l.startswith("tri ")]
+    assert len(rows) == 15
+    for s, f32, f64 in rows:
+        assert f32 % 2 == 1 and f64 % 2 == 1, (s, f32, f64)
+        assert 16 * f32 >= 8 * s and 16 * f32 >= 16 * (s - 2), (s, f32)
+        assert 16 * f64 >= 16 * s, (s, f64)
+        assert f32 <= f64
+
+
+def test_x_transform_lds_index_is_a_bijection(driver):
+    """Every compile-time x length: the LDS index map (XOR-permuted bank rows
+    for radix-16 transforms, padding otherwise) is one-to-one into the
+    buffer the host sizes, in both precisions."""
+    _, lines = driver
+    rows = [tuple(map(int, l.split()[1:])) for l in lines if l.startswith("xlds ")]
+    assert len(rows) > 40
+    for n, cb, length, sw, bad in rows:
+        assert bad == 0, (n, cb)
+        assert length == n if sw else length > n, (n, cb, length)
+    assert any(r[3] for r in rows) and not all(r[3] for r in rows)
 
 
 def test_vertical_tables_match_oracle(driver):
