@@ -131,6 +131,7 @@ class Runner:
             self.fields.append(f)
         self.batched = len(members) > 1
         self.points = sum(m.grid.points for m in members)
+        self.stats = None   # per-level reductions buffer (single grids), when timed with them
 
     def step(self, stream=None):
         if self.batched:
@@ -138,7 +139,7 @@ class Runner:
             self.monc.project_batched(self.plans, [x[0] for x in f], [x[1] for x in f], [x[2] for x in f],
                                       [x[3] for x in f], stream)
         else:
-            self.plans[0].project(*self.fields[0], stream)
+            self.plans[0].project(*self.fields[0], stream, stats=self.stats)
 
     def breakdown(self, steps):
         """Average ms per launch of every kernel (HIP events per launch)."""
@@ -314,6 +315,15 @@ def main():
     first = ([[t.cpu().numpy().astype(np.float64) for t in f] for f in runner.fields[:nchk]]
              if not args.no_cpu else None)
     res = measure(runner, args.steps, args.warmup, args.workload, None)
+    reductions = None
+    if not runner.batched:
+        # the same projections with the per-level horizontal reductions fused in
+        runner.stats = torch.empty(8 * runner.plans[0].nz, dtype=torch.float64, device="cuda:0")
+        wall_r, _ = runner.timed(args.steps, args.warmup)
+        runner.stats = None
+        ms_r = 1e3 * wall_r / args.steps
+        reductions = {"ms_per_step": ms_r, "overhead_frac": ms_r / res["ms_per_step"] - 1.0,
+                      "what": "per-level horizontal mean and max of u, v, w, p (monc_project_reduce)"}
     result = {
         "metric": METRIC,
         "value": res["value"],
@@ -333,6 +343,7 @@ def main():
         "roofline": res["roofline"],
         "path": res["path"],
         "device_copy_GBps": copy_gbps,
+        "with_reductions": reductions,
     }
     if not args.no_other:
         del runner

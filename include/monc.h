@@ -114,6 +114,23 @@ int monc_project_batched(monc_plan* const* plans, int count,
                          void* const* u, void* const* v, void* const* w,
                          void* const* p, void* stream);
 
+/*
+ * monc_project plus per-level horizontal reductions of its outputs, the
+ * diagnostic an I/O server takes of a prognostic field (Sec. 3 of the paper:
+ * the server's "horizontal reduction" actions), folded into the
+ * pressure-gradient kernel so that the fields are not read again.
+ * stats: device array of 8*nz doubles (caller-owned, 8-byte aligned, not
+ * overlapping the fields); on completion stats[(2f + s)*nz + k] holds, for
+ * field f = 0..3 (u, v, w after the projection, p) and statistic s = 0 (mean)
+ * or 1 (max), that statistic over the nx*ny points of level k. p is the
+ * pressure the velocities were corrected with: the output p on the FP64
+ * path, p1 + delta in FP64 on the mixed path (whose stored p is its FP32
+ * rounding). Means are accumulated with device-wide atomics, so their last
+ * bits can differ between runs; maxima are exact. Otherwise as monc_project.
+ * Returns MONC_OK, MONC_EINVAL or MONC_EHIP.
+ */
+int monc_project_reduce(monc_plan* plan, void* u, void* v, void* w, void* p, double* stats, void* stream);
+
 /* Message of the last failure on the calling thread ("" if none). */
 const char* monc_last_error(void);
 

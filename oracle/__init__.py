@@ -20,3 +20,4 @@ from .projection import (  # noqa: F401
     project,
     weighted_energy,
 )
+from .reductions import level_stats  # noqa: F401

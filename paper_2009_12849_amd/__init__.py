@@ -54,6 +54,8 @@ def lib() -> ctypes.CDLL:
     L.monc_plan_destroy.argtypes = [vp]
     L.monc_project.restype = ip
     L.monc_project.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.monc_project_reduce.restype = ip
+    L.monc_project_reduce.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.monc_project_batched.restype = ip
     L.monc_project_batched.argtypes = [ctypes.POINTER(vp), ip] + [ctypes.POINTER(vp)] * 4 + [vp]
     L.monc_last_error.restype = ctypes.c_char_p
@@ -155,10 +157,21 @@ class Plan:
             raise ValueError(f"{name} must have shape (nz, ny, nx) = {(self.nz, self.ny, self.nx)}")
         return ctypes.c_void_p(t.data_ptr())
 
-    def project(self, u, v, w, p, stream=None):
-        """In-place projection of u, v, w; p receives the pressure."""
+    def project(self, u, v, w, p, stream=None, stats=None):
+        """In-place projection of u, v, w; p receives the pressure. With
+        `stats` (a float64 device tensor of 8*nz values), also the per-level
+        horizontal mean and max of u, v, w, p: stats.view(4, 2, nz)[f, s, k]
+        (see monc_project_reduce)."""
         args = [self._field(t, n) for t, n in ((u, "u"), (v, "v"), (w, "w"), (p, "p"))]
-        _check(lib().monc_project(self._h, *args, ctypes.c_void_p(_stream_handle(stream))))
+        st = ctypes.c_void_p(_stream_handle(stream))
+        if stats is None:
+            _check(lib().monc_project(self._h, *args, st))
+            return
+        import torch
+        if stats.dtype != torch.float64 or not stats.is_cuda or stats.numel() != 8 * self.nz \
+                or not stats.is_contiguous():
+            raise ValueError(f"stats must be a contiguous float64 device tensor of {8 * self.nz} values")
+        _check(lib().monc_project_reduce(self._h, *args, ctypes.c_void_p(stats.data_ptr()), st))
 
     # -- introspection / stages / profiling / tuning ---------------------
     def spectral_layout(self):

@@ -21,6 +21,9 @@ SOURCES = ["kernels.hip", "api.hip", "plan_math.cpp"]
 # No packed FP32 instructions (v_pk_*_f32) in any HIP object.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             # FP atomics as the hardware instructions (the library's atomics
+             # only touch its callers' hipMalloc'd device buffers)
+             "-munsafe-fp-atomics",
              "-Wno-unused-result"]
 
 

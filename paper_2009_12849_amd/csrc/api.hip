@@ -580,8 +580,18 @@ static int launch_one(const Group& g, const std::vector<int>& idx, Phase ph, con
     case PH_TRI: launch_tridiag(a, grid, block, lds, g.fp64, v, stream); break;
     case PH_XINV: launch_xinv(a, grid, block, lds, g.fp64, 0, v, stream); break;
     case PH_XINV_CORR: launch_xinv(a, grid, block, lds, false, 1, v, stream); break;
-    case PH_GRAD: launch_grad(a, grid, g.fp64, v, stream); break;
-    case PH_GRAD_MIXED: launch_grad(a, grid, false, v, stream); break;
+    case PH_GRAD:
+    case PH_GRAD_MIXED: {
+      // per-level reductions of the outputs when the caller asked for them
+      bool red = false;
+      for (size_t t = 0; t < idx.size(); ++t)
+        if (a.io[t].stats) {
+          launch_stats_init(a.io[t].stats, g.mem[idx[t]].h->nz, stream);
+          red = true;
+        }
+      launch_grad(a, grid, ph == PH_GRAD && g.fp64, v, red, stream);
+      break;
+    }
   }
   hipError_t le = hipGetLastError();
   if (timed) {
@@ -674,6 +684,32 @@ extern "C" int monc_project(monc_plan* pl, void* u, void* v, void* w, void* p, v
   Group g;
   g.fp64 = pl->dtype == MONC_FP64;
   g.mem.push_back({&pl->h, pl->d_desc, IoPtrs{u, v, w, p, pl->d_spec}});
+  std::vector<Group> groups{g};
+  return run_phases(groups, full_sequence(g.fp64), stream, pl->prof.mask ? &pl->prof : nullptr);
+}
+
+extern "C" int monc_project_reduce(monc_plan* pl, void* u, void* v, void* w, void* p, double* stats,
+                                   void* stream) {
+  if (!pl) return fail(MONC_EINVAL, "plan is null");
+  if (!stats || reinterpret_cast<uintptr_t>(stats) % 8 != 0) return fail(MONC_EINVAL, "stats is null or misaligned");
+  void* ptrs[4] = {u, v, w, p};
+  int rc = check_fields(pl, ptrs, 4, "monc_project_reduce");
+  if (rc != MONC_OK) return rc;
+  {
+    const uintptr_t s0 = reinterpret_cast<uintptr_t>(stats), s1 = s0 + 8 * sizeof(double) * pl->nz;
+    const size_t bytes = (size_t)pl->nx * pl->ny * pl->nz * elem_bytes(pl->dtype);
+    for (int i = 0; i < 4; ++i) {
+      const uintptr_t a = reinterpret_cast<uintptr_t>(ptrs[i]);
+      if (a < s1 && s0 < a + bytes) return fail(MONC_EINVAL, "monc_project_reduce: stats overlaps array %d", i);
+    }
+  }
+  rc = check_device(pl);
+  if (rc != MONC_OK) return rc;
+  Group g;
+  g.fp64 = pl->dtype == MONC_FP64;
+  IoPtrs io{u, v, w, p, pl->d_spec};
+  io.stats = stats;
+  g.mem.push_back({&pl->h, pl->d_desc, io});
   std::vector<Group> groups{g};
   return run_phases(groups, full_sequence(g.fp64), stream, pl->prof.mask ? &pl->prof : nullptr);
 }

@@ -31,6 +31,9 @@ void launch_xinv(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64
 // fp64: pressure from io.p (FP64); else (mixed path) p1 + delta from the
 // float pair io.p + MemberDesc::prem. vec: points per thread (2 needs an even
 // nx, 4 a multiple of 4; else 1)
-void launch_grad(const LaunchArgs& a, int grid, bool fp64, int vec, void* stream);
+// red: also the per-level horizontal mean and max of u, v, w, p into io.stats
+// (after launch_stats_init on the same stream)
+void launch_grad(const LaunchArgs& a, int grid, bool fp64, int vec, bool red, void* stream);
+void launch_stats_init(double* stats, int nz, void* stream);
 
 }  // namespace monc

@@ -1266,7 +1266,66 @@ k_tridiag(LaunchArgs a) {
 // fields are T. A thread owns VEC consecutive points of one row of one
 // level (vector loads and stores need nx % VEC == 0); w[nz-1] = 0.
 // ---------------------------------------------------------------------------
-template <typename T, int VEC>
+// Per-level horizontal reductions of the projection's outputs (the
+// diagnostics an I/O server takes of a prognostic field, Sec. 3): stats[(2 f
+// + s) nz + k] for field f = u, v, w, p and statistic s = mean, max over the
+// nx ny points of level k. p is the pressure the velocities were corrected
+// with (p1 + delta in FP64 on the mixed path). The gradient kernel folds them
+// in: each workgroup reduces its points and adds one partial per statistic
+// with a device-wide atomic, so the accumulation order (and the last bits of
+// the means) can vary from run to run.
+__global__ void __launch_bounds__(256) k_stats_init(double* stats, int nz) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < 8 * nz) stats[t] = ((t / nz) & 1) ? -__builtin_inf() : 0.0;
+}
+
+// st[0..3]: sums of u, v, w, p over the caller's points, st[4..7]: maxima;
+// added into level k's statistics (sums scaled by rh = 1/(nx ny)) with the
+// hardware FP64 atomic add and max (the buffer is device memory)
+__device__ __forceinline__ void stats_commit(double* stats, int nz, int k, const double* st, double rh) {
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    __hip_atomic_fetch_add(stats + (2 * f) * nz + k, st[f] * rh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_max(stats + (2 * f + 1) * nz + k, st[4 + f], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Workgroup reduction of the statistics (`whole`: every point of the
+// workgroup is in level k), else one partial per thread.
+__device__ __forceinline__ void stats_reduce(double* stats, int nz, int k, double* st, double rh, bool whole,
+                                             bool live) {
+  if (!whole) {
+    if (live) stats_commit(stats, nz, k, st, rh);
+    return;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      st[f] += __shfl_xor(st[f], o);
+      st[4 + f] = fmax(st[4 + f], __shfl_xor(st[4 + f], o));
+    }
+  }
+  __shared__ double part[16][8];  // one row per wave (blockDim <= 1024)
+  const int wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int f = 0; f < 8; ++f) part[wv][f] = st[f];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < nw; ++i) {
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        st[f] += part[i][f];
+        st[4 + f] = fmax(st[4 + f], part[i][4 + f]);
+      }
+    }
+    stats_commit(stats, nz, k, st, rh);
+  }
+}
+
+template <typename T, int VEC, bool RED>
 __global__ void __launch_bounds__(256) k_grad(LaunchArgs a) {
   typedef T tv __attribute__((ext_vector_type(VEC)));
   typedef double dv __attribute__((ext_vector_type(VEC)));
@@ -1285,8 +1344,12 @@ __global__ void __launch_bounds__(256) k_grad(LaunchArgs a) {
     const long long row = tiled_index(lb / bpr, d.ny, d.nz, d.ptk, 8);
     blk = row * bpr + lb % bpr;
   }
-  const long long g = (blk * blockDim.x + threadIdx.x) * VEC;  // first point
-  if (g >= nh * nz) return;
+  const long long g0 = (blk * blockDim.x + threadIdx.x) * VEC;  // first point
+  const bool live = g0 < nh * nz;
+  if (!RED && !live) return;
+  // with the reductions every thread reaches the workgroup reduction: one
+  // past the grid reads point 0, stores nothing and contributes nothing
+  const long long g = live ? g0 : 0;
   const int k = (int)(g / nh);
   const long long h = g - (long long)k * nh;
   const int j = (int)(h / nx), i = (int)(h - (long long)j * nx);
@@ -1337,9 +1400,34 @@ __global__ void __launch_bounds__(256) k_grad(LaunchArgs a) {
     vv[e] = (T)((double)vv[e] - (pn[e] - pc[e]) * rdy);
     ww[e] = top ? (T)0 : (T)((double)ww[e] - (pu[e] - pc[e]) * rz);
   }
-  *reinterpret_cast<tv*>(u + g) = uu;
-  *reinterpret_cast<tv*>(v + g) = vv;
-  *reinterpret_cast<tv*>(w + g) = ww;
+  if (live) {
+    *reinterpret_cast<tv*>(u + g) = uu;
+    *reinterpret_cast<tv*>(v + g) = vv;
+    *reinterpret_cast<tv*>(w + g) = ww;
+  }
+  if constexpr (RED) {
+    double st[8];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      st[f] = 0.0;
+      st[4 + f] = -__builtin_inf();
+    }
+    if (live) {
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        const double x[4] = {(double)uu[e], (double)vv[e], (double)ww[e], pc[e]};
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          st[f] += x[f];
+          st[4 + f] = fmax(st[4 + f], x[f]);
+        }
+      }
+    }
+    // a workgroup whose points lie in one level reduces them first
+    const long long gb = blk * blockDim.x * VEC;
+    const long long gl = min(gb + (long long)blockDim.x * VEC, nh * nz) - 1;
+    stats_reduce(io.stats, nz, k, st, 1.0 / (double)nh, gb / nh == gl / nh, live);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1477,19 +1565,29 @@ void launch_tridiag(const LaunchArgs& a, int grid, int block, size_t lds, bool f
   }
 }
 
-void launch_grad(const LaunchArgs& a, int grid, bool fp64, int vec, void* stream) {
+void launch_grad(const LaunchArgs& a, int grid, bool fp64, int vec, bool red, void* stream) {
   const dim3 g(grid), b(256);
   hipStream_t st = (hipStream_t)stream;
-  if (vec == 4) {
-    if (fp64) hipLaunchKernelGGL((k_grad<double, 4>), g, b, 0, st, a);
-    else hipLaunchKernelGGL((k_grad<float, 4>), g, b, 0, st, a);
-  } else if (vec == 2) {
-    if (fp64) hipLaunchKernelGGL((k_grad<double, 2>), g, b, 0, st, a);
-    else hipLaunchKernelGGL((k_grad<float, 2>), g, b, 0, st, a);
-  } else {
-    if (fp64) hipLaunchKernelGGL((k_grad<double, 1>), g, b, 0, st, a);
-    else hipLaunchKernelGGL((k_grad<float, 1>), g, b, 0, st, a);
+#define MONC_GRAD(V)                                                                       \
+  if (red) {                                                                               \
+    if (fp64) hipLaunchKernelGGL((k_grad<double, V, true>), g, b, 0, st, a);               \
+    else hipLaunchKernelGGL((k_grad<float, V, true>), g, b, 0, st, a);                     \
+  } else {                                                                                 \
+    if (fp64) hipLaunchKernelGGL((k_grad<double, V, false>), g, b, 0, st, a);              \
+    else hipLaunchKernelGGL((k_grad<float, V, false>), g, b, 0, st, a);                    \
   }
+  if (vec == 4) {
+    MONC_GRAD(4)
+  } else if (vec == 2) {
+    MONC_GRAD(2)
+  } else {
+    MONC_GRAD(1)
+  }
+#undef MONC_GRAD
+}
+
+void launch_stats_init(double* stats, int nz, void* stream) {
+  hipLaunchKernelGGL(k_stats_init, dim3((8 * nz + 255) / 256), dim3(256), 0, (hipStream_t)stream, stats, nz);
 }
 
 }  // namespace monc

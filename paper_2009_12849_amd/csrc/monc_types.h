@@ -126,6 +126,7 @@ struct IoPtrs {
   void* w;
   void* p;
   void* spec;             // spectral buffer used by this launch
+  double* stats;          // per-level horizontal mean and max of u, v, w, p, or null
 };
 
 struct LaunchArgs {

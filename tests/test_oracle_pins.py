@@ -422,3 +422,27 @@ def test_pins_catch_planted_mistake(mutant, monkeypatch):
     monkeypatch.setattr(op, name, fn)
     worst = max(brute_error(6, 4, 5, seed=1), brute_error(5, 3, 4, seed=2))
     assert worst > 1e-6, f"planted mistake {mutant} went unnoticed ({worst})"
+
+
+def test_level_stats_closed_form():
+    """Per-level reductions on fields with known per-level mean and maximum:
+    a level constant plus a periodic mode whose horizontal mean is zero and
+    whose maximum over the grid is attained (cos at i = j = 0)."""
+    nz, ny, nx = 5, 6, 8
+    k = np.arange(nz, dtype=np.float64)[:, None, None]
+    i = np.arange(nx)[None, None, :]
+    j = np.arange(ny)[None, :, None]
+    mode = np.cos(2 * np.pi * i / nx) * np.cos(2 * np.pi * j / ny)
+    amp = np.array([0.5, 1.0, 2.0, 0.25])
+    fields = [(3.0 * f + 1.0) * k - 7.0 + a * mode for f, a in enumerate(amp)]
+    st = oracle.level_stats(*fields)
+    assert st.shape == (4, 2, nz)
+    for f, a in enumerate(amp):
+        base = (3.0 * f + 1.0) * np.arange(nz) - 7.0
+        np.testing.assert_allclose(st[f, 0], base, rtol=0, atol=1e-14)
+        np.testing.assert_allclose(st[f, 1], base + a, rtol=0, atol=1e-14)
+    # a field that is one value everywhere except a single point
+    p = np.zeros((nz, ny, nx))
+    p[2, 3, 4] = 48.0
+    st = oracle.level_stats(p, p, p, p)
+    assert st[0, 0, 2] == 1.0 and st[0, 1, 2] == 48.0 and st[0, 1, 1] == 0.0
