@@ -130,7 +130,8 @@ static int configure_tiles(monc_plan* pl, int ex, int ey, int ymt, int triP, int
   if (!fft_threads(fx, ex) || !fft_threads(fy, ey))
     return fail(MONC_EUNSUPPORTED, "FFT of nx=%d or ny=%d needs more than 1024 threads", pl->nx, pl->ny);
   const size_t cb = cplx_bytes(pl->dtype);
-  // y-FFT columns per workgroup: 128-byte rows by default, bounded by the
+  // y-FFT columns per workgroup (also the width of the spectral column
+  // blocks, up to 8): 128 bytes of a row by default, bounded by the
   // workgroup size (1024) and 128 KB of LDS
   const int nty = ct_supported(pl->ny) ? ct_threads_y_host(pl->ny) : fy.nt;
   const int mt_cap = std::max(1, std::min(1024 / nty, (int)(131072 / (pl->ny * cb))));

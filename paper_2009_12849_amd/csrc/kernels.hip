@@ -883,7 +883,7 @@ __global__ void __launch_bounds__(1024) k_xinv_gen(LaunchArgs a) {
 // Column (m, n): rows a_k P_{k-1} + (-a_k - c_k - rho0_k lam) P_k + c_k P_{k+1}
 // = B_k, lam = lamx[m] + lamy[n], solved in FP64 whatever the storage type.
 // P lanes of one wave share a column; lane q owns rows q*S .. q*S+S-1 (rows
-// >= nz are identity rows).
+// >= nz read P_k - P_{k-1} = 0: decoupled from the system by the lid).
 //  1. each lane eliminates inside its chunk so that every row depends only on
 //     the chunk's first unknown F_q and last unknown L_q;
 //  2. the interface rows of L_q are substituted into those of F_q, leaving a
@@ -968,7 +968,8 @@ __device__ __forceinline__ void tri_tile(const MemberDesc& d, const IoPtrs& io, 
   // columns run linearly over the padded level plane in memory order (offset
   // x inside a level holds column (n, m) = spec_nm(x)), so a tile is one
   // aligned contiguous run of each level; padding columns (m >= nxh) ride
-  // along as identity systems and are neither read nor written
+  // along as dummy systems with a zero right-hand side and are neither read
+  // nor written
   const int ncolp = d.ny * nxp;
   const int col0 = lb * CW;
   using CS = cx<TS>;
@@ -1143,7 +1144,8 @@ __device__ __forceinline__ void tri_tile(const MemberDesc& d, const IoPtrs& io, 
   //    reciprocal per step). A lane without a partner at distance h already
   //    has a zero coupling on that side (the first lane's a and the last
   //    lane's c are zero, and each step keeps them zero out to distance 2h),
-  //    so it reads its own row and every product with it vanishes.
+  //    so whatever it reads there (its own row through an LDS permute, 0
+  //    through DPP) is multiplied by zero.
   {
     const double ib = rcp64(row.b);
     row.a *= ib;
