@@ -21,3 +21,4 @@ from .projection import (  # noqa: F401
     weighted_energy,
 )
 from .reductions import level_stats  # noqa: F401
+from .variable import divergence_var, operator_matrix, project_var  # noqa: F401
