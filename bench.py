@@ -16,6 +16,9 @@ case, see synth/):
   ensemble48     48-member ensemble of uneven grids, one batched call (HIP
                  graph); headline = mixed, FP64 beside it
   2048x2048x160  k^-5/3 spectra; headline = mixed, FP64 beside it
+Single grids up to 3e8 points also time the variable-density projection
+(conjugate gradients with the spectral solve as preconditioner, a seeded
+density rho0(z)(1 + 0.2 f(x, y, z))) under "variable_density".
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -209,6 +212,62 @@ def measure(runner, steps, warmup, workload, nx_bytes):
     }
 
 
+def var_iteration_bytes_per_point(nx, mixed):
+    """Algorithmic HBM bytes per grid point of one conjugate-gradient
+    iteration of the variable-density projection: the operator (read d and
+    rho, write q), the update (read p, d, r, q; write p, r), the spectral
+    preconditioner (read r, the spectrum's four round trips, write z in the
+    plan's storage type), the two inner products (read r, z, q) and the
+    direction update (read z, d; write d). FP64 136 + 64f, mixed 124 + 32f."""
+    f = spectral_words(nx)
+    wb = 4.0 if mixed else 8.0
+    return 24 + 48 + (8 + 8 * f * wb + wb) + (16 + wb) + (16 + wb)
+
+
+def variable_density(monc, torch, member, reps=3, tol=1e-10, amp=0.2):
+    """The variable-density projection (conjugate gradients, the spectral
+    solve as preconditioner) on the workload's grid and fields with a
+    density rho0(z) (1 + amp f(x, y, z)), |f| <= 1: per preconditioner
+    precision the median wall time of `reps` solves from the same inputs
+    (inputs copied in before each, outside the timing), iterations,
+    relative residual and the per-iteration HBM fraction."""
+    import synth
+    g = member.grid
+    rho_np = synth.density_field(np.random.default_rng(6100), g, amp)
+    dev = "cuda:0"
+    rho = torch.from_numpy(rho_np).to(dev)
+    del rho_np
+    src = [torch.from_numpy(a.astype(np.float64, copy=False)).to(dev) for a in (member.u, member.v, member.w)]
+    work = [torch.empty_like(src[0]) for _ in range(4)]
+    out = {"what": f"D_rho(G p) = D_rho(u*) with rho = rho0(z)(1 + {amp} f(x,y,z)), FP64 conjugate gradients, "
+                   f"the spectral solve as preconditioner, stop at relative residual {tol}",
+           "tol": tol}
+    for dtype in ("f64", "mixed"):
+        plan = monc.Plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, rho.mean(dim=(1, 2)).cpu().numpy(), dtype)
+        plan.autotune()
+        times, it, rel = [], 0, 0.0
+        for r in range(reps + 1):
+            for a, b in zip(work[:3], src):
+                a.copy_(b)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            it, rel = plan.project_var(rho, *work, tol=tol, maxit=500)
+            torch.cuda.synchronize()
+            if r > 0:
+                times.append(time.perf_counter() - t0)
+        plan.close()
+        ms = 1e3 * float(np.median(times))
+        ms_it = ms / max(it, 1)
+        gbs = var_iteration_bytes_per_point(g.nx, dtype == "mixed") * g.points / (ms_it * 1e-3) / 1e9
+        out["fp64_preconditioner" if dtype == "f64" else "fp32_preconditioner"] = {
+            "ms_per_solve": ms, "iterations": it, "relres": rel, "ms_per_iteration": ms_it,
+            "grid_points_per_s": g.points / (ms * 1e-3),
+            "iteration_hbm_frac": gbs / HBM_PEAK_GBS}
+    del rho, src, work
+    torch.cuda.empty_cache()
+    return out
+
+
 def device_copy_gbps(torch, mb=2048, reps=10):
     """Read+write bandwidth of a plain device-to-device copy (context for the
     HBM peak)."""
@@ -278,6 +337,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline leg")
     ap.add_argument("--no-other", action="store_true", help="time only the headline path")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile parameters")
+    ap.add_argument("--no-var", action="store_true", help="skip the variable-density solve")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
                     help="also run a device copy of this many MB (counter calibration)")
     args = ap.parse_args()
@@ -345,6 +405,8 @@ def main():
         "device_copy_GBps": copy_gbps,
         "with_reductions": reductions,
     }
+    if not args.no_var and not runner.batched and runner.points <= 300_000_000:
+        result["variable_density"] = variable_density(monc, torch, members[0])
     if not args.no_other:
         del runner
         torch.cuda.empty_cache()

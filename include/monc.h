@@ -131,6 +131,44 @@ int monc_project_batched(monc_plan* const* plans, int count,
  */
 int monc_project_reduce(monc_plan* plan, void* u, void* v, void* w, void* p, double* stats, void* stream);
 
+/* Projection with a density rho(x, y, z) that also varies horizontally: the
+ * non-separable problem, on which the FFT solve above is no longer exact.
+ * The paper's Sec. 4 sets the FFT solver beside an iterative Krylov solver
+ * (preconditioned BiCGStab); Sec. 5 proposes preconditioners built from the
+ * problem's structure and a mixed-precision solver with a double-precision
+ * restart. Here the plan's own spectral solve is the preconditioner of a
+ * conjugate-gradient solve in FP64:
+ *   D_rho(u) = [rx_i u_i - rx_{i-1} u_{i-1}]/dx + [ry_j v_j - ry_{j-1} v_{j-1}]/dy
+ *              + (rz_k w_k - rz_{k-1} w_{k-1})/dz_k           (zero flux at lids)
+ *   rx = (rho_i + rho_{i+1})/2, ry = (rho_j + rho_{j+1})/2 (periodic),
+ *   rz_k = (dz_{k+1} rho_k + dz_k rho_{k+1})/(dz_k + dz_{k+1});
+ *   find p with D_rho(G p) = D_rho(u*) and sum_k dz_k sum_ij p = 0, then
+ *   u = u* - G p and w[nz-1] = 0.
+ * With rho[k,j,i] = rho0[k] this is monc_project's problem.
+ * Method: CG in the dz-weighted inner product (in which D_rho G is
+ * self-adjoint), z = M^-1 r the plan's spectral solve with its rho0 (the
+ * horizontal mean of rho per level is the natural choice): FP64 for an FP64
+ * plan; for a MIXED plan FP32 transforms with the FP64 tridiagonal solve and
+ * no refinement step. The residual and the iterates stay FP64 and the
+ * direction update is the flexible (Polak-Ribiere) one, which tolerates the
+ * inexact FP32 preconditioner.
+ * Arguments: rho, u, v, w, p are FP64 device arrays (nz, ny, nx), 16-byte
+ * aligned and pairwise disjoint, whatever the plan's precision; rho (> 0
+ * everywhere) is read only, u, v, w are updated in place, p is written.
+ * tol >= 0: stop once ||r|| <= tol ||D_rho(u*)|| (dz-weighted 2-norms of
+ * the residual r = D_rho(u*) - D_rho(G p)); maxit in [1, 10000]: the most
+ * iterations. *iters and *relres (either may be NULL) receive the iterations
+ * taken and the final ||r||/||D_rho(u*)||; reaching maxit is not an error,
+ * the caller compares *relres with tol. Work vectors (four fields) are
+ * allocated on the plan by the first call and freed with it.
+ * Unlike the other entry points this one synchronises the stream once per
+ * iteration, to read the residual norm.
+ * Returns MONC_OK, MONC_EINVAL (bad argument, non-finite input, breakdown),
+ * MONC_ENOMEM or MONC_EHIP.
+ */
+int monc_project_var(monc_plan* plan, const double* rho, double* u, double* v, double* w, double* p, double tol,
+                     int maxit, int* iters, double* relres, void* stream);
+
 /* Message of the last failure on the calling thread ("" if none). */
 const char* monc_last_error(void);
 

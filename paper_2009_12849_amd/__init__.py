@@ -56,6 +56,9 @@ def lib() -> ctypes.CDLL:
     L.monc_project.argtypes = [vp, vp, vp, vp, vp, vp]
     L.monc_project_reduce.restype = ip
     L.monc_project_reduce.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.monc_project_var.restype = ip
+    L.monc_project_var.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_double, ip, ctypes.POINTER(ip),
+                                   ctypes.POINTER(ctypes.c_double), vp]
     L.monc_project_batched.restype = ip
     L.monc_project_batched.argtypes = [ctypes.POINTER(vp), ip] + [ctypes.POINTER(vp)] * 4 + [vp]
     L.monc_last_error.restype = ctypes.c_char_p
@@ -172,6 +175,27 @@ class Plan:
                 or not stats.is_contiguous():
             raise ValueError(f"stats must be a contiguous float64 device tensor of {8 * self.nz} values")
         _check(lib().monc_project_reduce(self._h, *args, ctypes.c_void_p(stats.data_ptr()), st))
+
+    def project_var(self, rho, u, v, w, p, tol=1e-12, maxit=200, stream=None):
+        """Projection with the density field rho(x, y, z) (see
+        monc_project_var): preconditioned conjugate gradients with this
+        plan's spectral solve as the preconditioner. rho, u, v, w, p are
+        contiguous float64 device tensors of shape (nz, ny, nx) whatever the
+        plan's precision; u, v, w are updated in place, p receives the
+        pressure. Returns (iterations, final relative residual)."""
+        import torch
+        args = []
+        for t, n in ((rho, "rho"), (u, "u"), (v, "v"), (w, "w"), (p, "p")):
+            if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"{n} must be a contiguous float64 CUDA tensor")
+            if tuple(t.shape) != (self.nz, self.ny, self.nx):
+                raise ValueError(f"{n} must have shape (nz, ny, nx) = {(self.nz, self.ny, self.nx)}")
+            args.append(ctypes.c_void_p(t.data_ptr()))
+        it = ctypes.c_int(0)
+        rel = ctypes.c_double(0.0)
+        _check(lib().monc_project_var(self._h, *args, float(tol), int(maxit), ctypes.byref(it), ctypes.byref(rel),
+                                      ctypes.c_void_p(_stream_handle(stream))))
+        return it.value, rel.value
 
     # -- introspection / stages / profiling / tuning ---------------------
     def spectral_layout(self):

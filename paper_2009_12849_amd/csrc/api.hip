@@ -17,6 +17,7 @@
 
 #include "../../include/monc.h"
 #include "kernels.h"
+#include "krylov.h"
 #include "monc_types.h"
 #include "plan_math.h"
 
@@ -94,6 +95,7 @@ struct monc_plan {
   void* d_spec = nullptr;
   float* d_prem = nullptr;
   size_t spec_elems = 0;
+  void* d_var = nullptr;     // work vectors of monc_project_var (allocated at its first call)
   Profiler prof;
 };
 
@@ -425,6 +427,7 @@ extern "C" void monc_plan_destroy(monc_plan* pl) {
   if (pl->d_spec) (void)hipFree(pl->d_spec);
   if (pl->d_prem) (void)hipFree(pl->d_prem);
   if (pl->d_desc) (void)hipFree(pl->d_desc);
+  if (pl->d_var) (void)hipFree(pl->d_var);
   delete pl;
 }
 
@@ -461,11 +464,11 @@ struct Group {
   bool fp64 = true;
 };
 
-enum Phase { PH_XFWD, PH_RESID, PH_YFWD, PH_TRI, PH_YINV, PH_XINV, PH_XINV_CORR, PH_GRAD, PH_GRAD_MIXED };
+enum Phase { PH_XFWD, PH_XPRE, PH_RESID, PH_YFWD, PH_TRI, PH_YINV, PH_XINV, PH_XINV_CORR, PH_GRAD, PH_GRAD_MIXED };
 
 static int phase_kernel_id(Phase ph) {
   switch (ph) {
-    case PH_XFWD: return MONC_K_DIV_FFTX;
+    case PH_XFWD: case PH_XPRE: return MONC_K_DIV_FFTX;
     case PH_RESID: return MONC_K_RESID_FFTX;
     case PH_YFWD: return MONC_K_FFTY_FWD;
     case PH_TRI: return MONC_K_TRIDIAG;
@@ -477,7 +480,7 @@ static int phase_kernel_id(Phase ph) {
   return 0;
 }
 
-static bool is_xphase(Phase ph) { return ph == PH_XFWD || ph == PH_RESID || ph == PH_XINV || ph == PH_XINV_CORR; }
+static bool is_xphase(Phase ph) { return ph == PH_XFWD || ph == PH_XPRE || ph == PH_RESID || ph == PH_XINV || ph == PH_XINV_CORR; }
 static bool is_yphase(Phase ph) { return ph == PH_YFWD || ph == PH_YINV; }
 
 // Launch shape of one member in one phase. Members whose shapes agree share
@@ -575,6 +578,7 @@ static int launch_one(const Group& g, const std::vector<int>& idx, Phase ph, con
   const int v = sh.variant;
   switch (ph) {
     case PH_XFWD: launch_xfwd(a, grid, block, lds, g.fp64, 0, v, stream); break;
+    case PH_XPRE: launch_xfwd(a, grid, block, lds, g.fp64, 2, v, stream); break;
     case PH_RESID: launch_xfwd(a, grid, block, lds, false, 1, v, stream); break;
     case PH_YFWD: launch_ffty(a, grid, block, lds, g.fp64, false, v, stream); break;
     case PH_YINV: launch_ffty(a, grid, block, lds, g.fp64, true, v, stream); break;
@@ -713,6 +717,199 @@ extern "C" int monc_project_reduce(monc_plan* pl, void* u, void* v, void* w, voi
   g.mem.push_back({&pl->h, pl->d_desc, io});
   std::vector<Group> groups{g};
   return run_phases(groups, full_sequence(g.fp64), stream, pl->prof.mask ? &pl->prof : nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// variable-density projection: preconditioned conjugate gradients
+// ---------------------------------------------------------------------------
+static constexpr int kVarMaxIt = 10000;
+
+// Work vectors of one plan, carved from one allocation: r, d, q (FP64
+// fields), z (storage type), two partial-sum arrays, the per-iteration
+// scalars and the vertical interpolation weights za, zb.
+struct VarWs {
+  double *r, *d, *q, *part0, *part1, *scal, *za, *zb;
+  void* z;
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static int var_workspace(monc_plan* pl, VarWs* ws) {
+  const size_t n = (size_t)pl->nx * pl->ny * pl->nz;
+  const size_t nparts = (size_t)var_blocks_per_level(pl->nx, pl->ny) * pl->nz;
+  const size_t sizes[9] = {n * 8, n * 8, n * 8, n * elem_bytes(pl->dtype), nparts * 8, nparts * 8,
+                           (size_t)(kVarMaxIt + 2) * kVarSlots * 8, (size_t)pl->nz * 8, (size_t)pl->nz * 8};
+  size_t off[9], total = 0;
+  for (int i = 0; i < 9; ++i) {
+    off[i] = total;
+    total += align256(sizes[i]);
+  }
+  if (!pl->d_var) {
+    if (hipMalloc(&pl->d_var, total) != hipSuccess) {
+      pl->d_var = nullptr;
+      (void)hipGetLastError();
+      return fail(MONC_ENOMEM, "monc_project_var: cannot allocate %zu bytes of work vectors", total);
+    }
+    // za_k = dz_{k+1}/(dz_k + dz_{k+1}), zb_k = dz_k/(dz_k + dz_{k+1}), 0 on the lid
+    std::vector<double> za(pl->nz, 0.0), zb(pl->nz, 0.0);
+    for (int k = 0; k + 1 < pl->nz; ++k) {
+      const double s = pl->dz[k] + pl->dz[k + 1];
+      za[k] = pl->dz[k + 1] / s;
+      zb[k] = pl->dz[k] / s;
+    }
+    char* b = static_cast<char*>(pl->d_var);
+    if (hipMemcpy(b + off[7], za.data(), pl->nz * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b + off[8], zb.data(), pl->nz * 8, hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(pl->d_var);
+      pl->d_var = nullptr;
+      return fail(MONC_EHIP, "monc_project_var: upload of the interpolation weights failed");
+    }
+  }
+  char* b = static_cast<char*>(pl->d_var);
+  ws->r = reinterpret_cast<double*>(b + off[0]);
+  ws->d = reinterpret_cast<double*>(b + off[1]);
+  ws->q = reinterpret_cast<double*>(b + off[2]);
+  ws->z = b + off[3];
+  ws->part0 = reinterpret_cast<double*>(b + off[4]);
+  ws->part1 = reinterpret_cast<double*>(b + off[5]);
+  ws->scal = reinterpret_cast<double*>(b + off[6]);
+  ws->za = reinterpret_cast<double*>(b + off[7]);
+  ws->zb = reinterpret_cast<double*>(b + off[8]);
+  return MONC_OK;
+}
+
+static int read_scalar(const double* dev, double* host, void* stream) {
+  if (hipMemcpyAsync(host, dev, sizeof(double), hipMemcpyDeviceToHost, (hipStream_t)stream) != hipSuccess ||
+      hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+    return fail(MONC_EHIP, "monc_project_var: reading the residual norm failed: %s",
+                hipGetErrorString(hipGetLastError()));
+  return MONC_OK;
+}
+
+static int var_launched(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(MONC_EHIP, "monc_project_var: launch of %s failed: %s", what, hipGetErrorString(e));
+  return MONC_OK;
+}
+
+extern "C" int monc_project_var(monc_plan* pl, const double* rho, double* u, double* v, double* w, double* p,
+                                double tol, int maxit, int* iters, double* relres, void* stream) {
+  if (!pl) return fail(MONC_EINVAL, "plan is null");
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(MONC_EINVAL, "monc_project_var: tol must be finite and >= 0");
+  if (maxit < 1 || maxit > kVarMaxIt)
+    return fail(MONC_EINVAL, "monc_project_var: maxit must be in [1, %d], got %d", kVarMaxIt, maxit);
+  {
+    void* ptrs[5] = {const_cast<double*>(rho), u, v, w, p};
+    const size_t bytes = (size_t)pl->nx * pl->ny * pl->nz * sizeof(double);
+    for (int i = 0; i < 5; ++i) {
+      if (!ptrs[i]) return fail(MONC_EINVAL, "monc_project_var: pointer %d is null", i);
+      if (reinterpret_cast<uintptr_t>(ptrs[i]) % 16 != 0)
+        return fail(MONC_EINVAL, "monc_project_var: pointer %d is not 16-byte aligned", i);
+    }
+    for (int i = 0; i < 5; ++i)
+      for (int j = i + 1; j < 5; ++j) {
+        const uintptr_t a = reinterpret_cast<uintptr_t>(ptrs[i]), b = reinterpret_cast<uintptr_t>(ptrs[j]);
+        if (a < b + bytes && b < a + bytes) return fail(MONC_EINVAL, "monc_project_var: arrays %d and %d overlap", i, j);
+      }
+  }
+  int rc = check_device(pl);
+  if (rc != MONC_OK) return rc;
+  VarWs ws;
+  rc = var_workspace(pl, &ws);
+  if (rc != MONC_OK) return rc;
+  const MemberDesc& h = pl->h;
+  VarGrid g;
+  g.nx = pl->nx;
+  g.ny = pl->ny;
+  g.nz = pl->nz;
+  g.rdx = 1.0 / pl->dx;
+  g.rdy = 1.0 / pl->dy;
+  g.rdx2 = g.rdx * g.rdx;
+  g.rdy2 = g.rdy * g.rdy;
+  g.rho = rho;
+  g.dz = h.dz;
+  g.rdz = h.rdz;
+  g.rdzc = h.rdzc;
+  g.za = ws.za;
+  g.zb = ws.zb;
+  const long long nparts = var_blocks_per_level(pl->nx, pl->ny) * pl->nz;
+  const bool z64 = pl->dtype == MONC_FP64;
+  Profiler* prof = pl->prof.mask ? &pl->prof : nullptr;
+
+  // preconditioner z = M^-1 r: the plan's spectral solve with r as its source
+  Group pre;
+  pre.fp64 = z64;
+  pre.mem.push_back({&pl->h, pl->d_desc, IoPtrs{ws.r, nullptr, nullptr, ws.z, pl->d_spec}});
+  static const std::vector<Phase> pre_seq = {PH_XPRE, PH_YFWD, PH_TRI, PH_YINV, PH_XINV};
+  const std::vector<Group> pre_groups{pre};
+  auto precondition = [&]() { return run_phases(pre_groups, pre_seq, stream, prof); };
+  auto finish = [&](const double* part, int slot) {
+    launch_var_finish(part, nparts, ws.scal, slot, stream);
+    return var_launched("the partial-sum reduction");
+  };
+
+  launch_var_zero(ws.scal, (maxit + 1) * kVarSlots, stream);
+  launch_var_div(g, u, v, w, ws.r, p, ws.part0, stream);
+  if ((rc = var_launched("the divergence")) != MONC_OK || (rc = finish(ws.part0, var_slot(0, kVarRR))) != MONC_OK)
+    return rc;
+  double rr0 = 0.0, rr = 0.0;
+  if ((rc = read_scalar(ws.scal + var_slot(0, kVarRR), &rr0, stream)) != MONC_OK) return rc;
+  if (!std::isfinite(rr0)) return fail(MONC_EINVAL, "monc_project_var: the divergence of the input is not finite");
+  int it = 0;
+  double rel = 0.0;
+  if (rr0 > 0.0) {
+    if ((rc = precondition()) != MONC_OK) return rc;
+    launch_var_dots(g, ws.r, ws.z, z64, ws.q, ws.part0, ws.part1, stream);
+    if ((rc = var_launched("the inner products")) != MONC_OK || (rc = finish(ws.part0, var_slot(0, kVarRZ))) != MONC_OK)
+      return rc;
+    launch_var_dir(g, ws.scal, 0, ws.z, z64, ws.d, stream);
+    if ((rc = var_launched("the direction update")) != MONC_OK) return rc;
+    rel = 1.0;
+    while (it < maxit) {
+      launch_var_apply(g, ws.d, ws.q, ws.part0, stream);
+      if ((rc = var_launched("the operator")) != MONC_OK || (rc = finish(ws.part0, var_slot(it, kVarDQ))) != MONC_OK)
+        return rc;
+      launch_var_update(g, ws.scal, it, p, ws.r, ws.d, ws.q, ws.part0, stream);
+      if ((rc = var_launched("the solution update")) != MONC_OK ||
+          (rc = finish(ws.part0, var_slot(it + 1, kVarRR))) != MONC_OK)
+        return rc;
+      ++it;
+      if ((rc = read_scalar(ws.scal + var_slot(it, kVarRR), &rr, stream)) != MONC_OK) return rc;
+      if (!std::isfinite(rr))
+        return fail(MONC_EINVAL, "monc_project_var: breakdown at iteration %d (is rho positive everywhere?)", it);
+      rel = std::sqrt(rr / rr0);
+      if (rel <= tol || it == maxit) break;
+      if ((rc = precondition()) != MONC_OK) return rc;
+      launch_var_dots(g, ws.r, ws.z, z64, ws.q, ws.part0, ws.part1, stream);
+      if ((rc = var_launched("the inner products")) != MONC_OK ||
+          (rc = finish(ws.part0, var_slot(it, kVarRZ))) != MONC_OK ||
+          (rc = finish(ws.part1, var_slot(it, kVarZQ))) != MONC_OK)
+        return rc;
+      launch_var_dir(g, ws.scal, it, ws.z, z64, ws.d, stream);
+      if ((rc = var_launched("the direction update")) != MONC_OK) return rc;
+    }
+  }
+  // the gauge in FP64: subtract the dz-weighted mean of p (the constants are
+  // the operator's null space, so the residual does not change; an FP32
+  // preconditioner's rounding would otherwise leave a small mean in p)
+  if (it > 0) {
+    double wsum = 0.0;
+    for (int k = 0; k < pl->nz; ++k) wsum += pl->dz[k];
+    const int gslot = var_slot(kVarMaxIt + 1, 0);
+    launch_var_wsum(g, p, ws.part0, stream);
+    if ((rc = var_launched("the gauge sum")) != MONC_OK || (rc = finish(ws.part0, gslot)) != MONC_OK) return rc;
+    launch_var_shift(g, ws.scal, gslot, 1.0 / ((double)pl->nx * pl->ny * wsum), p, stream);
+    if ((rc = var_launched("the gauge shift")) != MONC_OK) return rc;
+  }
+  if (iters) *iters = it;
+  if (relres) *relres = rel;
+  // u = u* - G p, w = 0 on the lid: the FP64 gradient kernel
+  Group gr;
+  gr.fp64 = true;
+  gr.mem.push_back({&pl->h, pl->d_desc, IoPtrs{u, v, w, p, pl->d_spec}});
+  const std::vector<Group> grad_groups{gr};
+  static const std::vector<Phase> grad_seq = {PH_GRAD};
+  return run_phases(grad_groups, grad_seq, stream, prof);
 }
 
 // ---------------------------------------------------------------------------

@@ -19,7 +19,8 @@ inline int ct_threads_y_host(int n) { return ct_threads_y_n(n); }
 
 // ct_n: the compile-time length, or 0 for the runtime-length kernel.
 // mode 0: divergence of (u, v, w); mode 1 (float only): FP64 residual
-// D(u) - D(G p) with p the first-pass pressure.
+// D(u) - D(G p) with p the first-pass pressure; mode 2: the FP64 field at
+// io.u (nz, ny, nx), rounded to the storage type.
 void launch_xfwd(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, int mode, int ct_n, void* stream);
 void launch_ffty(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, bool inverse, int ct_n,
                  void* stream);

@@ -182,11 +182,17 @@ __device__ __forceinline__ double resid_at(const MemberDesc& d, const RowCtx& c,
   return c.rho0 * ((ue - uw) * d.rdx + (vn - vs) * d.rdy) + (ft - fb) * c.rdz;
 }
 
+// Sources of the x-forward transform: MODE 0 the divergence D(u*), MODE 1
+// the mixed path's FP64 residual, MODE 2 a given FP64 field (io.u) rounded to
+// T, i.e. the spectral solve applied to an arbitrary right-hand side (the
+// preconditioner of the variable-density Krylov solver).
 template <typename T, int MODE>
 __device__ __forceinline__ T source_at(const MemberDesc& d, const RowCtx& c, const IoPtrs& io, int i) {
   if constexpr (MODE == 0) {
     return div_at<T>(d, c, reinterpret_cast<const T*>(io.u), reinterpret_cast<const T*>(io.v),
                      reinterpret_cast<const T*>(io.w), i);
+  } else if constexpr (MODE == 2) {
+    return (T)reinterpret_cast<const double*>(io.u)[c.off + i];
   } else {
     return (T)resid_at(d, c, reinterpret_cast<const float*>(io.u), reinterpret_cast<const float*>(io.v),
                        reinterpret_cast<const float*>(io.w), reinterpret_cast<const float*>(io.p), i);
@@ -389,8 +395,19 @@ __device__ __forceinline__ void resid_pair_vec(const MemberDesc& d, const RowCtx
 
 template <typename T, int MODE>
 __device__ __forceinline__ void source_vec(const MemberDesc& d, const RowCtx& c, const IoPtrs& io, int i0, T* out) {
-  if constexpr (MODE == 0) div_vec<T>(d, c, io, i0, out);
-  else resid_vec(d, c, io, i0, out);
+  if constexpr (MODE == 0) {
+    div_vec<T>(d, c, io, i0, out);
+  } else if constexpr (MODE == 2) {
+    const double* __restrict__ r = reinterpret_cast<const double*>(io.u) + c.off + i0;
+#pragma unroll
+    for (int e = 0; e < Vec<T>::n; e += 2) {
+      const Vec<double>::type x = ldv(r + e);
+      out[e] = (T)x[0];
+      out[e + 1] = (T)x[1];
+    }
+  } else {
+    resid_vec(d, c, io, i0, out);
+  }
 }
 
 // Separate two real rows packed as z = a + i b:
@@ -1459,6 +1476,8 @@ void init_kernel_attributes() {
   set_lds_limit(k_xfwd_gen<double, 0>);
   set_lds_limit(k_xfwd_gen<float, 0>);
   set_lds_limit(k_xfwd_gen<float, 1>);
+  set_lds_limit(k_xfwd_gen<double, 2>);
+  set_lds_limit(k_xfwd_gen<float, 2>);
   set_lds_limit(k_ffty_gen<double, false>);
   set_lds_limit(k_ffty_gen<double, true>);
   set_lds_limit(k_ffty_gen<float, false>);
@@ -1477,6 +1496,8 @@ void init_kernel_attributes() {
   set_lds_limit(k_xfwd_ct<double, 0, N>);     \
   set_lds_limit(k_xfwd_ct<float, 0, N>);      \
   set_lds_limit(k_xfwd_ct<float, 1, N>);      \
+  set_lds_limit(k_xfwd_ct<double, 2, N>);     \
+  set_lds_limit(k_xfwd_ct<float, 2, N>);      \
   set_lds_limit(k_ffty_ct<double, false, N>); \
   set_lds_limit(k_ffty_ct<double, true, N>);  \
   set_lds_limit(k_ffty_ct<float, false, N>);  \
@@ -1494,16 +1515,20 @@ void launch_xfwd(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64
   switch (ct_n) {
 #define MONC_CASE(N)                                        \
   case N:                                                   \
-    if (fp64) MONC_GO((k_xfwd_ct<double, 0, N>));           \
+    if (fp64 && mode == 2) MONC_GO((k_xfwd_ct<double, 2, N>)); \
+    else if (fp64) MONC_GO((k_xfwd_ct<double, 0, N>));      \
     else if (mode == 0) MONC_GO((k_xfwd_ct<float, 0, N>));  \
-    else MONC_GO((k_xfwd_ct<float, 1, N>));                 \
+    else if (mode == 1) MONC_GO((k_xfwd_ct<float, 1, N>));  \
+    else MONC_GO((k_xfwd_ct<float, 2, N>));                 \
     return;
     MONC_CT_SIZES(MONC_CASE)
 #undef MONC_CASE
     default:
-      if (fp64) MONC_GO((k_xfwd_gen<double, 0>));
+      if (fp64 && mode == 2) MONC_GO((k_xfwd_gen<double, 2>));
+      else if (fp64) MONC_GO((k_xfwd_gen<double, 0>));
       else if (mode == 0) MONC_GO((k_xfwd_gen<float, 0>));
-      else MONC_GO((k_xfwd_gen<float, 1>));
+      else if (mode == 1) MONC_GO((k_xfwd_gen<float, 1>));
+      else MONC_GO((k_xfwd_gen<float, 2>));
   }
 }
 

@@ -1,0 +1,49 @@
+// Launchers of the variable-density Krylov kernels (krylov.hip): plain
+// device pointers to FP64 (nz, ny, nx) fields.
+#pragma once
+
+namespace monc {
+
+constexpr int kVarBlock = 256;                  // threads per workgroup
+constexpr int kVarPts = 4;                      // points per thread
+constexpr int kVarSpan = kVarBlock * kVarPts;   // points of one level per workgroup
+
+// Scalars of iteration it at scal[4 it + slot]: <r_it, z_it>, <d_it, q_it>,
+// <r_it, r_it> and <z_it, q_{it-1}>, all weighted by dz. A row past the
+// last iteration holds the gauge sum of p.
+enum { kVarRZ = 0, kVarDQ = 1, kVarRR = 2, kVarZQ = 3, kVarSlots = 4 };
+inline __host__ __device__ int var_slot(int it, int s) { return kVarSlots * it + s; }
+
+inline __host__ __device__ long long var_blocks_per_level(int nx, int ny) {
+  return ((long long)nx * ny + kVarSpan - 1) / kVarSpan;
+}
+
+struct VarGrid {
+  int nx, ny, nz;
+  double rdx, rdy;          // 1/dx, 1/dy
+  double rdx2, rdy2;        // 1/dx^2, 1/dy^2
+  const double* rho;        // density at the cell centres, (nz, ny, nx)
+  const double* dz;         // [nz] layer thicknesses (inner-product weights)
+  const double* rdz;        // [nz] 1/dz_k
+  const double* rdzc;       // [nz] 1/dzc_k (0 at nz-1)
+  const double* za;         // [nz] dz_{k+1}/(dz_k + dz_{k+1}) (0 at nz-1)
+  const double* zb;         // [nz] dz_k/(dz_k + dz_{k+1}) (0 at nz-1)
+};
+
+// part: one partial sum per workgroup, nz * var_blocks_per_level entries.
+void launch_var_div(const VarGrid& g, const double* u, const double* v, const double* w, double* r, double* p,
+                    double* part, void* stream);
+void launch_var_apply(const VarGrid& g, const double* d, double* q, double* part, void* stream);
+void launch_var_update(const VarGrid& g, const double* scal, int it, double* p, double* r, const double* d,
+                       const double* q, double* part, void* stream);
+// z: FP64 (z64) or FP32 field
+void launch_var_dots(const VarGrid& g, const double* r, const void* z, bool z64, const double* q, double* part0,
+                     double* part1, void* stream);
+void launch_var_dir(const VarGrid& g, const double* scal, int it, const void* z, bool z64, double* d, void* stream);
+// the dz-weighted sum of p, and p -= scal[slot] * rw
+void launch_var_wsum(const VarGrid& g, const double* p, double* part, void* stream);
+void launch_var_shift(const VarGrid& g, const double* scal, int slot, double rw, double* p, void* stream);
+void launch_var_finish(const double* part, long long n, double* scal, int slot, void* stream);
+void launch_var_zero(double* x, int n, void* stream);
+
+}  // namespace monc

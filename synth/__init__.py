@@ -36,7 +36,7 @@ from typing import List, Optional
 import numpy as np
 
 __all__ = ["Grid", "Member", "Workload", "CONFIGS", "make_workload",
-           "make_grid", "mode_fields", "random_grid", "random_fields"]
+           "make_grid", "mode_fields", "random_grid", "random_fields", "density_field"]
 
 
 @dataclasses.dataclass
@@ -208,6 +208,27 @@ def _spectral_fields(rng, g: Grid):
     w = _spectral_field(rng, g, 0.5)
     w[g.nz - 1] = 0.0
     return u, v, w
+
+
+def density_field(rng, g: Grid, amp: float = 0.2):
+    """Density varying in all three directions around the grid's rho0:
+    rho[k, j, i] = rho0_k (1 + amp (c_k f1 + (1 - c_k) f2)) with f1, f2 two
+    sums of 8 low-wavenumber plane waves at the cell centres (as in
+    mode_fields) scaled to max |f| = 1, and c_k = zc_k / H the height
+    fraction, so |rho/rho0 - 1| <= amp (positive for amp < 1)."""
+    xc, _, yc, _ = _staggered_coords(g)
+    dz = np.asarray(g.dz, dtype=np.float64)
+    zc = _zc(dz)
+    c = zc / dz.sum()
+    f1 = _mode_sum(rng, g, xc, yc)
+    f2 = _mode_sum(rng, g, xc, yc)
+    f1 /= np.abs(f1).max()
+    f2 /= np.abs(f2).max()
+    shape = (g.nz, g.ny, g.nx)
+    rho = np.empty(shape)
+    for k in range(g.nz):
+        rho[k] = g.rho0[k] * (1.0 + amp * (c[k] * f1 + (1.0 - c[k]) * f2))
+    return rho
 
 
 C3_SHAPES = [(64, 64, 64), (128, 128, 96), (192, 192, 128), (256, 256, 128)]

@@ -1,0 +1,138 @@
+"""Variable-density projection (monc_project_var): conjugate gradients with
+the plan's spectral solve as the preconditioner, against the oracle's direct
+sparse solve of the same discrete problem (oracle.project_var), and against
+properties that hold at any size.
+
+Tolerances. The solver stops at a relative residual tol = 1e-12 (dz-weighted
+2-norms). The outputs' own divergence D_rho(u) is that residual up to the
+rounding of the FP64 recurrences, so it is held to 100 tol. The pressure error
+e solves D_rho(G e) = residual, so |e| <= cond * tol * |p|; the condition of
+these small operators (stretched dz, density contrast 1.3/0.7) stays below
+1e3, which bounds p to 1e-8 relative and u, v, w (G e, one difference of e)
+to 1e-9 of the input scale with room to spare."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.tolerances import TOL64
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2009_12849_amd as monc  # noqa: E402
+
+DEV = "cuda:0"
+TOL = 1e-12
+SHAPES = [(32, 32, 16), (48, 27, 13), (24, 18, 9), (4, 4, 1), (1, 6, 5), (1, 1, 4)]
+
+
+def _case(shape, seed, amp=0.3):
+    rng = np.random.default_rng(seed)
+    g = synth.random_grid(rng, *shape, stretch=(1.0, min(1.1, 20.0 ** (1.0 / max(shape[2], 1)))))
+    rho = synth.density_field(rng, g, amp)
+    u, v, w = synth.random_fields(rng, g)
+    return g, rho, u, v, w
+
+
+def _plan(g, rho, dtype):
+    """Plan whose reference density is the horizontal mean of rho."""
+    return monc.Plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, rho.mean(axis=(1, 2)), dtype)
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, torch.float64)
+
+
+def _wnorm(x, dz):
+    return np.sqrt(np.sum(np.asarray(dz)[:, None, None] * x * x))
+
+
+def _run(g, rho, u, v, w, dtype, tol=TOL, maxit=200):
+    plan = _plan(g, rho, dtype)
+    t = [_t(a) for a in (u, v, w)]
+    p = torch.empty_like(t[0])
+    it, rel = plan.project_var(_t(rho), *t, p, tol=tol, maxit=maxit)
+    torch.cuda.synchronize()
+    plan.close()
+    return [x.cpu().numpy() for x in t + [p]], it, rel
+
+
+@pytest.mark.parametrize("dtype", ["f64", "mixed"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_variable_density_matches_direct_solve(shape, dtype):
+    print(f"case {shape} {dtype}", flush=True)
+    g, rho, u, v, w = _case(shape, 1200 + sum(shape))
+    outs, it, rel = _run(g, rho, u, v, w, dtype)
+    print(f"  iterations {it}, relative residual {rel:.3e}", flush=True)
+    assert rel <= TOL and it < 200
+    # the outputs' own divergence, recomputed by the oracle
+    b = oracle.divergence_var(u, v, w, g.dx, g.dy, g.dz, rho)
+    res = oracle.divergence_var(*outs[:3], g.dx, g.dy, g.dz, rho)
+    nb = _wnorm(b, g.dz)
+    if nb > 0:
+        assert _wnorm(res, g.dz) <= 100 * TOL * nb, _wnorm(res, g.dz) / nb
+    assert np.all(outs[2][-1] == 0.0)
+    # gauge: sum_k dz_k sum_ij p = 0 up to rounding
+    dz = np.asarray(g.dz)
+    pw = np.abs(outs[3]).max() * np.sum(dz) * g.nx * g.ny
+    assert abs(np.sum(dz[:, None, None] * outs[3])) <= 1e-12 * max(pw, 1e-300)
+    # the direct solve
+    ref = oracle.project_var(u, v, w, g.dx, g.dy, g.dz, rho)
+    scale = max(np.abs(a).max() for a in (u, v, w))
+    for f in range(3):
+        err = np.abs(outs[f] - ref[f]).max()
+        assert err <= 1e-9 * scale, (f, err / scale)
+    perr = np.abs(outs[3] - ref[3]).max()
+    assert perr <= 1e-8 * max(np.abs(ref[3]).max(), 1e-300), perr / np.abs(ref[3]).max()
+
+
+def test_separable_density_is_one_spectral_solve():
+    """rho = rho0(z): the preconditioner is the exact inverse, CG stops after
+    one iteration (two at most, from rounding) with monc_project's answer."""
+    rng = np.random.default_rng(77)
+    g = synth.random_grid(rng, 32, 24, 12, stretch=(1.0, 1.1))
+    u, v, w = synth.random_fields(rng, g)
+    rho = np.broadcast_to(np.asarray(g.rho0)[:, None, None], (g.nz, g.ny, g.nx)).copy()
+    outs, it, rel = _run(g, rho, u, v, w, "f64")
+    assert it <= 2 and rel <= TOL
+    plan = monc.Plan.from_grid(g, "f64")
+    t = [_t(a) for a in (u, v, w)]
+    p = torch.empty_like(t[0])
+    plan.project(*t, p)
+    torch.cuda.synchronize()
+    plan.close()
+    scale = max(np.abs(a).max() for a in (u, v, w))
+    for f in range(3):
+        assert np.abs(outs[f] - t[f].cpu().numpy()).max() <= TOL64 * scale
+    assert np.abs(outs[3] - p.cpu().numpy()).max() <= 1e-9 * np.abs(outs[3]).max()
+
+
+def test_divergence_free_input_takes_no_iteration():
+    g = synth.random_grid(np.random.default_rng(3), 16, 16, 6)
+    rho = synth.density_field(np.random.default_rng(4), g, 0.2)
+    z = np.zeros((g.nz, g.ny, g.nx))
+    outs, it, rel = _run(g, rho, z, z, z, "f64")
+    assert it == 0 and rel == 0.0
+    assert all(np.all(o == 0.0) for o in outs)
+
+
+def test_iteration_cap_is_reported():
+    g, rho, u, v, w = _case((32, 32, 16), 5)
+    outs, it, rel = _run(g, rho, u, v, w, "f64", tol=0.0, maxit=3)
+    assert it == 3 and 0.0 < rel < 1.0
+
+
+def test_bad_arguments_are_rejected():
+    g, rho, u, v, w = _case((16, 16, 4), 6)
+    plan = _plan(g, rho, "f64")
+    f = [_t(a) for a in (rho, u, v, w, np.zeros_like(u))]
+    with pytest.raises(monc.MoncError):
+        plan.project_var(*f, tol=-1.0)
+    with pytest.raises(monc.MoncError):
+        plan.project_var(*f, maxit=0)
+    with pytest.raises(ValueError):
+        plan.project_var(f[0].float(), *f[1:])
+    with pytest.raises(monc.MoncError):      # p aliases u
+        plan.project_var(f[0], f[1], f[2], f[3], f[1])
+    plan.close()
