@@ -96,6 +96,7 @@ struct monc_plan {
   float* d_prem = nullptr;
   size_t spec_elems = 0;
   void* d_var = nullptr;     // work vectors of monc_project_var (allocated at its first call)
+  MemberDesc h_pre{};        // the preconditioner's descriptor: h plus the solver's done flag
   Profiler prof;
 };
 
@@ -725,22 +726,26 @@ extern "C" int monc_project_reduce(monc_plan* pl, void* u, void* v, void* w, voi
 static constexpr int kVarMaxIt = 10000;
 
 // Work vectors of one plan, carved from one allocation: r, d, q (FP64
-// fields), z (storage type), two partial-sum arrays, the per-iteration
-// scalars and the vertical interpolation weights za, zb.
+// fields), z (storage type), two partial-sum arrays, the scalars (status
+// row and one row per iteration), the vertical interpolation weights za, zb,
+// and the preconditioner's device descriptor.
 struct VarWs {
   double *r, *d, *q, *part0, *part1, *scal, *za, *zb;
   void* z;
+  MemberDesc* desc;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static int var_workspace(monc_plan* pl, VarWs* ws) {
   const size_t n = (size_t)pl->nx * pl->ny * pl->nz;
-  const size_t nparts = (size_t)var_blocks_per_level(pl->nx, pl->ny) * pl->nz;
-  const size_t sizes[9] = {n * 8, n * 8, n * 8, n * elem_bytes(pl->dtype), nparts * 8, nparts * 8,
-                           (size_t)(kVarMaxIt + 2) * kVarSlots * 8, (size_t)pl->nz * 8, (size_t)pl->nz * 8};
-  size_t off[9], total = 0;
-  for (int i = 0; i < 9; ++i) {
+  const size_t nparts = (size_t)var_point_parts(pl->nx, pl->ny, pl->nz);  // the larger count
+  constexpr int kParts = 10;
+  const size_t sizes[kParts] = {n * 8, n * 8, n * 8, n * elem_bytes(pl->dtype), nparts * 8, nparts * 8,
+                                (size_t)(kVarMaxIt + 2) * kVarSlots * 8, (size_t)pl->nz * 8, (size_t)pl->nz * 8,
+                                sizeof(MemberDesc)};
+  size_t off[kParts], total = 0;
+  for (int i = 0; i < kParts; ++i) {
     off[i] = total;
     total += align256(sizes[i]);
   }
@@ -775,13 +780,14 @@ static int var_workspace(monc_plan* pl, VarWs* ws) {
   ws->scal = reinterpret_cast<double*>(b + off[6]);
   ws->za = reinterpret_cast<double*>(b + off[7]);
   ws->zb = reinterpret_cast<double*>(b + off[8]);
+  ws->desc = reinterpret_cast<MemberDesc*>(b + off[9]);
   return MONC_OK;
 }
 
-static int read_scalar(const double* dev, double* host, void* stream) {
-  if (hipMemcpyAsync(host, dev, sizeof(double), hipMemcpyDeviceToHost, (hipStream_t)stream) != hipSuccess ||
+static int read_scalars(const double* dev, double* host, int n, void* stream) {
+  if (hipMemcpyAsync(host, dev, n * sizeof(double), hipMemcpyDeviceToHost, (hipStream_t)stream) != hipSuccess ||
       hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
-    return fail(MONC_EHIP, "monc_project_var: reading the residual norm failed: %s",
+    return fail(MONC_EHIP, "monc_project_var: reading the solver's status failed: %s",
                 hipGetErrorString(hipGetLastError()));
   return MONC_OK;
 }
@@ -832,61 +838,87 @@ extern "C" int monc_project_var(monc_plan* pl, const double* rho, double* u, dou
   g.rdzc = h.rdzc;
   g.za = ws.za;
   g.zb = ws.zb;
-  const long long nparts = var_blocks_per_level(pl->nx, pl->ny) * pl->nz;
+  const long long np_st = var_stencil_parts(pl->nx, pl->ny, pl->nz);  // partials of the stencil kernels
+  const long long np_pt = var_point_parts(pl->nx, pl->ny, pl->nz);    // partials of the pointwise kernels
   const bool z64 = pl->dtype == MONC_FP64;
   Profiler* prof = pl->prof.mask ? &pl->prof : nullptr;
 
-  // preconditioner z = M^-1 r: the plan's spectral solve with r as its source
+  // preconditioner z = M^-1 r: the plan's spectral solve with r as its
+  // source, through a copy of the plan's descriptor that carries the
+  // solver's done flag (queued iterations past convergence then cost only
+  // their launches)
+  pl->h_pre = pl->h;
+  pl->h_pre.skip = ws.scal + kVarDone;
+  if (hipMemcpyAsync(ws.desc, &pl->h_pre, sizeof(MemberDesc), hipMemcpyHostToDevice, (hipStream_t)stream) !=
+      hipSuccess)
+    return fail(MONC_EHIP, "monc_project_var: descriptor upload failed");
   Group pre;
   pre.fp64 = z64;
-  pre.mem.push_back({&pl->h, pl->d_desc, IoPtrs{ws.r, nullptr, nullptr, ws.z, pl->d_spec}});
+  pre.mem.push_back({&pl->h_pre, ws.desc, IoPtrs{ws.r, nullptr, nullptr, ws.z, pl->d_spec}});
   static const std::vector<Phase> pre_seq = {PH_XPRE, PH_YFWD, PH_TRI, PH_YINV, PH_XINV};
   const std::vector<Group> pre_groups{pre};
-  auto precondition = [&]() { return run_phases(pre_groups, pre_seq, stream, prof); };
-  auto finish = [&](const double* part, int slot) {
-    launch_var_finish(part, nparts, ws.scal, slot, stream);
-    return var_launched("the partial-sum reduction");
+  // z_it = M^-1 r_it, <r_it, z_it>, <z_it, q_{it-1}>, then d_it
+  auto direction = [&](int i) {
+    int e = run_phases(pre_groups, pre_seq, stream, prof);
+    if (e != MONC_OK) return e;
+    launch_var_dots(g, ws.scal, ws.r, ws.z, z64, ws.q, ws.part0, ws.part1, stream);
+    if ((e = var_launched("the inner products")) != MONC_OK) return e;
+    launch_var_finish(ws.part0, i > 0 ? ws.part1 : nullptr, np_pt, ws.scal, var_slot(i, kVarRZ),
+                      var_slot(i, kVarZQ), true, stream);
+    if ((e = var_launched("the partial-sum reduction")) != MONC_OK) return e;
+    launch_var_dir(g, ws.scal, i, ws.z, z64, ws.d, stream);
+    return var_launched("the direction update");
+  };
+  // q = L d_it, alpha, p_{it+1}, r_{it+1} and its norm (sets the done flag)
+  const double tol2 = tol * tol;
+  auto step = [&](int i) {
+    launch_var_apply(g, ws.scal, ws.d, ws.q, ws.part0, stream);
+    int e = var_launched("the operator");
+    if (e != MONC_OK) return e;
+    launch_var_finish(ws.part0, nullptr, np_st, ws.scal, var_slot(i, kVarDQ), 0, true, stream);
+    if ((e = var_launched("the partial-sum reduction")) != MONC_OK) return e;
+    launch_var_update(g, ws.scal, i, p, ws.r, ws.d, ws.q, ws.part0, stream);
+    if ((e = var_launched("the solution update")) != MONC_OK) return e;
+    launch_var_finish_rr(ws.part0, np_pt, ws.scal, i + 1, tol2, stream);
+    return var_launched("the residual norm");
   };
 
-  launch_var_zero(ws.scal, (maxit + 1) * kVarSlots, stream);
+  launch_var_zero(ws.scal, (maxit + 2) * kVarSlots, stream);
   launch_var_div(g, u, v, w, ws.r, p, ws.part0, stream);
-  if ((rc = var_launched("the divergence")) != MONC_OK || (rc = finish(ws.part0, var_slot(0, kVarRR))) != MONC_OK)
-    return rc;
-  double rr0 = 0.0, rr = 0.0;
-  if ((rc = read_scalar(ws.scal + var_slot(0, kVarRR), &rr0, stream)) != MONC_OK) return rc;
+  if ((rc = var_launched("the divergence")) != MONC_OK) return rc;
+  launch_var_finish(ws.part0, nullptr, np_st, ws.scal, var_slot(0, kVarRR), 0, false, stream);
+  if ((rc = var_launched("the partial-sum reduction")) != MONC_OK) return rc;
+  double rr0 = 0.0;
+  if ((rc = read_scalars(ws.scal + var_slot(0, kVarRR), &rr0, 1, stream)) != MONC_OK) return rc;
   if (!std::isfinite(rr0)) return fail(MONC_EINVAL, "monc_project_var: the divergence of the input is not finite");
   int it = 0;
   double rel = 0.0;
   if (rr0 > 0.0) {
-    if ((rc = precondition()) != MONC_OK) return rc;
-    launch_var_dots(g, ws.r, ws.z, z64, ws.q, ws.part0, ws.part1, stream);
-    if ((rc = var_launched("the inner products")) != MONC_OK || (rc = finish(ws.part0, var_slot(0, kVarRZ))) != MONC_OK)
-      return rc;
-    launch_var_dir(g, ws.scal, 0, ws.z, z64, ws.d, stream);
-    if ((rc = var_launched("the direction update")) != MONC_OK) return rc;
-    rel = 1.0;
-    while (it < maxit) {
-      launch_var_apply(g, ws.d, ws.q, ws.part0, stream);
-      if ((rc = var_launched("the operator")) != MONC_OK || (rc = finish(ws.part0, var_slot(it, kVarDQ))) != MONC_OK)
-        return rc;
-      launch_var_update(g, ws.scal, it, p, ws.r, ws.d, ws.q, ws.part0, stream);
-      if ((rc = var_launched("the solution update")) != MONC_OK ||
-          (rc = finish(ws.part0, var_slot(it + 1, kVarRR))) != MONC_OK)
-        return rc;
-      ++it;
-      if ((rc = read_scalar(ws.scal + var_slot(it, kVarRR), &rr, stream)) != MONC_OK) return rc;
-      if (!std::isfinite(rr))
-        return fail(MONC_EINVAL, "monc_project_var: breakdown at iteration %d (is rho positive everywhere?)", it);
-      rel = std::sqrt(rr / rr0);
-      if (rel <= tol || it == maxit) break;
-      if ((rc = precondition()) != MONC_OK) return rc;
-      launch_var_dots(g, ws.r, ws.z, z64, ws.q, ws.part0, ws.part1, stream);
-      if ((rc = var_launched("the inner products")) != MONC_OK ||
-          (rc = finish(ws.part0, var_slot(it, kVarRZ))) != MONC_OK ||
-          (rc = finish(ws.part1, var_slot(it, kVarZQ))) != MONC_OK)
-        return rc;
-      launch_var_dir(g, ws.scal, it, ws.z, z64, ws.d, stream);
-      if ((rc = var_launched("the direction update")) != MONC_OK) return rc;
+    if ((rc = direction(0)) != MONC_OK) return rc;
+    // Iterations are queued in batches and the status read once per batch;
+    // the next batch's length is the iteration count that the convergence
+    // rate seen so far predicts (at least 1, at most 32).
+    int queued = 0, batch = 3;
+    double rel_prev = 1.0;
+    for (;;) {
+      const int nb = std::min(batch, maxit - queued);
+      for (int b = 0; b < nb; ++b, ++queued) {
+        if ((rc = step(queued)) != MONC_OK) return rc;
+        if (queued + 1 < maxit && (rc = direction(queued + 1)) != MONC_OK) return rc;
+      }
+      double st[4];
+      if ((rc = read_scalars(ws.scal, st, 4, stream)) != MONC_OK) return rc;
+      if (st[kVarDone] == 2.0)
+        return fail(MONC_EINVAL, "monc_project_var: breakdown at iteration %d (is rho positive everywhere?)",
+                    (int)st[kVarLast]);
+      it = (int)st[kVarLast];
+      rel = std::sqrt(st[kVarLastRR] / rr0);
+      if (st[kVarDone] != 0.0 || queued >= maxit) break;
+      const double rate = std::pow(rel / rel_prev, 1.0 / nb);
+      double want = (rate > 0.0 && rate < 1.0 && rel > 0.0) ? std::ceil(std::log(tol / rel) / std::log(rate)) : 1.0;
+      if (!(want >= 1.0)) want = 1.0;
+      batch = (int)std::min(want, 32.0);
+      rel_prev = rel;
     }
   }
   // the gauge in FP64: subtract the dz-weighted mean of p (the constants are
@@ -895,10 +927,11 @@ extern "C" int monc_project_var(monc_plan* pl, const double* rho, double* u, dou
   if (it > 0) {
     double wsum = 0.0;
     for (int k = 0; k < pl->nz; ++k) wsum += pl->dz[k];
-    const int gslot = var_slot(kVarMaxIt + 1, 0);
     launch_var_wsum(g, p, ws.part0, stream);
-    if ((rc = var_launched("the gauge sum")) != MONC_OK || (rc = finish(ws.part0, gslot)) != MONC_OK) return rc;
-    launch_var_shift(g, ws.scal, gslot, 1.0 / ((double)pl->nx * pl->ny * wsum), p, stream);
+    if ((rc = var_launched("the gauge sum")) != MONC_OK) return rc;
+    launch_var_finish(ws.part0, nullptr, np_pt, ws.scal, kVarGauge, 0, false, stream);
+    if ((rc = var_launched("the partial-sum reduction")) != MONC_OK) return rc;
+    launch_var_shift(g, ws.scal, kVarGauge, 1.0 / ((double)pl->nx * pl->ny * wsum), p, stream);
     if ((rc = var_launched("the gauge shift")) != MONC_OK) return rc;
   }
   if (iters) *iters = it;

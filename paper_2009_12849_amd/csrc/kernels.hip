@@ -63,6 +63,11 @@ __device__ __forceinline__ int xcd_local_block(const LaunchArgs& a, int mi) {
   return (lb & 7) * (full >> 3) + (lb >> 3);
 }
 
+// A descriptor with a skip flag drives the Krylov solver's preconditioner:
+// once the solver has converged the flag is set and the solve's remaining
+// launches return at once (whole workgroups, before any barrier).
+__device__ __forceinline__ bool skipped(const MemberDesc& d) { return d.skip && *d.skip != 0.0; }
+
 // ---------------------------------------------------------------------------
 // per-row context of the stencils: offsets of the neighbouring rows and the
 // vertical metrics of the row's level
@@ -493,6 +498,7 @@ __global__ void __launch_bounds__(512) k_xfwd_ct(LaunchArgs a) {
   extern __shared__ unsigned char smem_raw[];
   const int mi = find_member(a, blockIdx.x);
   const MemberDesc& d = *a.mem[mi];
+  if (skipped(d)) return;
   const IoPtrs io = a.io[mi];
   const int lb = xcd_local_block(a, mi);
   const int ipw = blockDim.x / NT;
@@ -589,6 +595,7 @@ __global__ void __launch_bounds__(1024) k_xfwd_gen(LaunchArgs a) {
   cx<T>* smem = reinterpret_cast<cx<T>*>(smem_raw);
   const int mi = find_member(a, blockIdx.x);
   const MemberDesc& d = *a.mem[mi];
+  if (skipped(d)) return;
   const IoPtrs io = a.io[mi];
   const int lb = xcd_local_block(a, mi);
   const int N = d.nx, nt = d.fx.nt;
@@ -635,6 +642,7 @@ __global__ void __launch_bounds__(1024) k_ffty_ct(LaunchArgs a) {
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   const int mi = find_member(a, blockIdx.x);
   const MemberDesc& d = *a.mem[mi];
+  if (skipped(d)) return;
   const IoPtrs io = a.io[mi];
   const int lb = xcd_local_block(a, mi);
   const int mt = blockDim.x / NT;
@@ -684,6 +692,7 @@ __global__ void __launch_bounds__(1024) k_ffty_gen(LaunchArgs a) {
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int mi = find_member(a, blockIdx.x);
   const MemberDesc& d = *a.mem[mi];
+  if (skipped(d)) return;
   const IoPtrs io = a.io[mi];
   const int lb = xcd_local_block(a, mi);
   const int mt = d.ymt, ny = d.ny, nt = d.fy.nt;
@@ -771,6 +780,7 @@ __global__ void __launch_bounds__(512) k_xinv_ct(LaunchArgs a) {
   extern __shared__ unsigned char smem_raw[];
   const int mi = find_member(a, blockIdx.x);
   const MemberDesc& d = *a.mem[mi];
+  if (skipped(d)) return;
   const IoPtrs io = a.io[mi];
   const int lb = blockIdx.x - a.block_start[mi];
   const int ipw = blockDim.x / NT;
@@ -872,6 +882,7 @@ __global__ void __launch_bounds__(1024) k_xinv_gen(LaunchArgs a) {
   cx<T>* smem = reinterpret_cast<cx<T>*>(smem_raw);
   const int mi = find_member(a, blockIdx.x);
   const MemberDesc& d = *a.mem[mi];
+  if (skipped(d)) return;
   const IoPtrs io = a.io[mi];
   const int lb = blockIdx.x - a.block_start[mi];
   const int N = d.nx, nt = d.fx.nt;
@@ -1270,6 +1281,7 @@ k_tridiag(LaunchArgs a) {
   double2* stage = reinterpret_cast<double2*>(smem_raw);
   const int mi = find_member(a, blockIdx.x);
   const MemberDesc& d = *a.mem[mi];
+  if (skipped(d)) return;
   const IoPtrs io = a.io[mi];
   const int lb = xcd_local_block(a, mi);
   if (lb == 0)

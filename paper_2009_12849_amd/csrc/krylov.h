@@ -7,16 +7,25 @@ namespace monc {
 constexpr int kVarBlock = 256;                  // threads per workgroup
 constexpr int kVarPts = 4;                      // points per thread
 constexpr int kVarSpan = kVarBlock * kVarPts;   // points of one level per workgroup
+constexpr int kVarLevels = 4;                   // levels per stencil workgroup (walked upwards)
+constexpr int kVarFinishBlock = 1024;           // threads of the partial-sum reduction
 
-// Scalars of iteration it at scal[4 it + slot]: <r_it, z_it>, <d_it, q_it>,
-// <r_it, r_it> and <z_it, q_{it-1}>, all weighted by dz. A row past the
-// last iteration holds the gauge sum of p.
+// Scalars in scal[]: a status row, then per iteration it the dz-weighted
+// <r_it, z_it>, <d_it, q_it>, <r_it, r_it> and <z_it, q_{it-1}>.
+// Status: the gauge sum of p; the done flag (0 running, 1 converged,
+// 2 non-finite residual); the last iteration whose <r, r> was formed, and
+// that <r, r>. Once the flag is set every later kernel of the solve returns
+// at once, so the host can queue several iterations between reads.
 enum { kVarRZ = 0, kVarDQ = 1, kVarRR = 2, kVarZQ = 3, kVarSlots = 4 };
-inline __host__ __device__ int var_slot(int it, int s) { return kVarSlots * it + s; }
+enum { kVarGauge = 0, kVarDone = 1, kVarLast = 2, kVarLastRR = 3 };
+inline __host__ __device__ int var_slot(int it, int s) { return kVarSlots * (it + 1) + s; }
 
 inline __host__ __device__ long long var_blocks_per_level(int nx, int ny) {
   return ((long long)nx * ny + kVarSpan - 1) / kVarSpan;
 }
+inline __host__ __device__ int var_level_groups(int nz) { return (nz + kVarLevels - 1) / kVarLevels; }
+inline long long var_stencil_parts(int nx, int ny, int nz) { return var_blocks_per_level(nx, ny) * var_level_groups(nz); }
+inline long long var_point_parts(int nx, int ny, int nz) { return var_blocks_per_level(nx, ny) * nz; }
 
 struct VarGrid {
   int nx, ny, nz;
@@ -30,20 +39,29 @@ struct VarGrid {
   const double* zb;         // [nz] dz_k/(dz_k + dz_{k+1}) (0 at nz-1)
 };
 
-// part: one partial sum per workgroup, nz * var_blocks_per_level entries.
+// part: one partial sum per workgroup: var_stencil_parts entries after the
+// divergence and the operator, var_point_parts after the other kernels.
+// Kernels taking scal (except the divergence) do nothing once the done
+// flag is set.
 void launch_var_div(const VarGrid& g, const double* u, const double* v, const double* w, double* r, double* p,
                     double* part, void* stream);
-void launch_var_apply(const VarGrid& g, const double* d, double* q, double* part, void* stream);
+void launch_var_apply(const VarGrid& g, const double* scal, const double* d, double* q, double* part, void* stream);
 void launch_var_update(const VarGrid& g, const double* scal, int it, double* p, double* r, const double* d,
                        const double* q, double* part, void* stream);
 // z: FP64 (z64) or FP32 field
-void launch_var_dots(const VarGrid& g, const double* r, const void* z, bool z64, const double* q, double* part0,
-                     double* part1, void* stream);
+void launch_var_dots(const VarGrid& g, const double* scal, const double* r, const void* z, bool z64, const double* q,
+                     double* part0, double* part1, void* stream);
 void launch_var_dir(const VarGrid& g, const double* scal, int it, const void* z, bool z64, double* d, void* stream);
 // the dz-weighted sum of p, and p -= scal[slot] * rw
 void launch_var_wsum(const VarGrid& g, const double* p, double* part, void* stream);
 void launch_var_shift(const VarGrid& g, const double* scal, int slot, double rw, double* p, void* stream);
-void launch_var_finish(const double* part, long long n, double* scal, int slot, void* stream);
+// scal[slot0] = sum part0 (and scal[slot1] = sum part1 when part1 is given);
+// gated: skip once done
+void launch_var_finish(const double* part0, const double* part1, long long n, double* scal, int slot0, int slot1,
+                       bool gated, void* stream);
+// <r, r> of iteration it into its slot and the status row; sets the done
+// flag when it is <= tol2 <r_0, r_0> or not finite
+void launch_var_finish_rr(const double* part, long long n, double* scal, int it, double tol2, void* stream);
 void launch_var_zero(double* x, int n, void* stream);
 
 }  // namespace monc

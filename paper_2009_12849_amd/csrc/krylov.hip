@@ -10,12 +10,19 @@
 //   rx = (rho_i + rho_{i+1})/2, ry = (rho_j + rho_{j+1})/2 (periodic),
 //   rz_k = za_k rho_k + zb_k rho_{k+1}, za_k = dz_{k+1}/(dz_k + dz_{k+1}),
 //   zb_k = dz_k/(dz_k + dz_{k+1}) (0 on the lid).
-// A workgroup of kVarBlock threads takes kVarSpan consecutive points of one
-// level (blockIdx.y = level), kVarPts per thread at stride kVarBlock, so
-// accesses stay coalesced and the level's vertical metrics are uniform.
+// A workgroup of kVarBlock threads takes kVarSpan consecutive points of a
+// level (kVarPts per thread at stride kVarBlock, coalesced). The stencil
+// kernels (divergence, operator) walk them up a group of kVarLevels levels
+// (blockIdx.y), keeping the column's values of the levels below and above in
+// registers, so only the x and y neighbours come through the caches; the
+// pointwise kernels take one level per workgroup (more, shorter workgroups
+// stream faster).
 // Inner products are weighted by dz_k (the weight that makes D_rho G
 // self-adjoint); each workgroup writes its partial sum and a one-workgroup
 // kernel adds the partials in a fixed order, so results are deterministic.
+// Loads are unconditional (a point past the level reads point 0, a missing
+// level reads its own) and the results selected, so that all loads of a
+// thread's points issue together.
 #include <hip/hip_runtime.h>
 
 #include "krylov.h"
@@ -30,103 +37,180 @@ __device__ __forceinline__ double wave_sum(double x) {
   return x;
 }
 
-// sum over the workgroup (kVarBlock threads), valid in thread 0
+// sum over a workgroup of NT threads, valid in thread 0
+template <int NT>
 __device__ __forceinline__ double block_sum(double x) {
-  __shared__ double part[kVarBlock / 64];
+  __shared__ double part[NT / 64];
   x = wave_sum(x);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = x;
   __syncthreads();
   double s = 0.0;
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int w = 0; w < kVarBlock / 64; ++w) s += part[w];
+    for (int w = 0; w < NT / 64; ++w) s += part[w];
   return s;
 }
 
-struct Pt {
-  long long o;   // offset of the point
-  long long ow, oe, os, on;  // x and y neighbours (periodic)
-  bool live;
+// One thread's points: kVarPts points of a level at stride kVarBlock
+// (horizontal offsets inside a level and their x and y neighbours, periodic),
+// revisited on each level of the workgroup's group of kVarLevels levels.
+struct Col {
+  int h[kVarPts], hw[kVarPts], he[kVarPts], hs[kVarPts], hn[kVarPts];
+  bool live[kVarPts];
 };
 
-__device__ __forceinline__ Pt point(const VarGrid& g, int t) {
-  Pt p;
+// The workgroup's (point chunk, level group)
+struct Blk {
+  int x, y;
+};
+__device__ __forceinline__ Blk var_block() { return Blk{(int)blockIdx.x, (int)blockIdx.y}; }
+
+__device__ __forceinline__ Col columns(const VarGrid& g, const Blk& bk) {
+  Col c;
   const int nh = g.nx * g.ny;
-  const int idx = blockIdx.x * kVarSpan + t * kVarBlock + threadIdx.x;
-  p.live = idx < nh;
-  const int id = p.live ? idx : 0;
-  const int j = id / g.nx, i = id - j * g.nx;
-  const long long row = (long long)blockIdx.y * nh + (long long)j * g.nx;
-  p.o = row + i;
-  p.ow = row + (i == 0 ? g.nx - 1 : i - 1);
-  p.oe = row + (i == g.nx - 1 ? 0 : i + 1);
-  p.os = (long long)blockIdx.y * nh + (long long)(j == 0 ? g.ny - 1 : j - 1) * g.nx + i;
-  p.on = (long long)blockIdx.y * nh + (long long)(j == g.ny - 1 ? 0 : j + 1) * g.nx + i;
-  return p;
+#pragma unroll
+  for (int t = 0; t < kVarPts; ++t) {
+    const int idx = bk.x * kVarSpan + t * kVarBlock + threadIdx.x;
+    c.live[t] = idx < nh;
+    const int id = c.live[t] ? idx : 0;   // past the level: point 0, nothing stored
+    const int j = id / g.nx, i = id - j * g.nx;
+    const int row = j * g.nx;
+    c.h[t] = row + i;
+    c.hw[t] = row + (i == 0 ? g.nx - 1 : i - 1);
+    c.he[t] = row + (i == g.nx - 1 ? 0 : i + 1);
+    c.hs[t] = (j == 0 ? g.ny - 1 : j - 1) * g.nx + i;
+    c.hn[t] = (j == g.ny - 1 ? 0 : j + 1) * g.nx + i;
+  }
+  return c;
 }
+
+// levels [level_begin, level_end) of a workgroup whose group holds LV levels
+template <int LV>
+__device__ __forceinline__ int level_begin(const Blk& bk) { return bk.y * LV; }
+template <int LV>
+__device__ __forceinline__ int level_end(const VarGrid& g, const Blk& bk) { return min(g.nz, (bk.y + 1) * LV); }
 
 __device__ __forceinline__ long long part_index() { return (long long)blockIdx.y * gridDim.x + blockIdx.x; }
 
+__device__ __forceinline__ bool var_done(const double* scal) { return scal[kVarDone] != 0.0; }
+
+// vertical metrics of level k
+struct Lev {
+  bool top, bot;      // a face above / below inside the domain
+  double dz, rdz, ct, cb, za, zb, zam, zbm;
+};
+
+__device__ __forceinline__ Lev level(const VarGrid& g, int k) {
+  Lev L;
+  L.top = k < g.nz - 1;
+  L.bot = k > 0;
+  L.dz = g.dz[k];
+  L.rdz = g.rdz[k];
+  L.ct = L.top ? g.rdzc[k] * L.rdz : 0.0;
+  L.cb = L.bot ? g.rdzc[k - 1] * L.rdz : 0.0;
+  L.za = g.za[k];       // 0 on the lid
+  L.zb = g.zb[k];
+  L.zam = L.bot ? g.za[k - 1] : 0.0;
+  L.zbm = L.bot ? g.zb[k - 1] : 0.0;
+  return L;
+}
+
 }  // namespace
 
-// r = D_rho(u*), p = 0, partial sums of dz r^2
+// r = D_rho(u*), p = 0, partial sums of dz r^2. Each thread walks up its
+// group of levels keeping rho and w of the level below in registers.
 __global__ void __launch_bounds__(kVarBlock) k_var_div(VarGrid g, const double* __restrict__ u,
                                                      const double* __restrict__ v, const double* __restrict__ w,
                                                      double* __restrict__ r, double* __restrict__ p,
                                                      double* __restrict__ part) {
-  const int k = blockIdx.y;
-  const long long pl = (long long)g.nx * g.ny;
-  const bool top = k < g.nz - 1, bot = k > 0;
-  const double rdz = g.rdz[k], dz = g.dz[k];
-  const double za = g.za[k], zb = g.zb[k];
-  const double zam = bot ? g.za[k - 1] : 0.0, zbm = bot ? g.zb[k - 1] : 0.0;
-  double acc = 0.0;
+  const Blk bk = var_block();
+  const Col c = columns(g, bk);
+  const long long nh = (long long)g.nx * g.ny;
+  const int k0 = level_begin<kVarLevels>(bk), k1 = level_end<kVarLevels>(g, bk);
+  double rdn[kVarPts], wdn[kVarPts], rc[kVarPts];
+  {
+    const long long b0 = (long long)k0 * nh, bd = k0 > 0 ? b0 - nh : b0;
 #pragma unroll
-  for (int t = 0; t < kVarPts; ++t) {
-    const Pt q = point(g, t);
-    if (!q.live) continue;
-    const double rc = g.rho[q.o];
-    const double rxe = 0.5 * (rc + g.rho[q.oe]), rxw = 0.5 * (g.rho[q.ow] + rc);
-    const double ryn = 0.5 * (rc + g.rho[q.on]), rys = 0.5 * (g.rho[q.os] + rc);
-    double div = (rxe * u[q.o] - rxw * u[q.ow]) * g.rdx + (ryn * v[q.o] - rys * v[q.os]) * g.rdy;
-    double ft = 0.0, fb = 0.0;
-    if (top) ft = (za * rc + zb * g.rho[q.o + pl]) * w[q.o];
-    if (bot) fb = (zam * g.rho[q.o - pl] + zbm * rc) * w[q.o - pl];
-    div += (ft - fb) * rdz;
-    r[q.o] = div;
-    p[q.o] = 0.0;
-    acc += dz * div * div;
+    for (int t = 0; t < kVarPts; ++t) {
+      rdn[t] = g.rho[bd + c.h[t]];
+      wdn[t] = w[bd + c.h[t]];
+      rc[t] = g.rho[b0 + c.h[t]];
+    }
   }
-  const double s = block_sum(acc);
+  double acc = 0.0;
+  for (int k = k0; k < k1; ++k) {
+    const Lev L = level(g, k);
+    const long long b = (long long)k * nh, bu = L.top ? b + nh : b;
+#pragma unroll
+    for (int t = 0; t < kVarPts; ++t) {
+      const double ru = g.rho[bu + c.h[t]], wc = w[b + c.h[t]];
+      const double rxe = 0.5 * (rc[t] + g.rho[b + c.he[t]]), rxw = 0.5 * (g.rho[b + c.hw[t]] + rc[t]);
+      const double ryn = 0.5 * (rc[t] + g.rho[b + c.hn[t]]), rys = 0.5 * (g.rho[b + c.hs[t]] + rc[t]);
+      // top and bottom face fluxes, selected away on the lids (whatever w holds there)
+      const double ft = L.top ? (L.za * rc[t] + L.zb * ru) * wc : 0.0;
+      const double fb = L.bot ? (L.zam * rdn[t] + L.zbm * rc[t]) * wdn[t] : 0.0;
+      const double div = (rxe * u[b + c.h[t]] - rxw * u[b + c.hw[t]]) * g.rdx +
+                         (ryn * v[b + c.h[t]] - rys * v[b + c.hs[t]]) * g.rdy + (ft - fb) * L.rdz;
+      if (c.live[t]) {
+        r[b + c.h[t]] = div;
+        p[b + c.h[t]] = 0.0;
+        acc += L.dz * div * div;
+      }
+      rdn[t] = rc[t];
+      rc[t] = ru;
+      wdn[t] = wc;
+    }
+  }
+  const double s = block_sum<kVarBlock>(acc);
   if (threadIdx.x == 0) part[part_index()] = s;
 }
 
-// q = D_rho(G d), partial sums of dz d q
-__global__ void __launch_bounds__(kVarBlock) k_var_apply(VarGrid g, const double* __restrict__ d,
-                                                       double* __restrict__ q, double* __restrict__ part) {
-  const int k = blockIdx.y;
-  const long long pl = (long long)g.nx * g.ny;
-  const bool top = k < g.nz - 1, bot = k > 0;
-  const double rdz = g.rdz[k], dz = g.dz[k];
-  const double ct = top ? g.rdzc[k] * rdz : 0.0, cb = bot ? g.rdzc[k - 1] * rdz : 0.0;
-  const double za = g.za[k], zb = g.zb[k];
-  const double zam = bot ? g.za[k - 1] : 0.0, zbm = bot ? g.zb[k - 1] : 0.0;
-  double acc = 0.0;
+// q = D_rho(G d), partial sums of dz d q; d and rho of the levels below and
+// above stay in registers as the thread walks up
+__global__ void __launch_bounds__(kVarBlock) k_var_apply(VarGrid g, const double* __restrict__ scal,
+                                                       const double* __restrict__ d, double* __restrict__ q,
+                                                       double* __restrict__ part) {
+  if (var_done(scal)) return;
+  const Blk bk = var_block();
+  const Col c = columns(g, bk);
+  const long long nh = (long long)g.nx * g.ny;
+  const int k0 = level_begin<kVarLevels>(bk), k1 = level_end<kVarLevels>(g, bk);
+  double ddn[kVarPts], rdn[kVarPts], dc[kVarPts], rc[kVarPts];
+  {
+    const long long b0 = (long long)k0 * nh, bd = k0 > 0 ? b0 - nh : b0;
 #pragma unroll
-  for (int t = 0; t < kVarPts; ++t) {
-    const Pt x = point(g, t);
-    if (!x.live) continue;
-    const double rc = g.rho[x.o], dc = d[x.o];
-    const double rxe = 0.5 * (rc + g.rho[x.oe]), rxw = 0.5 * (g.rho[x.ow] + rc);
-    const double ryn = 0.5 * (rc + g.rho[x.on]), rys = 0.5 * (g.rho[x.os] + rc);
-    double a = (rxe * (d[x.oe] - dc) - rxw * (dc - d[x.ow])) * g.rdx2 +
-               (ryn * (d[x.on] - dc) - rys * (dc - d[x.os])) * g.rdy2;
-    if (top) a += (za * rc + zb * g.rho[x.o + pl]) * (d[x.o + pl] - dc) * ct;
-    if (bot) a -= (zam * g.rho[x.o - pl] + zbm * rc) * (dc - d[x.o - pl]) * cb;
-    q[x.o] = a;
-    acc += dz * dc * a;
+    for (int t = 0; t < kVarPts; ++t) {
+      ddn[t] = d[bd + c.h[t]];
+      rdn[t] = g.rho[bd + c.h[t]];
+      dc[t] = d[b0 + c.h[t]];
+      rc[t] = g.rho[b0 + c.h[t]];
+    }
   }
-  const double s = block_sum(acc);
+  double acc = 0.0;
+  for (int k = k0; k < k1; ++k) {
+    const Lev L = level(g, k);
+    const long long b = (long long)k * nh, bu = L.top ? b + nh : b;
+#pragma unroll
+    for (int t = 0; t < kVarPts; ++t) {
+      const double du = d[bu + c.h[t]], ru = g.rho[bu + c.h[t]];
+      const double rxe = 0.5 * (rc[t] + g.rho[b + c.he[t]]), rxw = 0.5 * (g.rho[b + c.hw[t]] + rc[t]);
+      const double ryn = 0.5 * (rc[t] + g.rho[b + c.hn[t]]), rys = 0.5 * (g.rho[b + c.hs[t]] + rc[t]);
+      const double rzt = L.za * rc[t] + L.zb * ru;          // 0 on the lid
+      const double rzb = L.zam * rdn[t] + L.zbm * rc[t];    // 0 at k = 0
+      const double a = (rxe * (d[b + c.he[t]] - dc[t]) - rxw * (dc[t] - d[b + c.hw[t]])) * g.rdx2 +
+                       (ryn * (d[b + c.hn[t]] - dc[t]) - rys * (dc[t] - d[b + c.hs[t]])) * g.rdy2 +
+                       rzt * (du - dc[t]) * L.ct - rzb * (dc[t] - ddn[t]) * L.cb;
+      if (c.live[t]) {
+        q[b + c.h[t]] = a;
+        acc += L.dz * dc[t] * a;
+      }
+      ddn[t] = dc[t];
+      dc[t] = du;
+      rdn[t] = rc[t];
+      rc[t] = ru;
+    }
+  }
+  const double s = block_sum<kVarBlock>(acc);
   if (threadIdx.x == 0) part[part_index()] = s;
 }
 
@@ -135,41 +219,59 @@ __global__ void __launch_bounds__(kVarBlock) k_var_update(VarGrid g, const doubl
                                                         double* __restrict__ p, double* __restrict__ r,
                                                         const double* __restrict__ d, const double* __restrict__ q,
                                                         double* __restrict__ part) {
+  if (var_done(scal)) return;
   const double rz = scal[var_slot(it, kVarRZ)], dq = scal[var_slot(it, kVarDQ)];
   const double alpha = dq != 0.0 ? rz / dq : 0.0;
-  const double dz = g.dz[blockIdx.y];
+  const Blk bk = var_block();
+  const Col c = columns(g, bk);
+  const long long nh = (long long)g.nx * g.ny;
   double acc = 0.0;
+  for (int k = level_begin<1>(bk), k1 = level_end<1>(g, bk); k < k1; ++k) {
+    const long long b = (long long)k * nh;
+    const double dz = g.dz[k];
 #pragma unroll
-  for (int t = 0; t < kVarPts; ++t) {
-    const Pt x = point(g, t);
-    if (!x.live) continue;
-    p[x.o] += alpha * d[x.o];
-    const double rn = r[x.o] - alpha * q[x.o];
-    r[x.o] = rn;
-    acc += dz * rn * rn;
+    for (int t = 0; t < kVarPts; ++t) {
+      const long long o = b + c.h[t];
+      const double pn = p[o] + alpha * d[o];
+      const double rn = r[o] - alpha * q[o];
+      if (c.live[t]) {
+        p[o] = pn;
+        r[o] = rn;
+        acc += dz * rn * rn;
+      }
+    }
   }
-  const double s = block_sum(acc);
+  const double s = block_sum<kVarBlock>(acc);
   if (threadIdx.x == 0) part[part_index()] = s;
 }
 
 // partial sums of dz r z and dz z q (the second for the flexible update)
 template <typename ZT>
-__global__ void __launch_bounds__(kVarBlock) k_var_dots(VarGrid g, const double* __restrict__ r,
-                                                      const ZT* __restrict__ z, const double* __restrict__ q,
-                                                      double* __restrict__ part0, double* __restrict__ part1) {
-  const double dz = g.dz[blockIdx.y];
+__global__ void __launch_bounds__(kVarBlock) k_var_dots(VarGrid g, const double* __restrict__ scal,
+                                                      const double* __restrict__ r, const ZT* __restrict__ z,
+                                                      const double* __restrict__ q, double* __restrict__ part0,
+                                                      double* __restrict__ part1) {
+  if (var_done(scal)) return;
+  const Blk bk = var_block();
+  const Col c = columns(g, bk);
+  const long long nh = (long long)g.nx * g.ny;
   double a0 = 0.0, a1 = 0.0;
+  for (int k = level_begin<1>(bk), k1 = level_end<1>(g, bk); k < k1; ++k) {
+    const long long b = (long long)k * nh;
+    const double dz = g.dz[k];
 #pragma unroll
-  for (int t = 0; t < kVarPts; ++t) {
-    const Pt x = point(g, t);
-    if (!x.live) continue;
-    const double zc = (double)z[x.o];
-    a0 += dz * r[x.o] * zc;
-    a1 += dz * zc * q[x.o];
+    for (int t = 0; t < kVarPts; ++t) {
+      const long long o = b + c.h[t];
+      const double zc = (double)z[o], rc = r[o], qc = q[o];
+      if (c.live[t]) {
+        a0 += dz * rc * zc;
+        a1 += dz * zc * qc;
+      }
+    }
   }
-  const double s0 = block_sum(a0);
+  const double s0 = block_sum<kVarBlock>(a0);
   __syncthreads();  // block_sum's LDS is reused
-  const double s1 = block_sum(a1);
+  const double s1 = block_sum<kVarBlock>(a1);
   if (threadIdx.x == 0) {
     part0[part_index()] = s0;
     part1[part_index()] = s1;
@@ -180,31 +282,46 @@ __global__ void __launch_bounds__(kVarBlock) k_var_dots(VarGrid g, const double*
 template <typename ZT>
 __global__ void __launch_bounds__(kVarBlock) k_var_dir(VarGrid g, const double* __restrict__ scal, int it,
                                                      const ZT* __restrict__ z, double* __restrict__ d) {
+  if (var_done(scal)) return;
   double beta = 0.0;
   if (it > 0) {
     const double rzp = scal[var_slot(it - 1, kVarRZ)], dqp = scal[var_slot(it - 1, kVarDQ)];
     const double alpha = dqp != 0.0 ? rzp / dqp : 0.0;
     beta = rzp != 0.0 ? -alpha * scal[var_slot(it, kVarZQ)] / rzp : 0.0;
   }
+  const Blk bk = var_block();
+  const Col c = columns(g, bk);
+  const long long nh = (long long)g.nx * g.ny;
+  for (int k = level_begin<1>(bk), k1 = level_end<1>(g, bk); k < k1; ++k) {
+    const long long b = (long long)k * nh;
 #pragma unroll
-  for (int t = 0; t < kVarPts; ++t) {
-    const Pt x = point(g, t);
-    if (!x.live) continue;
-    d[x.o] = (double)z[x.o] + (it > 0 ? beta * d[x.o] : 0.0);
+    for (int t = 0; t < kVarPts; ++t) {
+      const long long o = b + c.h[t];
+      const double zc = (double)z[o];
+      // d is not yet defined at it = 0
+      const double dn = it > 0 ? zc + beta * d[o] : zc;
+      if (c.live[t]) d[o] = dn;
+    }
   }
 }
 
 // partial sums of dz p (the gauge)
 __global__ void __launch_bounds__(kVarBlock) k_var_wsum(VarGrid g, const double* __restrict__ p,
                                                       double* __restrict__ part) {
-  const double dz = g.dz[blockIdx.y];
+  const Blk bk = var_block();
+  const Col c = columns(g, bk);
+  const long long nh = (long long)g.nx * g.ny;
   double acc = 0.0;
+  for (int k = level_begin<1>(bk), k1 = level_end<1>(g, bk); k < k1; ++k) {
+    const long long b = (long long)k * nh;
+    const double dz = g.dz[k];
 #pragma unroll
-  for (int t = 0; t < kVarPts; ++t) {
-    const Pt x = point(g, t);
-    if (x.live) acc += dz * p[x.o];
+    for (int t = 0; t < kVarPts; ++t) {
+      const double pc = p[b + c.h[t]];
+      if (c.live[t]) acc += dz * pc;
+    }
   }
-  const double s = block_sum(acc);
+  const double s = block_sum<kVarBlock>(acc);
   if (threadIdx.x == 0) part[part_index()] = s;
 }
 
@@ -212,20 +329,59 @@ __global__ void __launch_bounds__(kVarBlock) k_var_wsum(VarGrid g, const double*
 __global__ void __launch_bounds__(kVarBlock) k_var_shift(VarGrid g, const double* __restrict__ scal, int slot,
                                                        double rw, double* __restrict__ p) {
   const double m = scal[slot] * rw;
+  const Blk bk = var_block();
+  const Col c = columns(g, bk);
+  const long long nh = (long long)g.nx * g.ny;
+  for (int k = level_begin<1>(bk), k1 = level_end<1>(g, bk); k < k1; ++k) {
+    const long long b = (long long)k * nh;
 #pragma unroll
-  for (int t = 0; t < kVarPts; ++t) {
-    const Pt x = point(g, t);
-    if (x.live) p[x.o] -= m;
+    for (int t = 0; t < kVarPts; ++t) {
+      const double pn = p[b + c.h[t]] - m;
+      if (c.live[t]) p[b + c.h[t]] = pn;
+    }
   }
 }
 
-// scal[slot] = sum of part[0 .. n) in a fixed order (one workgroup)
-__global__ void __launch_bounds__(kVarBlock) k_var_finish(const double* __restrict__ part, long long n,
-                                                        double* __restrict__ scal, int slot) {
+// sum of part[0 .. n) in a fixed order (one workgroup of kVarFinishBlock threads)
+__device__ __forceinline__ double finish_sum(const double* __restrict__ part, long long n) {
   double acc = 0.0;
-  for (long long i = threadIdx.x; i < n; i += kVarBlock) acc += part[i];
-  const double s = block_sum(acc);
-  if (threadIdx.x == 0) scal[slot] = s;
+  for (long long i = threadIdx.x; i < n; i += 4 * kVarFinishBlock) {
+    double a[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const long long ie = i + (long long)e * kVarFinishBlock;
+      a[e] = ie < n ? part[ie] : 0.0;
+    }
+    acc += (a[0] + a[1]) + (a[2] + a[3]);
+  }
+  return block_sum<kVarFinishBlock>(acc);
+}
+
+__global__ void __launch_bounds__(kVarFinishBlock) k_var_finish(const double* __restrict__ part0,
+                                                              const double* __restrict__ part1, long long n,
+                                                              double* __restrict__ scal, int slot0, int slot1,
+                                                              int gated) {
+  if (gated && var_done(scal)) return;
+  const double s0 = finish_sum(part0, n);
+  if (threadIdx.x == 0) scal[slot0] = s0;
+  if (part1) {
+    __syncthreads();  // block_sum's LDS is reused
+    const double s1 = finish_sum(part1, n);
+    if (threadIdx.x == 0) scal[slot1] = s1;
+  }
+}
+
+__global__ void __launch_bounds__(kVarFinishBlock) k_var_finish_rr(const double* __restrict__ part, long long n,
+                                                                 double* __restrict__ scal, int it, double tol2) {
+  if (var_done(scal)) return;
+  const double rr = finish_sum(part, n);
+  if (threadIdx.x == 0) {
+    scal[var_slot(it, kVarRR)] = rr;
+    scal[kVarLast] = (double)it;
+    scal[kVarLastRR] = rr;
+    if (!isfinite(rr)) scal[kVarDone] = 2.0;
+    else if (rr <= tol2 * scal[var_slot(0, kVarRR)]) scal[kVarDone] = 1.0;
+  }
 }
 
 __global__ void k_var_zero(double* __restrict__ x, int n) {
@@ -236,15 +392,20 @@ __global__ void k_var_zero(double* __restrict__ x, int n) {
 // ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
+// the stencil kernels' grid (level groups of kVarLevels) and the pointwise
+// kernels' grid (one level per workgroup)
+static dim3 var_grid_stencil(const VarGrid& g) {
+  return dim3((unsigned)var_blocks_per_level(g.nx, g.ny), (unsigned)var_level_groups(g.nz));
+}
 static dim3 var_grid(const VarGrid& g) { return dim3((unsigned)var_blocks_per_level(g.nx, g.ny), (unsigned)g.nz); }
 
 void launch_var_div(const VarGrid& g, const double* u, const double* v, const double* w, double* r, double* p,
                     double* part, void* stream) {
-  hipLaunchKernelGGL(k_var_div, var_grid(g), dim3(kVarBlock), 0, (hipStream_t)stream, g, u, v, w, r, p, part);
+  hipLaunchKernelGGL(k_var_div, var_grid_stencil(g), dim3(kVarBlock), 0, (hipStream_t)stream, g, u, v, w, r, p, part);
 }
 
-void launch_var_apply(const VarGrid& g, const double* d, double* q, double* part, void* stream) {
-  hipLaunchKernelGGL(k_var_apply, var_grid(g), dim3(kVarBlock), 0, (hipStream_t)stream, g, d, q, part);
+void launch_var_apply(const VarGrid& g, const double* scal, const double* d, double* q, double* part, void* stream) {
+  hipLaunchKernelGGL(k_var_apply, var_grid_stencil(g), dim3(kVarBlock), 0, (hipStream_t)stream, g, scal, d, q, part);
 }
 
 void launch_var_update(const VarGrid& g, const double* scal, int it, double* p, double* r, const double* d,
@@ -253,13 +414,13 @@ void launch_var_update(const VarGrid& g, const double* scal, int it, double* p, 
                      part);
 }
 
-void launch_var_dots(const VarGrid& g, const double* r, const void* z, bool z64, const double* q, double* part0,
-                     double* part1, void* stream) {
+void launch_var_dots(const VarGrid& g, const double* scal, const double* r, const void* z, bool z64, const double* q,
+                     double* part0, double* part1, void* stream) {
   if (z64)
-    hipLaunchKernelGGL(k_var_dots<double>, var_grid(g), dim3(kVarBlock), 0, (hipStream_t)stream, g, r,
+    hipLaunchKernelGGL(k_var_dots<double>, var_grid(g), dim3(kVarBlock), 0, (hipStream_t)stream, g, scal, r,
                        static_cast<const double*>(z), q, part0, part1);
   else
-    hipLaunchKernelGGL(k_var_dots<float>, var_grid(g), dim3(kVarBlock), 0, (hipStream_t)stream, g, r,
+    hipLaunchKernelGGL(k_var_dots<float>, var_grid(g), dim3(kVarBlock), 0, (hipStream_t)stream, g, scal, r,
                        static_cast<const float*>(z), q, part0, part1);
 }
 
@@ -280,8 +441,15 @@ void launch_var_shift(const VarGrid& g, const double* scal, int slot, double rw,
   hipLaunchKernelGGL(k_var_shift, var_grid(g), dim3(kVarBlock), 0, (hipStream_t)stream, g, scal, slot, rw, p);
 }
 
-void launch_var_finish(const double* part, long long n, double* scal, int slot, void* stream) {
-  hipLaunchKernelGGL(k_var_finish, dim3(1), dim3(kVarBlock), 0, (hipStream_t)stream, part, n, scal, slot);
+void launch_var_finish(const double* part0, const double* part1, long long n, double* scal, int slot0, int slot1,
+                       bool gated, void* stream) {
+  hipLaunchKernelGGL(k_var_finish, dim3(1), dim3(kVarFinishBlock), 0, (hipStream_t)stream, part0, part1, n, scal,
+                     slot0, slot1, gated ? 1 : 0);
+}
+
+void launch_var_finish_rr(const double* part, long long n, double* scal, int it, double tol2, void* stream) {
+  hipLaunchKernelGGL(k_var_finish_rr, dim3(1), dim3(kVarFinishBlock), 0, (hipStream_t)stream, part, n, scal, it,
+                     tol2);
 }
 
 void launch_var_zero(double* x, int n, void* stream) {

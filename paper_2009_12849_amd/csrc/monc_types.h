@@ -117,6 +117,10 @@ struct MemberDesc {
   unsigned bst_mul;       // x / bst = (umulhi(x, bst_mul) + x) >> bst_shift for 31-bit x
   int bst_shift;
   void* spec;             // spectral workspace, nz levels of `plane` complex values
+  // null, or (the preconditioner's copy of the descriptor) the Krylov
+  // solver's converged flag: while *skip != 0 the FFT and tridiagonal
+  // kernels do nothing
+  const double* skip;
   float* prem;            // mixed path: remainder (p1 + delta) - fl32(p1 + delta) in FP32, (nz, ny, nx)
 };
 
