@@ -172,3 +172,27 @@ def test_full_size_variable_density(name):
     for f in range(3):
         assert np.abs(outs["f64"][f] - outs["mixed"][f]).max() <= 1e-6 * scale
     assert np.abs(outs["f64"][3] - outs["mixed"][3]).max() <= 1e-5 * np.abs(outs["f64"][3]).max()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "mixed"])
+@pytest.mark.parametrize("shape", [(48, 1, 1), (96, 8, 5)])
+def test_x_only_density_closed_form(shape, dtype):
+    """rho and u* of x alone: u = C / rx (harmonic-mean flux) and p in
+    closed form (see tests/test_oracle_pins.py, _x_only_case)."""
+    from tests.test_oracle_pins import _x_only_case
+    dx, dy, dz, rho, u, z, uo, po = _x_only_case(*shape, seed=36)
+    nz, ny, nx = rho.shape
+    plan = monc.Plan(nx, ny, nz, dx, dy, dz, rho.mean(axis=(1, 2)), dtype)
+    t = [_t(a) for a in (u, z, z)]
+    p = torch.empty_like(t[0])
+    it, rel = plan.project_var(_t(rho), *t, p, tol=TOL, maxit=200)
+    torch.cuda.synchronize()
+    plan.close()
+    outs = [x.cpu().numpy() for x in t + [p]]
+    assert rel <= TOL
+    assert np.abs(outs[0] - uo).max() <= 1e-10 * np.abs(uo).max()
+    # v and w are zero up to the rounding of the transforms of row- and
+    # level-constant fields
+    assert np.abs(outs[1]).max() <= 1e-10 * np.abs(uo).max()
+    assert np.abs(outs[2]).max() <= 1e-10 * np.abs(uo).max()
+    assert np.abs(outs[3] - po).max() <= 1e-9 * np.abs(po).max()

@@ -495,3 +495,34 @@ def test_variable_projection_reduces_to_separable():
     ref = oracle.project(u, v, w, g.dx, g.dy, g.dz, g.rho0)
     for a, b in zip(got, ref):
         np.testing.assert_allclose(a, b, rtol=0, atol=1e-11 * max(np.abs(b).max(), 1.0))
+
+
+def _x_only_case(nx, ny, nz, seed):
+    """rho and u* functions of x alone (the same on every row and level),
+    v* = w* = 0. The projected flux rx_i u_i is then the same constant C on
+    every east face: the periodic sum of the gradient vanishes, so
+    C = sum_i u*_i / sum_i 1/rx_i and u_i = C / rx_i (a harmonic mean);
+    p_{i+1} - p_i = dx (u*_i - u_i), with zero mean (the gauge)."""
+    rng = np.random.default_rng(seed)
+    dx, dy = 40.0, 30.0
+    dz = 10.0 * 1.1 ** np.arange(nz)
+    r1 = 1.0 + 0.5 * rng.uniform(-1.0, 1.0, nx)
+    u1 = rng.standard_normal(nx)
+    rho = np.broadcast_to(r1, (nz, ny, nx)).copy()
+    u = np.broadcast_to(u1, (nz, ny, nx)).copy()
+    z = np.zeros((nz, ny, nx))
+    rx = 0.5 * (r1 + np.roll(r1, -1))
+    C = u1.sum() / np.sum(1.0 / rx)
+    uo = C / rx
+    p1 = np.concatenate([[0.0], np.cumsum(dx * (u1 - uo))[:-1]])
+    p1 -= p1.mean()
+    return dx, dy, dz, rho, u, z, np.broadcast_to(uo, (nz, ny, nx)), np.broadcast_to(p1, (nz, ny, nx))
+
+
+@pytest.mark.parametrize("shape", [(12, 1, 1), (9, 4, 3)])
+def test_variable_projection_x_only_closed_form(shape):
+    dx, dy, dz, rho, u, z, uo, po = _x_only_case(*shape, seed=35)
+    got = oracle.project_var(u, z, z, dx, dy, dz, rho)
+    np.testing.assert_allclose(got[0], uo, rtol=0, atol=1e-12 * np.abs(uo).max())
+    assert np.abs(got[1]).max() <= 1e-12 and np.abs(got[2]).max() <= 1e-12
+    np.testing.assert_allclose(got[3], po, rtol=0, atol=1e-11 * np.abs(po).max())
