@@ -31,7 +31,8 @@
  * Thread safety: all functions may be called from several host threads; a
  * plan (and a batch) must not be used by two calls that overlap in time
  * (one workspace per plan). Every enqueueing call is asynchronous on the
- * given stream and never synchronises the host.
+ * given stream and never synchronises the host, except monc_project_var,
+ * which reads its solver's status from the device.
  */
 #ifndef MONC_H
 #define MONC_H
@@ -161,8 +162,13 @@ int monc_project_reduce(monc_plan* plan, void* u, void* v, void* w, void* p, dou
  * taken and the final ||r||/||D_rho(u*)||; reaching maxit is not an error,
  * the caller compares *relres with tol. Work vectors (four fields) are
  * allocated on the plan by the first call and freed with it.
- * Unlike the other entry points this one synchronises the stream once per
- * iteration, to read the residual norm.
+ * Unlike the other entry points this one synchronises the stream: the
+ * residual-norm reduction decides convergence on the device (later kernels
+ * of the solve then do nothing), and the host reads the solver's status once
+ * per batch of queued iterations (two or three reads for a typical solve).
+ * The per-iteration scalars and the preconditioner's copy of the plan's
+ * descriptor live in the plan's work vectors, so calls on one plan must not
+ * overlap (as for every entry point).
  * Returns MONC_OK, MONC_EINVAL (bad argument, non-finite input, breakdown),
  * MONC_ENOMEM or MONC_EHIP.
  */
