@@ -215,13 +215,14 @@ def measure(runner, steps, warmup, workload, nx_bytes):
 def var_iteration_bytes_per_point(nx, mixed):
     """Algorithmic HBM bytes per grid point of one conjugate-gradient
     iteration of the variable-density projection: the operator (read d and
-    rho, write q), the update (read p, d, r, q; write p, r), the spectral
-    preconditioner (read r, the spectrum's four round trips, write z in the
-    plan's storage type), the two inner products (read r, z, q) and the
-    direction update (read z, d; write d). FP64 136 + 64f, mixed 124 + 32f."""
+    rho, write q), the update (read p, d, r, q and the FP32 scaling s; write
+    p, r), the spectral preconditioner (read r, the spectrum's four round
+    trips, write z in the plan's storage type), the two inner products (read
+    r, z, q, s) and the direction update (read z, d, s; write d).
+    FP64 148 + 64f, mixed 136 + 32f."""
     f = spectral_words(nx)
     wb = 4.0 if mixed else 8.0
-    return 24 + 48 + (8 + 8 * f * wb + wb) + (16 + wb) + (16 + wb)
+    return 24 + (48 + 4) + (8 + 8 * f * wb + wb) + (16 + wb + 4) + (16 + wb + 4)
 
 
 def variable_density(monc, torch, member, reps=3, tol=1e-10, amp=0.2):

@@ -728,9 +728,10 @@ static constexpr int kVarMaxIt = 10000;
 // Work vectors of one plan, carved from one allocation: r, d, q (FP64
 // fields), z (storage type), two partial-sum arrays, the scalars (status
 // row and one row per iteration), the vertical interpolation weights za, zb,
-// and the preconditioner's device descriptor.
+// the preconditioner's device descriptor and its scaling field s (FP32).
 struct VarWs {
   double *r, *d, *q, *part0, *part1, *scal, *za, *zb;
+  float* s;
   void* z;
   MemberDesc* desc;
 };
@@ -740,10 +741,10 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 static int var_workspace(monc_plan* pl, VarWs* ws) {
   const size_t n = (size_t)pl->nx * pl->ny * pl->nz;
   const size_t nparts = (size_t)var_point_parts(pl->nx, pl->ny, pl->nz);  // the larger count
-  constexpr int kParts = 10;
+  constexpr int kParts = 11;
   const size_t sizes[kParts] = {n * 8, n * 8, n * 8, n * elem_bytes(pl->dtype), nparts * 8, nparts * 8,
                                 (size_t)(kVarMaxIt + 2) * kVarSlots * 8, (size_t)pl->nz * 8, (size_t)pl->nz * 8,
-                                sizeof(MemberDesc)};
+                                sizeof(MemberDesc), n * 4};
   size_t off[kParts], total = 0;
   for (int i = 0; i < kParts; ++i) {
     off[i] = total;
@@ -781,6 +782,7 @@ static int var_workspace(monc_plan* pl, VarWs* ws) {
   ws->za = reinterpret_cast<double*>(b + off[7]);
   ws->zb = reinterpret_cast<double*>(b + off[8]);
   ws->desc = reinterpret_cast<MemberDesc*>(b + off[9]);
+  ws->s = reinterpret_cast<float*>(b + off[10]);
   return MONC_OK;
 }
 
@@ -838,6 +840,8 @@ extern "C" int monc_project_var(monc_plan* pl, const double* rho, double* u, dou
   g.rdzc = h.rdzc;
   g.za = ws.za;
   g.zb = ws.zb;
+  g.rho0 = h.rho0;
+  g.s = ws.s;
   const long long np_st = var_stencil_parts(pl->nx, pl->ny, pl->nz);  // partials of the stencil kernels
   const long long np_pt = var_point_parts(pl->nx, pl->ny, pl->nz);    // partials of the pointwise kernels
   const bool z64 = pl->dtype == MONC_FP64;

@@ -48,6 +48,23 @@ def _wnorm(x, dz):
     return np.sqrt(np.sum(np.asarray(dz)[:, None, None] * x * x))
 
 
+def _cond_estimate(nx, ny, dx, dy, dz, contrast=1.5):
+    """Condition number of D_rho G estimated from the grid: largest
+    eigenvalue 4/dx^2 + 4/dy^2 + 4/(min dz min dzc), smallest that of the
+    longest horizontal or vertical mode, times the density contrast. Two
+    solutions that meet a relative residual tol differ by at most about
+    tol times this, relative to the solution."""
+    dz = np.asarray(dz, dtype=np.float64)
+    dzc = 0.5 * (dz[:-1] + dz[1:]) if dz.size > 1 else dz
+    lmax = 4 / dx ** 2 + 4 / dy ** 2 + 4 / (dz.min() * dzc.min())
+    modes = [(np.pi / dz.sum()) ** 2]
+    if nx > 1:
+        modes.append((2 * np.pi / (nx * dx)) ** 2)
+    if ny > 1:
+        modes.append((2 * np.pi / (ny * dy)) ** 2)
+    return contrast * lmax / min(modes)
+
+
 def _run(g, rho, u, v, w, dtype, tol=TOL, maxit=200):
     plan = _plan(g, rho, dtype)
     t = [_t(a) for a in (u, v, w)]
@@ -166,14 +183,9 @@ def test_full_size_variable_density(name):
         pw = np.abs(o[3]).max() * np.sum(dz) * g.nx * g.ny
         assert abs(np.sum(dz[:, None, None] * o[3])) <= 1e-12 * pw
         outs[dtype] = o
-    # The two answers differ by at most the solver tolerance times the
-    # operator's condition number; estimated from the grid: largest
-    # eigenvalue 4/dx^2 + 4/dy^2 + 4/(min dz min dzc), smallest that of the
-    # longest horizontal or vertical mode, density contrast (1.2/0.8)
-    dzc = 0.5 * (dz[:-1] + dz[1:])
-    lmax = 4 / g.dx ** 2 + 4 / g.dy ** 2 + 4 / (dz.min() * dzc.min())
-    lmin = min((2 * np.pi / (g.nx * g.dx)) ** 2, (2 * np.pi / (g.ny * g.dy)) ** 2, (np.pi / dz.sum()) ** 2)
-    cond = 1.5 * lmax / lmin
+    # the two answers differ by at most the solver tolerance times the
+    # operator's condition number (density contrast 1.2/0.8)
+    cond = _cond_estimate(g.nx, g.ny, g.dx, g.dy, dz)
     scale = max(np.abs(a).max() for a in (u, v, w))
     du = max(np.abs(outs["f64"][f] - outs["mixed"][f]).max() for f in range(3)) / scale
     dp = np.abs(outs["f64"][3] - outs["mixed"][3]).max() / np.abs(outs["f64"][3]).max()
@@ -197,9 +209,14 @@ def test_x_only_density_closed_form(shape, dtype):
     plan.close()
     outs = [x.cpu().numpy() for x in t + [p]]
     assert rel <= TOL
-    assert np.abs(outs[0] - uo).max() <= 1e-10 * np.abs(uo).max()
-    # v and w are zero up to the rounding of the transforms of row- and
-    # level-constant fields
-    assert np.abs(outs[1]).max() <= 1e-10 * np.abs(uo).max()
-    assert np.abs(outs[2]).max() <= 1e-10 * np.abs(uo).max()
-    assert np.abs(outs[3] - po).max() <= 1e-9 * np.abs(po).max()
+    # within TOL times the condition estimate (density contrast 1.5/0.5);
+    # v and w are zero up to that and the rounding of the transforms of row-
+    # and level-constant fields
+    bound = max(TOL * _cond_estimate(nx, ny, dx, dy, dz, contrast=3.0), 1e-12)
+    print(f"  bound {bound:.1e}: u {np.abs(outs[0] - uo).max() / np.abs(uo).max():.1e}, "
+          f"v {np.abs(outs[1]).max() / np.abs(uo).max():.1e}, w {np.abs(outs[2]).max() / np.abs(uo).max():.1e}, "
+          f"p {np.abs(outs[3] - po).max() / np.abs(po).max():.1e}", flush=True)
+    assert np.abs(outs[0] - uo).max() <= bound * np.abs(uo).max()
+    assert np.abs(outs[1]).max() <= bound * np.abs(uo).max()
+    assert np.abs(outs[2]).max() <= bound * np.abs(uo).max()
+    assert np.abs(outs[3] - po).max() <= bound * np.abs(po).max()
