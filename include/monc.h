@@ -63,7 +63,7 @@ enum {
   MONC_EHIP = -4           /* a HIP runtime call or launch failed            */
 };
 
-/* Limits of this build: nx, ny in [1, 8192] with no prime factor above 3
+/* Limits of the library: nx, ny in [1, 8192] with no prime factor above 3
  * (FFT radices 2, 3, 4, 8); nz in [1, 1024]; batches of 1..256 members. */
 #define MONC_MAX_N 8192
 #define MONC_MAX_NZ 1024
