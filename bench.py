@@ -225,13 +225,20 @@ def var_iteration_bytes_per_point(nx, mixed):
     return 24 + (48 + 4) + (8 + 8 * f * wb + wb) + (16 + wb + 4) + (16 + wb + 4)
 
 
-def variable_density(monc, torch, member, reps=3, tol=1e-10, amp=0.2):
+def variable_density(monc, torch, member, reps=3, tol=1e-10, amp=0.2, strong=0.5):
     """The variable-density projection (conjugate gradients, the spectral
     solve as preconditioner) on the workload's grid and fields with a
     density rho0(z) (1 + amp f(x, y, z)), |f| <= 1: per preconditioner
     precision the median wall time of `reps` solves from the same inputs
     (inputs copied in before each, outside the timing), iterations,
-    relative residual and the per-iteration HBM fraction."""
+    relative residual and the per-iteration HBM fraction; then the same
+    with a stronger contrast (amp = `strong`) under "stronger_contrast"."""
+    out = _variable_density_case(monc, torch, member, reps, tol, amp)
+    out["stronger_contrast"] = _variable_density_case(monc, torch, member, reps, tol, strong)
+    return out
+
+
+def _variable_density_case(monc, torch, member, reps, tol, amp):
     import synth
     g = member.grid
     rho_np = synth.density_field(np.random.default_rng(6100), g, amp)
@@ -242,7 +249,7 @@ def variable_density(monc, torch, member, reps=3, tol=1e-10, amp=0.2):
     work = [torch.empty_like(src[0]) for _ in range(4)]
     out = {"what": f"D_rho(G p) = D_rho(u*) with rho = rho0(z)(1 + {amp} f(x,y,z)), FP64 conjugate gradients, "
                    f"the spectral solve as preconditioner, stop at relative residual {tol}",
-           "tol": tol}
+           "tol": tol, "amp": amp}
     for dtype in ("f64", "mixed"):
         plan = monc.Plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, rho.mean(dim=(1, 2)).cpu().numpy(), dtype)
         plan.autotune()

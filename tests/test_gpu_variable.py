@@ -220,3 +220,19 @@ def test_x_only_density_closed_form(shape, dtype):
     assert np.abs(outs[1]).max() <= bound * np.abs(uo).max()
     assert np.abs(outs[2]).max() <= bound * np.abs(uo).max()
     assert np.abs(outs[3] - po).max() <= bound * np.abs(po).max()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "mixed"])
+def test_strong_contrast_matches_direct_solve(dtype):
+    """Density varying by +-60 %: more iterations, the same answer."""
+    shape = (32, 24, 12)
+    g, rho, u, v, w = _case(shape, 1300, amp=0.6)
+    outs, it, rel = _run(g, rho, u, v, w, dtype)
+    print(f"  iterations {it}, relative residual {rel:.3e}", flush=True)
+    assert rel <= TOL and it < 200
+    ref = oracle.project_var(u, v, w, g.dx, g.dy, g.dz, rho)
+    scale = max(np.abs(a).max() for a in (u, v, w))
+    bound = TOL * _cond_estimate(g.nx, g.ny, g.dx, g.dy, g.dz, contrast=1.6 / 0.4)
+    for f in range(3):
+        assert np.abs(outs[f] - ref[f]).max() <= bound * scale, f
+    assert np.abs(outs[3] - ref[3]).max() <= bound * np.abs(ref[3]).max()
