@@ -236,3 +236,24 @@ def test_strong_contrast_matches_direct_solve(dtype):
     for f in range(3):
         assert np.abs(outs[f] - ref[f]).max() <= bound * scale, f
     assert np.abs(outs[3] - ref[3]).max() <= bound * np.abs(ref[3]).max()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "mixed"])
+def test_solve_is_deterministic(dtype):
+    """The inner products add per-workgroup partials in a fixed order (no
+    atomics): two solves of the same input on one plan are bitwise equal."""
+    g, rho, u, v, w = _case((64, 48, 20), 1400)
+    plan = _plan(g, rho, dtype)
+    r = _t(rho)
+    res = []
+    for _ in range(2):
+        t = [_t(a) for a in (u, v, w)]
+        p = torch.empty_like(t[0])
+        it, rel = plan.project_var(r, *t, p, tol=TOL, maxit=200)
+        torch.cuda.synchronize()
+        res.append(([x.cpu().numpy() for x in t + [p]], it, rel))
+    plan.close()
+    (o0, i0, r0), (o1, i1, r1) = res
+    assert i0 == i1 and r0 == r1
+    for a, b in zip(o0, o1):
+        assert np.array_equal(a, b)
