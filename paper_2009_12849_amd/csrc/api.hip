@@ -756,13 +756,8 @@ static int var_workspace(monc_plan* pl, VarWs* ws) {
       (void)hipGetLastError();
       return fail(MONC_ENOMEM, "monc_project_var: cannot allocate %zu bytes of work vectors", total);
     }
-    // za_k = dz_{k+1}/(dz_k + dz_{k+1}), zb_k = dz_k/(dz_k + dz_{k+1}), 0 on the lid
-    std::vector<double> za(pl->nz, 0.0), zb(pl->nz, 0.0);
-    for (int k = 0; k + 1 < pl->nz; ++k) {
-      const double s = pl->dz[k] + pl->dz[k + 1];
-      za[k] = pl->dz[k + 1] / s;
-      zb[k] = pl->dz[k] / s;
-    }
+    std::vector<double> za, zb;
+    face_weights(pl->nz, pl->dz.data(), za, zb);
     char* b = static_cast<char*>(pl->d_var);
     if (hipMemcpy(b + off[7], za.data(), pl->nz * 8, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(b + off[8], zb.data(), pl->nz * 8, hipMemcpyHostToDevice) != hipSuccess) {
@@ -918,10 +913,7 @@ extern "C" int monc_project_var(monc_plan* pl, const double* rho, double* u, dou
       it = (int)st[kVarLast];
       rel = std::sqrt(st[kVarLastRR] / rr0);
       if (st[kVarDone] != 0.0 || queued >= maxit) break;
-      const double rate = std::pow(rel / rel_prev, 1.0 / nb);
-      double want = (rate > 0.0 && rate < 1.0 && rel > 0.0) ? std::ceil(std::log(tol / rel) / std::log(rate)) : 1.0;
-      if (!(want >= 1.0)) want = 1.0;
-      batch = (int)std::min(want, 32.0);
+      batch = krylov_batch(rel, rel_prev, nb, tol, 32);
       rel_prev = rel;
     }
   }

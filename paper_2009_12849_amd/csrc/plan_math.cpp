@@ -170,4 +170,26 @@ void div_magic(unsigned d, unsigned& mul, int& shift) {
   mul = (unsigned)((((1ull << l) - d) << 32) / d + 1);
 }
 
+void face_weights(int nz, const double* dz, std::vector<double>& za, std::vector<double>& zb) {
+  za.assign(nz > 0 ? nz : 0, 0.0);
+  zb.assign(nz > 0 ? nz : 0, 0.0);
+  for (int k = 0; k + 1 < nz; ++k) {
+    const double s = dz[k] + dz[k + 1];
+    za[k] = dz[k + 1] / s;
+    zb[k] = dz[k] / s;
+  }
+}
+
+int krylov_batch(double rel, double rel_prev, int done, double tol, int cap) {
+  if (cap < 1) cap = 1;
+  if (!(done >= 1) || !(rel > 0.0) || !(rel_prev > 0.0)) return 1;
+  const double rate = std::pow(rel / rel_prev, 1.0 / done);
+  if (!(rate > 0.0 && rate < 1.0)) return 1;
+  if (!(tol > 0.0)) return cap;
+  // (a count that is whole up to rounding is not rounded up)
+  const double want = std::ceil(std::log(tol / rel) / std::log(rate) - 1e-9);
+  if (!(want >= 1.0)) return 1;
+  return want >= (double)cap ? cap : (int)want;
+}
+
 }  // namespace monc

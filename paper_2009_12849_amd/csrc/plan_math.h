@@ -44,4 +44,17 @@ std::vector<double> modified_wavenumbers(int n, int count, double h);
 // exp(-2 pi i t / n), t = 0 .. n-1, as interleaved (re, im).
 std::vector<double> twiddles(int n);
 
+// Weights of the linear interpolation in z of a cell-centred quantity q to
+// the top face of cell k: q_face = za_k q_k + zb_k q_{k+1} with
+// za_k = dz_{k+1}/(dz_k + dz_{k+1}), zb_k = dz_k/(dz_k + dz_{k+1}); both 0 on
+// the lid (k = nz-1), which has no face above.
+void face_weights(int nz, const double* dz, std::vector<double>& za, std::vector<double>& zb);
+
+// Iterations the Krylov solver queues before it next reads its status: the
+// count that the convergence rate over the last `done` iterations (relative
+// residual rel_prev before them, rel after) predicts to reach tol, at least 1
+// and at most cap; 1 when no rate can be measured (no decrease, or rel = 0),
+// cap when tol = 0.
+int krylov_batch(double rel, double rel_prev, int done, double tol, int cap);
+
 }  // namespace monc

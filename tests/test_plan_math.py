@@ -1,7 +1,8 @@
 """Host-side plan arithmetic of the library (csrc/plan_math.cpp), built with
 g++ on its own and driven by a small test program: the multiply-shift
-division used by the kernels' index math, the FFT radix plans, and the
-vertical and horizontal tables against the oracle's definitions."""
+division used by the kernels' index math, the FFT radix plans, the
+vertical and horizontal tables against the oracle's definitions, and the
+variable-density solver's face weights and batch prediction."""
 import os
 import shutil
 import subprocess
@@ -10,6 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
+import oracle.variable
 import synth
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -105,6 +107,13 @@ int main(int argc, char** argv) {
   for (double v : modified_wavenumbers(48, 25, 25.0)) std::printf("lx %.17g\n", v);
   std::vector<double> tw = twiddles(12);
   for (size_t i = 0; i < tw.size(); i += 2) std::printf("tw %.17g %.17g\n", tw[i], tw[i + 1]);
+  // 5. the variable-density solver's face weights and batch prediction
+  std::vector<double> za, zb;
+  face_weights(nz, dz.data(), za, zb);
+  for (int k = 0; k < nz; ++k) std::printf("fw %.17g %.17g\n", za[k], zb[k]);
+  const double kb[][4] = {{1e-3, 1.0, 3, 1e-10}, {1e-3, 1e-3, 2, 1e-10}, {0.0, 1.0, 3, 1e-10},
+                          {1e-2, 1.0, 2, 0.0}, {0.5, 1.0, 1, 1e-10}, {1e-9, 1e-8, 1, 1e-10}};
+  for (const auto& c : kb) std::printf("kb %d\n", krylov_batch(c[0], c[1], (int)c[2], c[3], 32));
   return 0;
 }
 """
@@ -208,3 +217,26 @@ def test_horizontal_tables(driver):
     ref = np.exp(-2j * np.pi * np.arange(12) / 12)
     # the angle 2 pi t / n is rounded before the sine and cosine: a few ulps
     np.testing.assert_allclose(tw[:, 0] + 1j * tw[:, 1], ref, rtol=0, atol=2e-15)
+
+
+def test_face_weights_match_oracle(driver):
+    """za_k q_k + zb_k q_{k+1} is the oracle's face value of a column q
+    (oracle.face_densities, the linear interpolation in z)."""
+    g, lines = driver
+    fw = np.array([list(map(float, l.split()[1:])) for l in lines if l.startswith("fw ")])
+    assert fw.shape == (g.nz, 2)
+    assert fw[-1, 0] == 0.0 and fw[-1, 1] == 0.0
+    q = np.asarray(g.rho0, dtype=np.float64)
+    col = q[:, None, None] * np.ones((1, 1, 1))
+    _, _, rz = oracle.variable.face_densities(col, g.dz)
+    mine = fw[:-1, 0] * q[:-1] + fw[:-1, 1] * q[1:]
+    np.testing.assert_allclose(mine, rz[:, 0, 0], rtol=1e-15, atol=0)
+
+
+def test_krylov_batch_prediction(driver):
+    """Rate 0.1 per iteration from 1e-3 to 1e-10: 7 more; no decrease or no
+    residual: 1; tol 0: the cap; a slow rate: capped at 32; one iteration to
+    go: 1."""
+    _, lines = driver
+    got = [int(l.split()[1]) for l in lines if l.startswith("kb ")]
+    assert got == [7, 1, 1, 32, 32, 1]
