@@ -12,7 +12,9 @@
 // 12 instead of 17 at +-50 %). The solver keeps the scaled residual
 // rt = S r, which is what the spectral solve reads (z' = Lbar^-1 rt, z = S z'),
 // so <r, z> = <rt, z'>; S enters the residual update, <z, q> and the
-// direction update, and the residual norm is taken of r = rt / S.
+// direction update, and the residual norm is taken of r = rt / S. S is
+// stored in FP32 and every use takes that same rounded value, so the
+// preconditioner stays exactly symmetric.
 //
 // All vectors are FP64 (nz, ny, nx) fields; the preconditioned residual z is
 // in the plan's storage type (ZT). Face densities come from rho on the fly:
@@ -25,7 +27,8 @@
 // (blockIdx.y), keeping the column's values of the levels below and above in
 // registers, so only the x and y neighbours come through the caches; the
 // pointwise kernels take one level per workgroup (more, shorter workgroups
-// stream faster).
+// stream faster). For even nx the operator works on pairs of adjacent x
+// points with 16-byte loads (k_var_apply2).
 // Inner products are weighted by dz_k (the weight that makes D_rho G
 // self-adjoint); each workgroup writes its partial sum and a one-workgroup
 // kernel adds the partials in a fixed order, so results are deterministic.
