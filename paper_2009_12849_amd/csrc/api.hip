@@ -885,37 +885,39 @@ extern "C" int monc_project_var(monc_plan* pl, const double* rho, double* u, dou
   launch_var_zero(ws.scal, (maxit + 2) * kVarSlots, stream);
   launch_var_div(g, u, v, w, ws.r, p, ws.part0, stream);
   if ((rc = var_launched("the divergence")) != MONC_OK) return rc;
-  launch_var_finish(ws.part0, nullptr, np_st, ws.scal, var_slot(0, kVarRR), 0, false, stream);
+  // <r_0, r_0>, through the residual-norm reduction of iteration 0: it sets
+  // the done flag when the input is already divergence-free (or tol >= 1) and
+  // flags a non-finite input, so the host needs no read before the first
+  // batch; a done flag makes the queued work of that batch return at once
+  launch_var_finish_rr(ws.part0, np_st, ws.scal, 0, tol * tol, stream);
   if ((rc = var_launched("the partial-sum reduction")) != MONC_OK) return rc;
-  double rr0 = 0.0;
-  if ((rc = read_scalars(ws.scal + var_slot(0, kVarRR), &rr0, 1, stream)) != MONC_OK) return rc;
-  if (!std::isfinite(rr0)) return fail(MONC_EINVAL, "monc_project_var: the divergence of the input is not finite");
   int it = 0;
   double rel = 0.0;
-  if (rr0 > 0.0) {
-    if ((rc = direction(0)) != MONC_OK) return rc;
-    // Iterations are queued in batches and the status read once per batch;
-    // the next batch's length is the iteration count that the convergence
-    // rate seen so far predicts (at least 1, at most 32).
-    int queued = 0, batch = 3;
-    double rel_prev = 1.0;
-    for (;;) {
-      const int nb = std::min(batch, maxit - queued);
-      for (int b = 0; b < nb; ++b, ++queued) {
-        if ((rc = step(queued)) != MONC_OK) return rc;
-        if (queued + 1 < maxit && (rc = direction(queued + 1)) != MONC_OK) return rc;
-      }
-      double st[4];
-      if ((rc = read_scalars(ws.scal, st, 4, stream)) != MONC_OK) return rc;
-      if (st[kVarDone] == 2.0)
-        return fail(MONC_EINVAL, "monc_project_var: breakdown at iteration %d (is rho positive everywhere?)",
-                    (int)st[kVarLast]);
-      it = (int)st[kVarLast];
-      rel = std::sqrt(st[kVarLastRR] / rr0);
-      if (st[kVarDone] != 0.0 || queued >= maxit) break;
-      batch = krylov_batch(rel, rel_prev, nb, tol, 32);
-      rel_prev = rel;
+  if ((rc = direction(0)) != MONC_OK) return rc;
+  // Iterations are queued in batches and the status read once per batch;
+  // the next batch's length is the iteration count that the convergence rate
+  // seen so far predicts (at least 1, at most 32).
+  int queued = 0, batch = 3;
+  double rel_prev = 1.0;
+  for (;;) {
+    const int nb = std::min(batch, maxit - queued);
+    for (int b = 0; b < nb; ++b, ++queued) {
+      if ((rc = step(queued)) != MONC_OK) return rc;
+      if (queued + 1 < maxit && (rc = direction(queued + 1)) != MONC_OK) return rc;
     }
+    // the status row and iteration 0's row (<r_0, r_0>) in one read
+    double st[2 * kVarSlots];
+    if ((rc = read_scalars(ws.scal, st, 2 * kVarSlots, stream)) != MONC_OK) return rc;
+    const double rr0 = st[var_slot(0, kVarRR)];
+    it = (int)st[kVarLast];
+    if (st[kVarDone] == 2.0) {
+      if (it == 0) return fail(MONC_EINVAL, "monc_project_var: the divergence of the input is not finite");
+      return fail(MONC_EINVAL, "monc_project_var: breakdown at iteration %d (is rho positive everywhere?)", it);
+    }
+    rel = rr0 > 0.0 ? std::sqrt(st[kVarLastRR] / rr0) : 0.0;
+    if (st[kVarDone] != 0.0 || queued >= maxit) break;
+    batch = krylov_batch(rel, rel_prev, nb, tol, 32);
+    rel_prev = rel;
   }
   // the gauge in FP64: subtract the dz-weighted mean of p (the constants are
   // the operator's null space, so the residual does not change; an FP32

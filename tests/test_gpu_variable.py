@@ -257,3 +257,14 @@ def test_solve_is_deterministic(dtype):
     assert i0 == i1 and r0 == r1
     for a, b in zip(o0, o1):
         assert np.array_equal(a, b)
+
+
+def test_non_finite_input_is_reported():
+    g, rho, u, v, w = _case((16, 16, 4), 7)
+    u = u.copy()
+    u[1, 2, 3] = np.nan
+    plan = _plan(g, rho, "f64")
+    f = [_t(a) for a in (rho, u, v, w, np.zeros_like(u))]
+    with pytest.raises(monc.MoncError, match="not finite"):
+        plan.project_var(*f)
+    plan.close()
