@@ -232,9 +232,10 @@ __global__ void __launch_bounds__(kVarBlock) k_var_apply(VarGrid g, const double
 }
 
 // The operator for even nx on pairs of adjacent x points with 16-byte
-// loads: the kVarSpan points of a workgroup are kVarSpan/2 pairs, two per
-// thread at stride kVarBlock pairs; a pair's x neighbours outside it are two
-// 8-byte loads. 10 load instructions per pair instead of 16 for two points.
+// loads: a workgroup takes a tile of var_tile_rows rows of var_tile_pairs
+// pairs (kVarSpan/2 pairs at most), two per thread at stride kVarBlock; a
+// pair's x neighbours outside it are two 8-byte loads. 10 load instructions
+// per pair instead of 16 for two points.
 typedef double d2v __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ d2v ld2(const double* p) { return *reinterpret_cast<const d2v*>(p); }
 
@@ -244,15 +245,17 @@ __global__ void __launch_bounds__(kVarBlock) k_var_apply2(VarGrid g, const doubl
   if (var_done(scal)) return;
   constexpr int NP = kVarPts / 2;   // pairs per thread
   const Blk bk = var_block();
-  const int hx = g.nx / 2, nhp = hx * g.ny;
+  const int hx = g.nx / 2;
+  const int txp = var_tile_pairs(g.nx), tyr = var_tile_rows(g.nx), ntx = var_tiles_x(g.nx);
+  const int tile_y = bk.x / ntx, tile_x = bk.x - tile_y * ntx;
   int h[NP], hw[NP], he[NP], hs[NP], hn[NP];
   bool live[NP];
 #pragma unroll
   for (int t = 0; t < NP; ++t) {
-    const int idx = bk.x * (kVarSpan / 2) + t * kVarBlock + threadIdx.x;
-    live[t] = idx < nhp;
-    const int id = live[t] ? idx : 0;
-    const int j = id / hx, i0 = 2 * (id - j * hx);
+    const int sl = t * kVarBlock + threadIdx.x;          // slot in the tile
+    const int rr = sl / txp, pc = tile_x * txp + (sl - rr * txp), jr = tile_y * tyr + rr;
+    live[t] = rr < tyr && pc < hx && jr < g.ny;
+    const int j = live[t] ? jr : 0, i0 = live[t] ? 2 * pc : 0;   // outside the grid: pair 0, nothing stored
     const int row = j * g.nx;
     h[t] = row + i0;
     hw[t] = row + (i0 == 0 ? g.nx - 1 : i0 - 1);
@@ -506,8 +509,9 @@ void launch_var_div(const VarGrid& g, const double* u, const double* v, const do
 
 void launch_var_apply(const VarGrid& g, const double* scal, const double* d, double* q, double* part, void* stream) {
   if (g.nx % 2 == 0)
-    hipLaunchKernelGGL(k_var_apply2, var_grid_stencil(g), dim3(kVarBlock), 0, (hipStream_t)stream, g, scal, d, q,
-                       part);
+    hipLaunchKernelGGL(k_var_apply2, dim3((unsigned)(var_tiles_x(g.nx) * var_tiles_y(g.nx, g.ny)),
+                                          (unsigned)var_level_groups(g.nz)),
+                       dim3(kVarBlock), 0, (hipStream_t)stream, g, scal, d, q, part);
   else
     hipLaunchKernelGGL(k_var_apply, var_grid_stencil(g), dim3(kVarBlock), 0, (hipStream_t)stream, g, scal, d, q, part);
 }
