@@ -740,8 +740,7 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static int var_workspace(monc_plan* pl, VarWs* ws) {
   const size_t n = (size_t)pl->nx * pl->ny * pl->nz;
-  const size_t nparts = (size_t)std::max(var_point_parts(pl->nx, pl->ny, pl->nz),
-                                         var_apply_parts(pl->nx, pl->ny, pl->nz));  // the largest count
+  const size_t nparts = (size_t)var_point_parts(pl->nx, pl->ny, pl->nz);  // the larger count
   constexpr int kParts = 11;
   const size_t sizes[kParts] = {n * 8, n * 8, n * 8, n * elem_bytes(pl->dtype), nparts * 8, nparts * 8,
                                 (size_t)(kVarMaxIt + 2) * kVarSlots * 8, (size_t)pl->nz * 8, (size_t)pl->nz * 8,
@@ -840,7 +839,6 @@ extern "C" int monc_project_var(monc_plan* pl, const double* rho, double* u, dou
   g.s = ws.s;
   const long long np_st = var_stencil_parts(pl->nx, pl->ny, pl->nz);  // partials of the stencil kernels
   const long long np_pt = var_point_parts(pl->nx, pl->ny, pl->nz);    // partials of the pointwise kernels
-  const long long np_op = var_apply_parts(pl->nx, pl->ny, pl->nz);    // partials of the operator
   const bool z64 = pl->dtype == MONC_FP64;
   Profiler* prof = pl->prof.mask ? &pl->prof : nullptr;
 
@@ -876,7 +874,7 @@ extern "C" int monc_project_var(monc_plan* pl, const double* rho, double* u, dou
     launch_var_apply(g, ws.scal, ws.d, ws.q, ws.part0, stream);
     int e = var_launched("the operator");
     if (e != MONC_OK) return e;
-    launch_var_finish(ws.part0, nullptr, np_op, ws.scal, var_slot(i, kVarDQ), 0, true, stream);
+    launch_var_finish(ws.part0, nullptr, np_st, ws.scal, var_slot(i, kVarDQ), 0, true, stream);
     if ((e = var_launched("the partial-sum reduction")) != MONC_OK) return e;
     launch_var_update(g, ws.scal, i, p, ws.r, ws.d, ws.q, ws.part0, stream);
     if ((e = var_launched("the solution update")) != MONC_OK) return e;

@@ -20,25 +20,20 @@ enum { kVarRZ = 0, kVarDQ = 1, kVarRR = 2, kVarZQ = 3, kVarSlots = 4 };
 enum { kVarGauge = 0, kVarDone = 1, kVarLast = 2, kVarLastRR = 3 };
 inline __host__ __device__ int var_slot(int it, int s) { return kVarSlots * (it + 1) + s; }
 
+// A workgroup covers a 2-D tile of a level: var_tile_w(nx) = min(nx, 256)
+// points wide and kVarSpan / var_tile_w rows high, so that the rows a
+// stencil reads above and below its own are few against the rows it
+// computes (a run of kVarSpan points would be a single row at nx = 1024).
+inline __host__ __device__ int var_tile_w(int nx) { return nx < 256 ? nx : 256; }
+inline __host__ __device__ int var_tile_h(int nx) { return kVarSpan / var_tile_w(nx); }
+inline __host__ __device__ int var_tiles_x(int nx) { return (nx + var_tile_w(nx) - 1) / var_tile_w(nx); }
+inline __host__ __device__ int var_tiles_y(int nx, int ny) { return (ny + var_tile_h(nx) - 1) / var_tile_h(nx); }
 inline __host__ __device__ long long var_blocks_per_level(int nx, int ny) {
-  return ((long long)nx * ny + kVarSpan - 1) / kVarSpan;
+  return (long long)var_tiles_x(nx) * var_tiles_y(nx, ny);
 }
 inline __host__ __device__ int var_level_groups(int nz) { return (nz + kVarLevels - 1) / kVarLevels; }
 inline long long var_stencil_parts(int nx, int ny, int nz) { return var_blocks_per_level(nx, ny) * var_level_groups(nz); }
-// The paired operator (even nx) takes 2-D tiles of a level, var_tile_pairs
-// pairs (<= 128, i.e. 256 points) wide and var_tile_rows rows high, so that
-// the rows it reads above and below its own are few against the rows it
-// computes even when a row alone holds kVarSpan points.
-inline __host__ __device__ int var_tile_pairs(int nx) { return nx / 2 < 128 ? nx / 2 : 128; }
-inline __host__ __device__ int var_tile_rows(int nx) { return (kVarSpan / 2) / var_tile_pairs(nx); }
-inline __host__ __device__ int var_tiles_x(int nx) { return (nx / 2 + var_tile_pairs(nx) - 1) / var_tile_pairs(nx); }
-inline __host__ __device__ int var_tiles_y(int nx, int ny) { return (ny + var_tile_rows(nx) - 1) / var_tile_rows(nx); }
-// partial sums written by the operator: the paired kernel's tiles for even
-// nx, the stencil grid otherwise
-inline long long var_apply_parts(int nx, int ny, int nz) {
-  return nx % 2 == 0 ? (long long)var_tiles_x(nx) * var_tiles_y(nx, ny) * var_level_groups(nz)
-                     : var_stencil_parts(nx, ny, nz);
-}
+
 inline long long var_point_parts(int nx, int ny, int nz) { return var_blocks_per_level(nx, ny) * nz; }
 
 struct VarGrid {

@@ -21,8 +21,9 @@
 //   rx = (rho_i + rho_{i+1})/2, ry = (rho_j + rho_{j+1})/2 (periodic),
 //   rz_k = za_k rho_k + zb_k rho_{k+1}, za_k = dz_{k+1}/(dz_k + dz_{k+1}),
 //   zb_k = dz_k/(dz_k + dz_{k+1}) (0 on the lid).
-// A workgroup of kVarBlock threads takes kVarSpan consecutive points of a
-// level (kVarPts per thread at stride kVarBlock, coalesced). The stencil
+// A workgroup of kVarBlock threads takes a 2-D tile of kVarSpan points of a
+// level, min(nx, 256) wide (kVarPts per thread at stride kVarBlock in the
+// tile, coalesced along rows). The stencil
 // kernels (divergence, operator) walk them up a group of kVarLevels levels
 // (blockIdx.y), keeping the column's values of the levels below and above in
 // registers, so only the x and y neighbours come through the caches; the
@@ -79,13 +80,15 @@ __device__ __forceinline__ Blk var_block() { return Blk{(int)blockIdx.x, (int)bl
 
 __device__ __forceinline__ Col columns(const VarGrid& g, const Blk& bk) {
   Col c;
-  const int nh = g.nx * g.ny;
+  const int tw = var_tile_w(g.nx), th = var_tile_h(g.nx), ntx = var_tiles_x(g.nx);
+  const int tile_y = bk.x / ntx, tile_x = bk.x - tile_y * ntx;
 #pragma unroll
   for (int t = 0; t < kVarPts; ++t) {
-    const int idx = bk.x * kVarSpan + t * kVarBlock + threadIdx.x;
-    c.live[t] = idx < nh;
-    const int id = c.live[t] ? idx : 0;   // past the level: point 0, nothing stored
-    const int j = id / g.nx, i = id - j * g.nx;
+    const int sl = t * kVarBlock + threadIdx.x;          // slot in the tile
+    const int rr = sl / tw, ic = tile_x * tw + (sl - rr * tw), jr = tile_y * th + rr;
+    c.live[t] = rr < th && ic < g.nx && jr < g.ny;
+    // outside the grid: point 0, nothing stored
+    const int j = c.live[t] ? jr : 0, i = c.live[t] ? ic : 0;
     const int row = j * g.nx;
     c.h[t] = row + i;
     c.hw[t] = row + (i == 0 ? g.nx - 1 : i - 1);
@@ -232,10 +235,10 @@ __global__ void __launch_bounds__(kVarBlock) k_var_apply(VarGrid g, const double
 }
 
 // The operator for even nx on pairs of adjacent x points with 16-byte
-// loads: a workgroup takes a tile of var_tile_rows rows of var_tile_pairs
-// pairs (kVarSpan/2 pairs at most), two per thread at stride kVarBlock; a
-// pair's x neighbours outside it are two 8-byte loads. 10 load instructions
-// per pair instead of 16 for two points.
+// loads: a workgroup's tile (var_tile_h rows of var_tile_w / 2 pairs) holds
+// kVarSpan/2 pairs, two per thread at stride kVarBlock; a pair's x
+// neighbours outside it are two 8-byte loads. 10 load instructions per pair
+// instead of 16 for two points.
 typedef double d2v __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ d2v ld2(const double* p) { return *reinterpret_cast<const d2v*>(p); }
 
@@ -246,7 +249,7 @@ __global__ void __launch_bounds__(kVarBlock) k_var_apply2(VarGrid g, const doubl
   constexpr int NP = kVarPts / 2;   // pairs per thread
   const Blk bk = var_block();
   const int hx = g.nx / 2;
-  const int txp = var_tile_pairs(g.nx), tyr = var_tile_rows(g.nx), ntx = var_tiles_x(g.nx);
+  const int txp = var_tile_w(g.nx) / 2, tyr = var_tile_h(g.nx), ntx = var_tiles_x(g.nx);
   const int tile_y = bk.x / ntx, tile_x = bk.x - tile_y * ntx;
   int h[NP], hw[NP], he[NP], hs[NP], hn[NP];
   bool live[NP];
@@ -509,9 +512,8 @@ void launch_var_div(const VarGrid& g, const double* u, const double* v, const do
 
 void launch_var_apply(const VarGrid& g, const double* scal, const double* d, double* q, double* part, void* stream) {
   if (g.nx % 2 == 0)
-    hipLaunchKernelGGL(k_var_apply2, dim3((unsigned)(var_tiles_x(g.nx) * var_tiles_y(g.nx, g.ny)),
-                                          (unsigned)var_level_groups(g.nz)),
-                       dim3(kVarBlock), 0, (hipStream_t)stream, g, scal, d, q, part);
+    hipLaunchKernelGGL(k_var_apply2, var_grid_stencil(g), dim3(kVarBlock), 0, (hipStream_t)stream, g, scal, d, q,
+                       part);
   else
     hipLaunchKernelGGL(k_var_apply, var_grid_stencil(g), dim3(kVarBlock), 0, (hipStream_t)stream, g, scal, d, q, part);
 }
