@@ -336,6 +336,29 @@ def cpu_baseline(members, min_s=10.0, budget_s=25.0):
     return rec, outs
 
 
+def variable_cpu_baseline(min_s=3.0, amp=0.2):
+    """The variable-density oracle (a direct sparse solve) timed on this host.
+    It cannot solve the benchmark grid (8e6 unknowns and up), so the sample is
+    a 32 x 32 x 16 grid with the same density recipe, solved repeatedly until
+    min_s seconds are timed: the oracle's rate on a problem it can do, not a
+    rate at the benchmark's size."""
+    import oracle
+    import synth
+    rng = np.random.default_rng(6101)
+    g = synth.random_grid(rng, 32, 32, 16, stretch=(1.0, 1.1))
+    rho = synth.density_field(np.random.default_rng(6100), g, amp)
+    u, v, w = synth.random_fields(rng, g)
+    times = []
+    while sum(times) < min_s:
+        t0 = time.perf_counter()
+        oracle.project_var(u, v, w, g.dx, g.dy, g.dz, rho)
+        times.append(time.perf_counter() - t0)
+    tot = sum(times)
+    return {"value": len(times) * g.points / tot, "unit": "grid-points/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(times)} direct sparse solves (SciPy SuperLU) of a {g.nx}x{g.ny}x{g.nz} grid with "
+                      f"rho0(z)(1 + {amp} f), {tot:.2f} s, host {platform.processor() or platform.machine()}"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -415,6 +438,8 @@ def main():
     }
     if not args.no_var and not runner.batched and runner.points <= 300_000_000:
         result["variable_density"] = variable_density(monc, torch, members[0])
+        if not args.no_cpu:
+            result["variable_density"]["cpu_baseline"] = variable_cpu_baseline()
     if not args.no_other:
         del runner
         torch.cuda.empty_cache()
