@@ -150,9 +150,10 @@ int monc_project_reduce(monc_plan* plan, void* u, void* v, void* w, void* p, dou
  * self-adjoint), z = M^-1 r the plan's spectral solve with its rho0 (the
  * horizontal mean of rho per level is the natural choice): FP64 for an FP64
  * plan; for a MIXED plan FP32 transforms with the FP64 tridiagonal solve and
- * no refinement step. The residual and the iterates stay FP64 and the
- * direction update is the flexible (Polak-Ribiere) one, which tolerates the
- * inexact FP32 preconditioner.
+ * no refinement step. The residual and the iterates stay FP64; with the
+ * FP32 preconditioner the direction update is the flexible (Polak-Ribiere)
+ * one, which tolerates its inexactness, with the FP64 one the classic
+ * Fletcher-Reeves update (one inner product fewer per iteration).
  * Arguments: rho, u, v, w, p are FP64 device arrays (nz, ny, nx), 16-byte
  * aligned and pairwise disjoint, whatever the plan's precision; rho (> 0
  * everywhere) is read only, u, v, w are updated in place, p is written.

@@ -862,7 +862,8 @@ extern "C" int monc_project_var(monc_plan* pl, const double* rho, double* u, dou
     if (e != MONC_OK) return e;
     launch_var_dots(g, ws.scal, ws.r, ws.z, z64, ws.q, ws.part0, ws.part1, stream);
     if ((e = var_launched("the inner products")) != MONC_OK) return e;
-    launch_var_finish(ws.part0, i > 0 ? ws.part1 : nullptr, np_pt, ws.scal, var_slot(i, kVarRZ),
+    // <z, q> only for the flexible update (FP32 preconditioner)
+    launch_var_finish(ws.part0, (i > 0 && !z64) ? ws.part1 : nullptr, np_pt, ws.scal, var_slot(i, kVarRZ),
                       var_slot(i, kVarZQ), true, stream);
     if ((e = var_launched("the partial-sum reduction")) != MONC_OK) return e;
     launch_var_dir(g, ws.scal, i, ws.z, z64, ws.d, stream);

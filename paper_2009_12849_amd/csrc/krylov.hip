@@ -350,9 +350,9 @@ __global__ void __launch_bounds__(kVarBlock) k_var_update(VarGrid g, const doubl
   if (threadIdx.x == 0) part[part_index()] = s;
 }
 
-// partial sums of dz rt z' (= <r, z>) and dz s z' q (= <z, q>, for the
-// flexible update)
-template <typename ZT>
+// partial sums of dz rt z' (= <r, z>) and, for the flexible update (FLEX),
+// dz s z' q (= <z, q>)
+template <typename ZT, bool FLEX>
 __global__ void __launch_bounds__(kVarBlock) k_var_dots(VarGrid g, const double* __restrict__ scal,
                                                       const double* __restrict__ r, const ZT* __restrict__ z,
                                                       const double* __restrict__ q, double* __restrict__ part0,
@@ -368,32 +368,40 @@ __global__ void __launch_bounds__(kVarBlock) k_var_dots(VarGrid g, const double*
 #pragma unroll
     for (int t = 0; t < kVarPts; ++t) {
       const long long o = b + c.h[t];
-      const double zc = (double)z[o], rc = r[o], qc = q[o], sc = (double)g.s[o];
-      if (c.live[t]) {
-        a0 += dz * rc * zc;
-        a1 += dz * sc * zc * qc;
+      const double zc = (double)z[o], rc = r[o];
+      if (c.live[t]) a0 += dz * rc * zc;
+      if constexpr (FLEX) {
+        const double qc = q[o], sc = (double)g.s[o];
+        if (c.live[t]) a1 += dz * sc * zc * qc;
       }
     }
   }
   const double s0 = block_sum<kVarBlock>(a0);
-  __syncthreads();  // block_sum's LDS is reused
-  const double s1 = block_sum<kVarBlock>(a1);
-  if (threadIdx.x == 0) {
-    part0[part_index()] = s0;
-    part1[part_index()] = s1;
+  if (threadIdx.x == 0) part0[part_index()] = s0;
+  if constexpr (FLEX) {
+    __syncthreads();  // block_sum's LDS is reused
+    const double s1 = block_sum<kVarBlock>(a1);
+    if (threadIdx.x == 0) part1[part_index()] = s1;
   }
 }
 
-// d = s z' + beta d, beta = -alpha_{it-1} <z_it, q_{it-1}> / rz_{it-1} (0 at it = 0)
-template <typename ZT>
+// d = s z' + beta d (beta = 0 at it = 0); flexible (Polak-Ribiere):
+// beta = <z_it, r_it - r_{it-1}> / rz_{it-1} = -alpha_{it-1} <z_it, q_{it-1}> / rz_{it-1};
+// otherwise (Fletcher-Reeves) beta = rz_it / rz_{it-1}
+template <typename ZT, bool FLEX>
 __global__ void __launch_bounds__(kVarBlock) k_var_dir(VarGrid g, const double* __restrict__ scal, int it,
                                                      const ZT* __restrict__ z, double* __restrict__ d) {
   if (var_done(scal)) return;
   double beta = 0.0;
   if (it > 0) {
-    const double rzp = scal[var_slot(it - 1, kVarRZ)], dqp = scal[var_slot(it - 1, kVarDQ)];
-    const double alpha = dqp != 0.0 ? rzp / dqp : 0.0;
-    beta = rzp != 0.0 ? -alpha * scal[var_slot(it, kVarZQ)] / rzp : 0.0;
+    const double rzp = scal[var_slot(it - 1, kVarRZ)];
+    if constexpr (FLEX) {
+      const double dqp = scal[var_slot(it - 1, kVarDQ)];
+      const double alpha = dqp != 0.0 ? rzp / dqp : 0.0;
+      beta = rzp != 0.0 ? -alpha * scal[var_slot(it, kVarZQ)] / rzp : 0.0;
+    } else {
+      beta = rzp != 0.0 ? scal[var_slot(it, kVarRZ)] / rzp : 0.0;
+    }
   }
   const Blk bk = var_block();
   const Col c = columns(g, bk);
@@ -524,22 +532,24 @@ void launch_var_update(const VarGrid& g, const double* scal, int it, double* p, 
                      part);
 }
 
+// the FP64 preconditioner takes the Fletcher-Reeves update, the FP32 one the
+// flexible update
 void launch_var_dots(const VarGrid& g, const double* scal, const double* r, const void* z, bool z64, const double* q,
                      double* part0, double* part1, void* stream) {
   if (z64)
-    hipLaunchKernelGGL(k_var_dots<double>, var_grid(g), dim3(kVarBlock), 0, (hipStream_t)stream, g, scal, r,
+    hipLaunchKernelGGL((k_var_dots<double, false>), var_grid(g), dim3(kVarBlock), 0, (hipStream_t)stream, g, scal, r,
                        static_cast<const double*>(z), q, part0, part1);
   else
-    hipLaunchKernelGGL(k_var_dots<float>, var_grid(g), dim3(kVarBlock), 0, (hipStream_t)stream, g, scal, r,
+    hipLaunchKernelGGL((k_var_dots<float, true>), var_grid(g), dim3(kVarBlock), 0, (hipStream_t)stream, g, scal, r,
                        static_cast<const float*>(z), q, part0, part1);
 }
 
 void launch_var_dir(const VarGrid& g, const double* scal, int it, const void* z, bool z64, double* d, void* stream) {
   if (z64)
-    hipLaunchKernelGGL(k_var_dir<double>, var_grid(g), dim3(kVarBlock), 0, (hipStream_t)stream, g, scal, it,
-                       static_cast<const double*>(z), d);
+    hipLaunchKernelGGL((k_var_dir<double, false>), var_grid(g), dim3(kVarBlock), 0, (hipStream_t)stream, g, scal,
+                       it, static_cast<const double*>(z), d);
   else
-    hipLaunchKernelGGL(k_var_dir<float>, var_grid(g), dim3(kVarBlock), 0, (hipStream_t)stream, g, scal, it,
+    hipLaunchKernelGGL((k_var_dir<float, true>), var_grid(g), dim3(kVarBlock), 0, (hipStream_t)stream, g, scal, it,
                        static_cast<const float*>(z), d);
 }
 
