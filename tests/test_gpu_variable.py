@@ -291,3 +291,47 @@ def test_plan_density_far_from_rho(dtype):
     for f in range(3):
         assert np.abs(outs[f] - ref[f]).max() <= bound * scale, f
     assert np.abs(outs[3] - ref[3]).max() <= bound * np.abs(ref[3]).max()
+
+
+def test_side_stream_and_retuned_plan():
+    """The solve on a non-default stream (its kernels and its status reads
+    follow the caller's stream) gives bitwise the default stream's answer;
+    after the plan's tiles change (autotune, or explicit parameters) the
+    preconditioner's descriptor follows them and the answer is the same to
+    the solver tolerance."""
+    g, rho, u, v, w = _case((64, 48, 20), 1600)
+    plan = _plan(g, rho, "f64")
+    r = _t(rho)
+
+    def solve(stream=None):
+        t = [_t(a) for a in (u, v, w)]
+        p = torch.empty_like(t[0])
+        if stream is None:
+            it, rel = plan.project_var(r, *t, p, tol=TOL)
+        else:
+            torch.cuda.synchronize()
+            with torch.cuda.stream(stream):
+                it, rel = plan.project_var(r, *t, p, tol=TOL, stream=stream)
+            stream.synchronize()
+        torch.cuda.synchronize()
+        return [x.cpu().numpy() for x in t + [p]], it, rel
+
+    ref, it0, _ = solve()
+    side, it1, _ = solve(torch.cuda.Stream())
+    assert it0 == it1
+    for a, b in zip(ref, side):
+        assert np.array_equal(a, b)
+    params = plan.params
+    alt = list(params)
+    alt[3] = 8 if params[3] != 8 else 16        # tridiagonal lanes per column
+    alt[4] = 0                                  # columns per workgroup: automatic
+    plan.params = alt
+    assert plan.params[3] == alt[3]
+    out, it2, rel2 = solve()
+    plan.close()
+    assert rel2 <= TOL
+    scale = max(np.abs(a).max() for a in (u, v, w))
+    bound = TOL * _cond_estimate(g.nx, g.ny, g.dx, g.dy, g.dz, contrast=1.3 / 0.7)
+    for f in range(3):
+        assert np.abs(out[f] - ref[f]).max() <= bound * scale
+    assert np.abs(out[3] - ref[3]).max() <= bound * np.abs(ref[3]).max()
