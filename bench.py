@@ -9,17 +9,24 @@ costs exactly the same kernels and bytes as the first pass.
 
 Workloads (seeded synthetic stand-ins for the paper's dry boundary-layer
 case, see synth/):
-  256x256x128    stretched anelastic grid; headline = plain FP64 path, the
-                 mixed FP32/FP64 path (one FP64 refinement step) timed
-                 beside it (default)
-  1024x1024x256  same vertical profiles; headline = mixed, FP64 beside it
+  2048x2048x160  k^-5/3 spectra, one GPU's share of a large run; headline =
+                 the mixed path, the plain FP64 path beside it (default)
+  1024x1024x256  stretched anelastic grid; headline = mixed, FP64 beside it
   ensemble48     48-member ensemble of uneven grids, one batched call (HIP
                  graph); headline = mixed, FP64 beside it
-  2048x2048x160  k^-5/3 spectra; headline = mixed, FP64 beside it
+  256x256x128    headline = plain FP64 path, mixed beside it
+  4096x4096x64   the paper's 1.07e9-point global problem; headline = mixed
+`value` is the warm rate (K projections back to back); `cold` times single
+projections after a 1 GiB write has flushed the 256 MB Infinity Cache.
 Single grids up to 3e8 points also time the variable-density projection
 (conjugate gradients with the spectral solve as preconditioner, a seeded
 density rho0(z)(1 + 0.2 f(x, y, z))) under "variable_density".
 Prints one JSON line.
+
+Counter profiles (rocprofv3 --pmc, one pass per counter set):
+  python bench.py --pmc-run [--workload NAME]      short run to profile
+  python bench.py --summarize-counters RD_CSV WR_CSV [--workload NAME]
+                                                   per-kernel HBM bytes
 """
 from __future__ import annotations
 
@@ -38,8 +45,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "grid-points/s full projection (mixed vs FP64 GPU) at rel err ≤1e-6, %HBM roofline"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_2009_12849_amd", "csrc", "kernels.hip")
-WORKLOADS = ["256x256x128", "1024x1024x256", "ensemble48", "2048x2048x160", "4096x4096x64"]
+KERNEL_DIR = os.path.join(ROOT, "paper_2009_12849_amd", "csrc")
+WORKLOADS = ["2048x2048x160", "1024x1024x256", "ensemble48", "256x256x128", "4096x4096x64"]
 KERNELS = ["div_fftx", "ffty_fwd", "tridiag", "ffty_inv", "ifftx", "grad", "resid_fftx", "grad_final"]
 
 
@@ -77,9 +84,25 @@ def path_bytes_per_point(nx, mixed):
     return (16 + 8 * f) * 4.0 if mixed else (10 + 4 * f) * 8.0
 
 
+def kernel_path_bytes_per_point(nx, mixed):
+    """What the kernels of one projection move, each launch at its
+    algorithmic bytes: FP64 11 + 8f words (div-FFT 3 + f, four spectral
+    passes 2f each, inverse f + 1, gradient 7), mixed 19 + 16f words (two
+    solves, the residual 4 + f, the correction's inverse f + 3, the final
+    gradient 8)."""
+    f = spectral_words(nx)
+    return (19 + 16 * f) * 4.0 if mixed else (11 + 8 * f) * 8.0
+
+
 def kernel_source_hash():
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """Hash of every kernel source (a counter summary taken on other sources
+    is stale)."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(KERNEL_DIR)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(KERNEL_DIR, name), "rb") as fh:
+                h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_file(workload):
@@ -106,27 +129,68 @@ def read_traffic(workload, kernel, mixed):
     return float(vals[key]) if key in vals else None
 
 
+TUNING_FILE = os.path.join(ROOT, "paper_2009_12849_amd", "tuning", "gfx950.json")
+
+
+def use_tuning_cache():
+    """Point MONC_TUNE_CACHE at a private copy of the committed tuning table
+    (tile parameters the library's autotuner chose on an MI355X for the
+    benchmark grids) unless the caller named a cache. Plans created
+    afterwards start from the cached parameters of their grid; grids missing
+    from it are autotuned by the Runner. Returns the cache's path."""
+    if os.environ.get("MONC_TUNE_CACHE"):
+        return os.environ["MONC_TUNE_CACHE"]
+    import shutil
+    import tempfile
+    fd, path = tempfile.mkstemp(prefix="monc_tune_", suffix=".json")
+    os.close(fd)
+    if os.path.exists(TUNING_FILE):
+        shutil.copyfile(TUNING_FILE, path)
+    else:
+        with open(path, "w") as fh:
+            fh.write("{}\n")
+    os.environ["MONC_TUNE_CACHE"] = path
+    return path
+
+
+def cached_params(nx, ny, nz, dtype):
+    path = os.environ.get("MONC_TUNE_CACHE")
+    if not path or not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        try:
+            data = json.load(fh)
+        except ValueError:
+            return None
+    return data.get(f"gfx950:{nx},{ny},{nz}:{'fp64' if dtype == 'f64' else 'mixed'}")
+
+
 class Runner:
     """Owns the plans and device fields of one path (FP64 or mixed) of a
     workload and runs whole projections on them."""
 
-    def __init__(self, monc, torch, members, dtype, tune=True):
+    def __init__(self, monc, torch, members, dtype, tune=True, retune=False):
         self.torch = torch
         self.monc = monc
         self.mixed = dtype == "mixed"
         cast = np.float32 if self.mixed else np.float64
         self.plans = [monc.Plan.from_grid(m.grid, dtype) for m in members]
         self.tuned = {}
-        if tune:
-            # the library's autotuner picks the tile parameters once per
-            # distinct grid (untimed); plans of the same grid reuse them
-            for pl in self.plans:
-                key = (pl.nx, pl.ny, pl.nz)
-                if key not in self.tuned:
-                    pl.autotune()
-                    self.tuned[key] = pl.params
-                else:
-                    pl.params = self.tuned[key]
+        self.tuning = {}
+        # tile parameters: the tuning cache's (read by the library at plan
+        # creation), else the library's autotuner once per distinct grid
+        # (untimed); plans of the same grid share them
+        for pl in self.plans:
+            key = (pl.nx, pl.ny, pl.nz)
+            if key in self.tuned:
+                pl.params = self.tuned[key]
+                continue
+            if tune and (retune or cached_params(pl.nx, pl.ny, pl.nz, dtype) is None):
+                pl.autotune()
+                self.tuning[key] = "autotuned"
+            else:
+                self.tuning[key] = "cache" if cached_params(pl.nx, pl.ny, pl.nz, dtype) else "default"
+            self.tuned[key] = pl.params
         self.fields = []
         for m in members:
             f = [torch.from_numpy(a.astype(cast, copy=False)).to("cuda:0") for a in (m.u, m.v, m.w)]
@@ -157,8 +221,9 @@ class Runner:
         return {k: (ms / n, n // steps) for k, (ms, n) in prof.items()}
 
     def timed(self, steps, warmup, profile_kernel=None):
-        """Wall-clock time of `steps` projections; with profile_kernel, HIP
-        events on the launch stream bracket every launch of that kernel."""
+        """Wall-clock time of `steps` projections back to back (synchronised
+        before and after); with profile_kernel, HIP events on the launch
+        stream bracket every launch of that kernel."""
         torch = self.torch
         stream = torch.cuda.current_stream()
         for _ in range(warmup):
@@ -179,13 +244,32 @@ class Runner:
             self.plans[0].profile_enable(0)
         return wall, prof
 
+    def cold(self, steps, flush):
+        """Median time (ms, HIP events) of single projections, each after a
+        write of the `flush` buffer (outside the events) has replaced the
+        Infinity Cache's contents."""
+        torch = self.torch
+        stream = torch.cuda.current_stream()
+        pairs = []
+        for _ in range(steps):
+            self.monc.stream_probe("write", [flush], stream)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            self.step(stream)
+            b.record(stream)
+            pairs.append((a, b))
+        torch.cuda.synchronize()
+        return float(np.median([a.elapsed_time(b) for a, b in pairs]))
 
-def measure(runner, steps, warmup, workload, nx_bytes):
-    """Throughput, kernel breakdown and dominant-kernel roofline of a path."""
+
+def measure(runner, steps, warmup, workload, cold_steps, flush):
+    """Throughput (warm and cold), kernel breakdown and dominant-kernel
+    roofline of a path."""
     bd = runner.breakdown(3)
     dom = max(bd, key=lambda k: bd[k][0] * bd[k][1])
     wall, _ = runner.timed(steps, warmup)                    # clean timing
     _, prof = runner.timed(steps, 0, profile_kernel=dom)     # events around the dominant kernel
+    cold_ms = runner.cold(cold_steps, flush) if cold_steps > 0 else None
     value = runner.points * steps / wall
     dom_ms, dom_n = prof[dom]
     dom_avg_s = dom_ms / dom_n / 1e3
@@ -198,20 +282,79 @@ def measure(runner, steps, warmup, workload, nx_bytes):
     per_launch = per_step / max(1, dom_n // steps)
     achieved = per_launch / dom_avg_s / 1e9
     path_bytes = sum(path_bytes_per_point(p.nx, runner.mixed) * p.nx * p.ny * p.nz for p in runner.plans)
-    return {
+    kernel_bytes = sum(kernel_path_bytes_per_point(p.nx, runner.mixed) * p.nx * p.ny * p.nz for p in runner.plans)
+    traffic = read_traffic(workload, dom, runner.mixed)
+    out = {
         "value": value,
         "ms_per_step": 1e3 * wall / steps,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": read_traffic(workload, dom, runner.mixed),
+                     "traffic": traffic,
+                     "traffic_over_algorithmic": (traffic / per_launch) if traffic else None,
                      "avg_launch_ms": dom_avg_s * 1e3, "algorithmic_bytes_per_launch": per_launch},
         "path": {"algorithmic_bytes_per_point": path_bytes / runner.points,
+                 "kernel_bytes_per_point": kernel_bytes / runner.points,
                  "end_to_end_hbm_frac": path_bytes * steps / wall / 1e9 / HBM_PEAK_GBS,
                  "kernels_ms": {k: round(v[0], 5) for k, v in bd.items()},
                  "launches_per_step": {k: v[1] for k, v in bd.items()}},
     }
+    if cold_ms is not None:
+        out["cold"] = {"ms_per_step": cold_ms, "value": runner.points / (cold_ms * 1e-3),
+                       "end_to_end_hbm_frac": path_bytes / (cold_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                       "steps": cold_steps,
+                       "what": "median of single projections, each after a 1 GiB write (outside the timed "
+                               "events) has flushed the 256 MB Infinity Cache"}
+    return out
 
 
+def streaming_ceilings(monc, torch, mib=1024, reps=5):
+    """Bandwidth of the library's streaming probes (read only, write only,
+    copy, and the 4-read 3-write pointwise update of the gradient's access
+    mix) over `mib` MiB buffers: what a plain streaming kernel reaches on
+    this device, next to the vendor peak."""
+    n = mib * (1 << 20) // 4
+    bufs = [torch.zeros(n, dtype=torch.float32, device="cuda:0") for _ in range(4)]
+    sink = torch.zeros(4, dtype=torch.float32, device="cuda:0")
+    nbytes = n * 4
+    cases = {"read": ([bufs[0], sink], 1), "write": ([bufs[0]], 1), "copy": (bufs[:2], 2),
+             "update_4r3w": (bufs, 7)}
+    out = {}
+    stream = torch.cuda.current_stream()
+    for name, (b, mult) in cases.items():
+        kind = name.split("_")[0]
+        for _ in range(2):
+            monc.stream_probe(kind, b, stream)
+        evs = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            monc.stream_probe(kind, b, stream)
+            e1.record(stream)
+            evs.append((e0, e1))
+        torch.cuda.synchronize()
+        ms = float(np.median([a.elapsed_time(c) for a, c in evs]))
+        out[name] = mult * nbytes / (ms * 1e-3) / 1e9
+    del bufs, sink
+    torch.cuda.empty_cache()
+    return out
+
+
+def _max_abs_diff(a, b, chunk=8):
+    """max |a - b| in FP64, a level chunk at a time (bounded host memory)."""
+    m = 0.0
+    for k0 in range(0, a.shape[0], chunk):
+        d = np.abs(a[k0:k0 + chunk].astype(np.float64) - b[k0:k0 + chunk].astype(np.float64))
+        m = max(m, float(d.max()) if d.size else 0.0)
+    return m
+
+
+def max_errors(out, ref, members_in):
+    """Normwise errors of u, v, w (relative to the input velocity scale) and p."""
+    u, v, w = members_in
+    vs = max(float(np.abs(u).max()), float(np.abs(v).max()), float(np.abs(w).max()))
+    errs = [_max_abs_diff(out[t], ref[t]) / vs for t in range(3)]
+    errs.append(_max_abs_diff(out[3], ref[3]) / float(np.abs(ref[3]).max()))
+    return errs
 def var_iteration_bytes_per_point(nx, mixed):
     """Algorithmic HBM bytes per grid point of one conjugate-gradient
     iteration of the variable-density projection: the operator (read d and
@@ -278,32 +421,6 @@ def _variable_density_case(monc, torch, member, reps, tol, amp):
     return out
 
 
-def device_copy_gbps(torch, mb=2048, reps=10):
-    """Read+write bandwidth of a plain device-to-device copy (context for the
-    HBM peak)."""
-    n = mb * (1 << 20) // 4
-    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        dst.copy_(src)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / reps
-    del src, dst
-    return 2 * n * 4 / dt / 1e9
-
-
-def max_errors(out, ref, members_in):
-    """Normwise errors of u, v, w (relative to the input velocity scale) and p."""
-    u, v, w = members_in
-    vs = max(np.abs(u).max(), np.abs(v).max(), np.abs(w).max())
-    errs = [float(np.abs(out[t] - ref[t]).max() / vs) for t in range(3)]
-    errs.append(float(np.abs(out[3] - ref[3]).max() / np.abs(ref[3]).max()))
-    return errs
-
-
 def cpu_baseline(members, min_s=10.0, budget_s=25.0):
     """The FP64 oracle timed on this host: whole projections of the workload's
     members in order, pass after pass, until at least min_s seconds are timed
@@ -361,62 +478,244 @@ def variable_cpu_baseline(min_s=3.0, amp=0.2):
                       f"rho0(z)(1 + {amp} f), {tot:.2f} s, host {platform.processor() or platform.machine()}"}
 
 
+
+
+# ---------------------------------------------------------------------------
+# hardware counters: a short run to profile, and its per-kernel summary
+# ---------------------------------------------------------------------------
+CALIB_MIB = 1024   # probe buffers of the counter calibration
+
+
+def pmc_run(monc, torch, members, head, other):
+    """What the counter passes profile: the probes over CALIB_MIB MiB (copy
+    twice, then read and write once each: known bytes that calibrate the
+    counters), then two projections of each path with the tuning cache's
+    tile parameters (no autotuning, so every launch of a kernel has the
+    shape the benchmark times)."""
+    n = CALIB_MIB * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.zeros_like(a)
+    sink = torch.zeros(4, dtype=torch.float32, device="cuda:0")
+    for _ in range(2):
+        monc.stream_probe("copy", [a, b])
+    monc.stream_probe("read", [a, sink])
+    monc.stream_probe("write", [b])
+    torch.cuda.synchronize()
+    del a, b, sink
+    torch.cuda.empty_cache()
+    for dtype in (head, other):
+        r = Runner(monc, torch, members, dtype, tune=False)
+        for _ in range(2):
+            r.step()
+        torch.cuda.synchronize()
+        print(f"pmc-run: {dtype} path, 2 projections, tile params {r.tuned}", flush=True)
+        del r
+        torch.cuda.empty_cache()
+
+
+_MODES_X = {"0": "div_fftx", "1": "resid_fftx", "2": "precond_fftx"}
+
+
+def classify_kernel(name):
+    """(path, kernel) of a library kernel from its demangled name, e.g.
+    'void monc::k_xfwd_ct<float, 1, 2048>(monc::LaunchArgs)' -> ('mixed',
+    'resid_fftx'); probes give ('probe', kind); None for anything else."""
+    import re
+    if "k_probe_" in name:
+        return ("probe", name.split("k_probe_", 1)[1].split("(", 1)[0].split("<", 1)[0])
+    m = re.search(r"k_(xfwd|ffty|xinv|tridiag|grad)(?:_ct|_gen)?<([^>]*)>", name)
+    if not m:
+        return None
+    kind, args = m.group(1), [x.strip() for x in m.group(2).split(",")]
+    path = "fp64" if args[0] == "double" else "mixed"
+    if kind == "xfwd":
+        return (path, _MODES_X.get(args[1], "xfwd"))
+    if kind == "ffty":
+        return (path, "ffty_inv" if args[1] == "true" else "ffty_fwd")
+    if kind == "xinv":
+        return (path, "ifftx_corr" if args[1] == "1" else "ifftx")
+    if kind == "tridiag":
+        return (path, "tridiag")
+    return (path, "grad" if path == "fp64" else "grad_final")
+
+
+def _read_counter_csv(path):
+    """{dispatch id: (kernel name, {counter: value})} of a rocprofv3
+    counter-collection CSV (one row per counter and dispatch)."""
+    import csv
+    out = {}
+    with open(path, newline="") as fh:
+        for row in csv.DictReader(fh):
+            did = row.get("Dispatch_Id") or row.get("Correlation_Id")
+            name = row.get("Kernel_Name", "")
+            ent = out.setdefault(int(did), (name, {}))
+            ent[1][row["Counter_Name"]] = ent[1].get(row["Counter_Name"], 0.0) + float(row["Counter_Value"])
+    return out
+
+
+def read_bytes(c):
+    """Bytes the L2 read from the memory side: 32, 64 and 128-byte requests."""
+    return 32.0 * c.get("TCC_EA0_RDREQ_32B_sum", 0.0) + 64.0 * c.get("TCC_EA0_RDREQ_64B_sum", 0.0) \
+        + 128.0 * c.get("TCC_EA0_RDREQ_128B_sum", 0.0)
+
+
+def write_bytes(c):
+    """Bytes the L2 wrote to the memory side: 64-byte and 32-byte requests."""
+    n64 = c.get("TCC_EA0_WRREQ_64B_sum", 0.0)
+    return 64.0 * n64 + 32.0 * (c.get("TCC_EA0_WRREQ_sum", 0.0) - n64)
+
+
+def kernel_launch_bytes(kernel, nx, points, mixed):
+    """Algorithmic bytes of one launch of a kernel as the counters see it
+    (ifftx and its correction pass separately)."""
+    f = spectral_words(nx)
+    wb = 4.0 if mixed else 8.0
+    per = {"ifftx": (f + 1) * wb, "ifftx_corr": (f + 3) * wb}.get(kernel)
+    if per is None:
+        per = kernel_bytes_per_point(kernel, nx, mixed)
+    return per * points
+
+
+def summarize_counters(rd_csv, wr_csv, workload, command):
+    """Per-kernel HBM traffic from two counter passes over `pmc_run`: read
+    bytes from the L2's 32/64/128-byte read requests, write bytes from its
+    64/32-byte write requests, each scaled by the factor that makes the
+    calibration copy (CALIB_MIB MiB read, CALIB_MIB MiB written) exact. The
+    median over a kernel's launches; all launches of a kernel have one shape
+    (no autotuning in the profiled run)."""
+    import synth
+    rd, wr = _read_counter_csv(rd_csv), _read_counter_csv(wr_csv)
+    known = CALIB_MIB * float(1 << 20)
+
+    def collect(table, fn):
+        per = {}
+        for did in sorted(table):
+            name, c = table[did]
+            cls = classify_kernel(name)
+            if cls is not None:
+                per.setdefault(cls, []).append(fn(c))
+        return per
+
+    r_all, w_all = collect(rd, read_bytes), collect(wr, write_bytes)
+    copy_r = r_all.get(("probe", "copy"), [])
+    copy_w = w_all.get(("probe", "copy"), [])
+    if not copy_r or not copy_w:
+        raise SystemExit("no calibration copy dispatch in the counter data")
+    fr = known / float(np.median(copy_r))
+    fw = known / float(np.median(copy_w))
+    g = synth.make_grid(workload)
+    lines = [f"# HBM traffic per kernel launch, {workload} ({g.nx}x{g.ny}x{g.nz} = {g.points} points)",
+             f"# command: {command}",
+             "# read bytes  = 32 TCC_EA0_RDREQ_32B + 64 TCC_EA0_RDREQ_64B + 128 TCC_EA0_RDREQ_128B (sums over",
+             "#               the L2 channels), write bytes = 64 TCC_EA0_WRREQ_64B + 32 (TCC_EA0_WRREQ -",
+             "#               TCC_EA0_WRREQ_64B); L2-to-memory-side traffic, Infinity Cache hits included",
+             f"# calibration: the probe copy of {CALIB_MIB} MiB reads and writes {int(known)} bytes; raw counters",
+             f"#   read {np.median(copy_r):.0f} and write {np.median(copy_w):.0f} bytes, so factors "
+             f"read {fr:.4f}, write {fw:.4f}",
+             f"kernels_sha256_16: {kernel_source_hash()}",
+             f"calibration.read_factor: {fr:.6f}",
+             f"calibration.write_factor: {fw:.6f}"]
+    for probe in ("read", "write"):
+        rr = r_all.get(("probe", probe))
+        ww = w_all.get(("probe", probe))
+        if rr and ww:
+            lines.append(f"probe.{probe}.read_bytes: {np.median(rr) * fr:.0f}   # expected "
+                         f"{known if probe == 'read' else 0:.0f}")
+            lines.append(f"probe.{probe}.write_bytes: {np.median(ww) * fw:.0f}   # expected "
+                         f"{known if probe == 'write' else 0:.0f}")
+    for key in sorted(k for k in r_all if k[0] != "probe"):
+        path, kern = key
+        rr = float(np.median(r_all[key])) * fr
+        ww = float(np.median(w_all.get(key, [0.0]))) * fw
+        alg = kernel_launch_bytes(kern, g.nx, g.points, path == "mixed")
+        lines.append(f"{path}.{kern}.read_bytes_per_launch: {rr:.0f}")
+        lines.append(f"{path}.{kern}.write_bytes_per_launch: {ww:.0f}")
+        lines.append(f"{path}.{kern}.bytes_per_launch: {rr + ww:.0f}   # algorithmic {alg:.0f}, "
+                     f"ratio {(rr + ww) / alg:.3f}, launches {len(r_all[key])}")
+    return "\n".join(lines) + "\n"
+
+
+# ---------------------------------------------------------------------------
+DESCRIPTIONS = {
+    "256x256x128": "plain FP64 projection 256x256x128, dx=dy=25 m, dz=min(10*1.015^k,60) m, rho0=1.2exp(-z/8 km), "
+                   "periodic x,y, rigid lids",
+    "1024x1024x256": "mixed FP32/FP64 projection with one FP64 refinement step, 1024x1024x256, "
+                     "dz=min(10*1.015^k,60) m, rho0=1.2exp(-z/8 km)",
+    "ensemble48": "batched ensemble of 48 uneven grids (64^2x64..256^2x128), one graph launch, mixed",
+    "2048x2048x160": "mixed FP32/FP64 projection with one FP64 refinement step, 2048x2048x160, dx=dy=25 m, "
+                     "dz=5*20^(k/159) m, rho0=1.2exp(-z/8 km), k^-5/3 horizontal spectra",
+    "4096x4096x64": "mixed projection 4096x4096x64 (the paper's 1.07e9-point global problem on one GPU), "
+                    "dz=min(10*1.015^k,60) m, rho0=1.2exp(-z/8 km)",
+}
+
+
 def main():
-    ap = argparse.ArgumentParser(description=__doc__)
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="256x256x128", choices=WORKLOADS)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline leg")
+    ap.add_argument("--cold-steps", type=int, default=5, help="single projections timed after a cache flush")
+    ap.add_argument("--workload", default="2048x2048x160", choices=WORKLOADS)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs (CPU baseline and accuracy)")
     ap.add_argument("--no-other", action="store_true", help="time only the headline path")
-    ap.add_argument("--no-tune", action="store_true", help="keep the default tile parameters")
+    ap.add_argument("--retune", action="store_true", help="autotune every grid, ignoring the tuning cache")
     ap.add_argument("--no-var", action="store_true", help="skip the variable-density solve")
-    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
-                    help="also run a device copy of this many MB (counter calibration)")
+    ap.add_argument("--pmc-run", action="store_true", help="the short run that the counter passes profile")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("RD_CSV", "WR_CSV"),
+                    help="print the per-kernel traffic summary of two counter passes over --pmc-run")
+    ap.add_argument("--command", default="", help="command line recorded in the counter summary")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the projection is built and measured on a single "
               "MI355X (sharding across GPUs is described, not built). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.summarize_counters:
+        sys.stdout.write(summarize_counters(*args.summarize_counters, args.workload, args.command))
+        return
 
     import torch
     import synth
     import paper_2009_12849_amd as monc
 
+    use_tuning_cache()
     wl = synth.make_workload(args.workload)
     members = wl.members
     head = "f64" if args.workload == "256x256x128" else "mixed"
     other = "mixed" if head == "f64" else "f64"
-    g = members[0].grid
-    desc = {
-        "256x256x128": f"plain FP64 projection {g.nx}x{g.ny}x{g.nz}, dx=dy=25 m, dz=min(10*1.015^k,60) m, "
-              f"rho0=1.2exp(-z/8 km), periodic x,y, rigid lids",
-        "1024x1024x256": f"mixed FP32/FP64 projection with one FP64 refinement step, {g.nx}x{g.ny}x{g.nz}, "
-              f"dz=min(10*1.015^k,60) m, rho0=1.2exp(-z/8 km)",
-        "ensemble48": f"batched ensemble of {len(members)} uneven grids (64^2x64..256^2x128), one graph launch, mixed",
-        "2048x2048x160": f"mixed projection {g.nx}x{g.ny}x{g.nz}, dz=5*20^(k/159) m, rho0=1.2exp(-z/8 km), "
-              f"k^-5/3 horizontal spectra",
-        "4096x4096x64": f"mixed projection {g.nx}x{g.ny}x{g.nz} (the paper's 1.07e9-point global problem on one "
-              f"GPU), dz=min(10*1.015^k,60) m, rho0=1.2exp(-z/8 km)",
-    }[args.workload]
+    if args.pmc_run:
+        pmc_run(monc, torch, members, head, other)
+        return
 
-    copy_gbps = device_copy_gbps(torch)
-    runner = Runner(monc, torch, members, head, tune=not args.no_tune)
-    runner.step()
-    torch.cuda.synchronize()
+    ceilings = streaming_ceilings(monc, torch)
+    flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0")   # 1 GiB
     nchk = 1 if len(members) == 1 else 3      # members whose outputs the oracle checks
-    first = ([[t.cpu().numpy().astype(np.float64) for t in f] for f in runner.fields[:nchk]]
-             if not args.no_cpu else None)
-    res = measure(runner, args.steps, args.warmup, args.workload, None)
-    reductions = None
-    if not runner.batched:
-        # the same projections with the per-level horizontal reductions fused in
-        runner.stats = torch.empty(8 * runner.plans[0].nz, dtype=torch.float64, device="cuda:0")
-        wall_r, _ = runner.timed(args.steps, args.warmup)
-        runner.stats = None
-        ms_r = 1e3 * wall_r / args.steps
-        reductions = {"ms_per_step": ms_r, "overhead_frac": ms_r / res["ms_per_step"] - 1.0,
-                      "what": "per-level horizontal mean and max of u, v, w, p (monc_project_reduce)"}
+
+    def run_path(dtype):
+        r = Runner(monc, torch, members, dtype, retune=args.retune)
+        r.step()
+        torch.cuda.synchronize()
+        first = None
+        if not args.no_cpu:
+            first = [[t.cpu().numpy() for t in f] for f in r.fields[:nchk]]
+        res = measure(r, args.steps, args.warmup, args.workload, args.cold_steps, flush)
+        res["tile_params"] = {f"{k[0]}x{k[1]}x{k[2]}": v for k, v in r.tuned.items()}
+        res["tuning"] = {f"{k[0]}x{k[1]}x{k[2]}": v for k, v in r.tuning.items()}
+        extra = {}
+        if not r.batched:
+            # the same projections with the per-level horizontal reductions fused in
+            r.stats = torch.empty(8 * r.plans[0].nz, dtype=torch.float64, device="cuda:0")
+            wall_r, _ = r.timed(args.steps, args.warmup)
+            r.stats = None
+            ms_r = 1e3 * wall_r / args.steps
+            extra["with_reductions"] = {"ms_per_step": ms_r, "overhead_frac": ms_r / res["ms_per_step"] - 1.0,
+                                        "what": "per-level horizontal mean and max of u, v, w, p "
+                                                "(monc_project_reduce)"}
+        del r
+        torch.cuda.empty_cache()
+        return res, first, extra
+
+    res, first, extra = run_path(head)
+    g = members[0].grid
     result = {
         "metric": METRIC,
         "value": res["value"],
@@ -430,72 +729,59 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if head == "f64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": desc, "grid_points": runner.points, "members": len(members),
-                   "path": "fp64" if head == "f64" else "mixed",
-                   "tile_params": {f"{k[0]}x{k[1]}x{k[2]}": v for k, v in runner.tuned.items()}},
-        "roofline": res["roofline"],
-        "path": res["path"],
-        "device_copy_GBps": copy_gbps,
-        "with_reductions": reductions,
+        "config": {"workload": DESCRIPTIONS[args.workload], "grid_points": sum(m.grid.points for m in members),
+                   "members": len(members), "path": "fp64" if head == "f64" else "mixed",
+                   "tile_params": res.pop("tile_params"), "tuning": res.pop("tuning")},
+        "roofline": res.pop("roofline"),
+        "cold": res.pop("cold", None),
+        "path": res.pop("path"),
+        "streaming_ceiling_GBps": ceilings,
     }
-    if not args.no_var and not runner.batched and runner.points <= 300_000_000:
+    result.update(extra)
+    if not args.no_var and len(members) == 1 and g.points <= 300_000_000:
         result["variable_density"] = variable_density(monc, torch, members[0])
         if not args.no_cpu:
             result["variable_density"]["cpu_baseline"] = variable_cpu_baseline()
+    ofirst = None
     if not args.no_other:
-        del runner
-        torch.cuda.empty_cache()
-        orun = Runner(monc, torch, members, other, tune=not args.no_tune)
-        orun.step()
-        torch.cuda.synchronize()
-        ofirst = ([[t.cpu().numpy().astype(np.float64) for t in f] for f in orun.fields[:nchk]]
-                  if not args.no_cpu else None)
-        ores = measure(orun, args.steps, args.warmup, args.workload, None)
+        ores, ofirst, oextra = run_path(other)
         key = "mixed" if other == "mixed" else "fp64"
-        result[key] = {"value": ores["value"], "ms_per_step": ores["ms_per_step"],
-                       "roofline": ores["roofline"], "path": ores["path"],
-                       "tile_params": {f"{k[0]}x{k[1]}x{k[2]}": v for k, v in orun.tuned.items()}}
-        sp = res["value"] / ores["value"] if head == "mixed" else ores["value"] / res["value"]
-        result["mixed_speedup_vs_fp64"] = sp
-        del orun
-    else:
-        ofirst = None
-
-    if args.calibrate_copy:
-        n = args.calibrate_copy * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        result["calibration_copy_bytes"] = 2 * n * 4
+        result[key] = dict(ores, **oextra)
+        mixed_v, fp64_v = (res, ores) if head == "mixed" else (ores, res)
+        result["mixed_speedup_vs_fp64"] = mixed_v["value"] / fp64_v["value"]
+        if mixed_v.get("cold") and fp64_v.get("cold"):
+            result["mixed_speedup_vs_fp64_cold"] = fp64_v["cold"]["ms_per_step"] / mixed_v["cold"]["ms_per_step"]
+    del flush
+    torch.cuda.empty_cache()
 
     if not args.no_cpu:
+        import oracle
         base, refs = cpu_baseline(members)
         result["cpu_baseline"] = base
         acc = {}
-        import oracle
         n = min(len(refs), nchk)
-        for name, outs in (("head", first), ("other", ofirst)):
+        for path, outs in ((head, first), (other, ofirst)):
             if outs is None:
                 continue
-            path = head if name == "head" else other
-            errs = []
+            errs, divs = [], []
             for i in range(n):
                 m = members[i]
                 ins = (m.u, m.v, m.w)
                 ref = refs[i]
                 if path == "mixed":   # the oracle on the FP32-rounded inputs
-                    g_ = m.grid
                     ins = tuple(a.astype(np.float32).astype(np.float64) for a in ins)
-                    ref = oracle.project(*ins, g_.dx, g_.dy, g_.dz, g_.rho0)
+                    ref = oracle.project(*ins, m.grid.dx, m.grid.dy, m.grid.dz, m.grid.rho0)
                 errs.append(max_errors(outs[i], ref, ins))
+                del ref
+                o64 = [x.astype(np.float64, copy=False) for x in outs[i][:3]]
+                divs.append(float(np.abs(oracle.divergence(*o64, m.grid.dx, m.grid.dy, m.grid.dz,
+                                                           m.grid.rho0)).max()))
+                del o64
             worst = [max(e[t] for e in errs) for t in range(4)]
-            div = max(float(np.abs(oracle.divergence(outs[i][0], outs[i][1], outs[i][2], members[i].grid.dx,
-                                                     members[i].grid.dy, members[i].grid.dz,
-                                                     members[i].grid.rho0)).max()) for i in range(n))
-            acc["fp64" if path == "f64" else "mixed"] = {"max_rel_err": max(worst), "rel_err_u_v_w_p": worst,
-                                                         "max_abs_divergence": div, "members_checked": n}
+            acc["fp64" if path == "f64" else "mixed"] = {
+                "max_rel_err": max(worst), "rel_err_u_v_w_p": worst, "max_abs_divergence": max(divs),
+                "members_checked": n,
+                "reference": "the FP64 oracle" + (" on the FP32-rounded inputs" if path == "mixed" else "")}
         result["accuracy"] = acc
     else:
         result["cpu_baseline"] = None

@@ -253,6 +253,22 @@ int monc_profile_read(monc_plan* plan, double* ms, int* launches);
  * Returns MONC_OK or an error. */
 int monc_autotune(monc_plan* plan, void* stream);
 
+/* Streaming-bandwidth probes: one launch of the plainest kernel that moves
+ * a known number of bytes, to measure the bandwidth a streaming kernel
+ * reaches on the device (the practical ceiling next to the vendor's HBM
+ * peak) and to calibrate hardware traffic counters. kind and buffers (device
+ * pointers, 16-byte aligned, `bytes` each unless stated, a multiple of 16):
+ *   MONC_PROBE_READ    reads a; b is a 16-byte sink that is never written
+ *                      in practice (read bytes: `bytes`);
+ *   MONC_PROBE_WRITE   writes zeros to a (written: `bytes`);
+ *   MONC_PROBE_COPY    copies a to b (read and written: `bytes` each);
+ *   MONC_PROBE_UPDATE  b, c, d -= a elementwise as floats, in place (read
+ *                      4 x `bytes`, written 3 x `bytes`).
+ * Asynchronous on `stream`. Returns MONC_OK, MONC_EINVAL (bad kind, size or
+ * pointer), MONC_EUNSUPPORTED (too large for one launch) or MONC_EHIP. */
+enum { MONC_PROBE_READ = 0, MONC_PROBE_WRITE = 1, MONC_PROBE_COPY = 2, MONC_PROBE_UPDATE = 3 };
+int monc_stream_probe(int kind, void* a, void* b, void* c, void* d, size_t bytes, void* stream);
+
 /* Number of tile parameters. */
 #define MONC_NPARAMS 5
 

@@ -17,7 +17,7 @@ from typing import Optional, Sequence
 
 import numpy as np
 
-__all__ = ["Plan", "project_batched", "lib", "last_error", "MoncError",
+__all__ = ["Plan", "project_batched", "stream_probe", "lib", "last_error", "MoncError",
            "FP64", "MIXED", "STAGE_FORWARD", "STAGE_SOLVE", "STAGE_INVERSE",
            "STAGE_GRADIENT", "STAGE_RESIDUAL", "KERNELS"]
 
@@ -80,6 +80,8 @@ def lib() -> ctypes.CDLL:
     L.monc_plan_params.argtypes = [vp, ctypes.POINTER(ip)]
     L.monc_plan_set_params.restype = ip
     L.monc_plan_set_params.argtypes = [vp, ctypes.POINTER(ip)]
+    L.monc_stream_probe.restype = ip
+    L.monc_stream_probe.argtypes = [ip, vp, vp, vp, vp, ctypes.c_size_t, vp]
     _lib = L
     return L
 
@@ -262,6 +264,27 @@ class Plan:
             raise ValueError(f"expected at most {NPARAMS} tile parameters")
         arr = (ctypes.c_int * NPARAMS)(*[int(x) for x in vals])
         _check(lib().monc_plan_set_params(self._h, arr))
+
+
+PROBES = {"read": 0, "write": 1, "copy": 2, "update": 3}
+
+
+def stream_probe(kind: str, bufs, stream=None):
+    """One launch of a streaming-bandwidth probe (see monc_stream_probe) over
+    equally sized contiguous CUDA tensors: "read" (data, 16-byte sink),
+    "write" (out), "copy" (src, dst), "update" (p, u, v, w)."""
+    need = {"read": 2, "write": 1, "copy": 2, "update": 4}[kind]
+    if len(bufs) != need:
+        raise ValueError(f"probe {kind!r} takes {need} buffers")
+    nbytes = bufs[0].numel() * bufs[0].element_size()
+    for t in bufs:
+        if not (t.is_cuda and t.is_contiguous()):
+            raise ValueError("probe buffers must be contiguous CUDA tensors")
+    for t in bufs[1:]:
+        if kind != "read" and t.numel() * t.element_size() != nbytes:
+            raise ValueError("probe buffers must have equal sizes")
+    ptrs = [ctypes.c_void_p(t.data_ptr()) for t in bufs] + [None] * (4 - len(bufs))
+    _check(lib().monc_stream_probe(PROBES[kind], *ptrs, nbytes, ctypes.c_void_p(_stream_handle(stream))))
 
 
 def project_batched(plans: Sequence[Plan], us, vs, ws, ps, stream=None):

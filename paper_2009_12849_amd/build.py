@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmonc.so")
-SOURCES = ["kernels.hip", "krylov.hip", "api.hip", "plan_math.cpp"]
+SOURCES = ["kernels.hip", "krylov.hip", "api.hip", "probe.hip", "plan_math.cpp"]
 
 # No packed FP32 instructions (v_pk_*_f32) in any HIP object.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

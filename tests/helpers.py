@@ -5,12 +5,19 @@ import numpy as np
 
 
 def relerr(x, ref):
-    """Normwise max relative error max|x - ref| / max|ref| (0 if ref == 0)."""
-    x = np.asarray(x, dtype=np.float64)
-    ref = np.asarray(ref, dtype=np.float64)
-    scale = np.max(np.abs(ref)) if ref.size else 0.0
-    diff = np.max(np.abs(x - ref)) if ref.size else 0.0
-    return float(diff / scale) if scale > 0 else float(diff)
+    """Normwise max relative error max|x - ref| / max|ref| (0 if ref == 0).
+
+    Complex arrays keep their dtype, so the modulus of the complex
+    difference (real and imaginary parts together) is what is measured."""
+    x = np.asarray(x)
+    ref = np.asarray(ref)
+    if x.shape != ref.shape:
+        raise ValueError(f"shape mismatch {x.shape} vs {ref.shape}")
+    if np.iscomplexobj(x) != np.iscomplexobj(ref):
+        raise TypeError("relerr compares real with real and complex with complex")
+    scale = float(np.max(np.abs(ref))) if ref.size else 0.0
+    diff = float(np.max(np.abs(x - ref))) if ref.size else 0.0
+    return diff / scale if scale > 0 else diff
 
 
 def max_field_relerr(out, ref):

@@ -98,3 +98,14 @@ def test_kernel_names():
     names = [L.monc_kernel_name(i).decode() for i in range(len(monc.KERNELS))]
     assert names == monc.KERNELS
     assert L.monc_kernel_name(99) == b""
+
+
+def test_stream_probe_argument_checks_run_before_the_device():
+    L = monc.lib()
+    vp = ctypes.c_void_p
+    fake = vp(1 << 20)  # aligned, never dereferenced: every call below fails its checks first
+    assert L.monc_stream_probe(9, fake, fake, fake, fake, 1024, None) == monc.EINVAL    # unknown kind
+    assert L.monc_stream_probe(2, fake, None, None, None, 1024, None) == monc.EINVAL    # copy needs b
+    assert L.monc_stream_probe(1, fake, None, None, None, 1000, None) == monc.EINVAL    # not a multiple of 16
+    assert L.monc_stream_probe(1, vp((1 << 20) + 8), None, None, None, 1024, None) == monc.EINVAL  # misaligned
+    assert L.monc_stream_probe(0, fake, None, None, None, 1024, None) == monc.EINVAL    # read needs its sink
