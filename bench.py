@@ -65,21 +65,21 @@ def kernel_bytes_per_point(kernel, nx, mixed):
         "ffty_fwd": 2 * f * wb,                 # read + write spectrum
         "tridiag": 2 * f * wb,
         "ffty_inv": 2 * f * wb,
-        # read spectrum, write p; on the mixed path the mean of its two
-        # launches: p1 (f + 1 words), then the correction (read spectrum and
-        # p1, write p and the remainder: f + 3 words)
-        "ifftx": (f + 2) * wb if mixed else (f + 1) * wb,
+        # read spectrum, write p (mixed: p1, then the correction delta)
+        "ifftx": (f + 1) * wb,
         "grad": 7 * wb,                         # read p, u, v, w; write u, v, w
         "resid_fftx": (4 + f) * wb,             # read u, v, w, p1; write spectrum
-        "grad_final": 8 * wb,                   # read p and remainder; read/write u, v, w
+        "grad_final": 9 * wb,                   # read p1, delta, u, v, w; write u, v, w, p
     }
     return table[kernel]
 
 
 def path_bytes_per_point(nx, mixed):
-    """Minimum HBM traffic of the whole path (inputs once, one round trip of
-    the spectrum per global-dependency boundary, outputs once): FP64
-    10 + 4f words, mixed with one refinement step 16 + 8f words."""
+    """Minimum HBM traffic of the whole path as built (inputs once, one round
+    trip of the spectrum per global-dependency boundary, outputs once): FP64
+    10 + 4f words; mixed 16 + 8f words: first solve 3 + f, 2f, f + 1 (p1);
+    residual 4 + f; correction 2f; final f + 1 (delta) + 2 (p1, delta) + 3
+    + 3 + 1 (p)."""
     f = spectral_words(nx)
     return (16 + 8 * f) * 4.0 if mixed else (10 + 4 * f) * 8.0
 
@@ -87,11 +87,11 @@ def path_bytes_per_point(nx, mixed):
 def kernel_path_bytes_per_point(nx, mixed):
     """What the kernels of one projection move, each launch at its
     algorithmic bytes: FP64 11 + 8f words (div-FFT 3 + f, four spectral
-    passes 2f each, inverse f + 1, gradient 7), mixed 19 + 16f words (two
-    solves, the residual 4 + f, the correction's inverse f + 3, the final
-    gradient 8)."""
+    passes 2f each, inverse f + 1, gradient 7), mixed 18 + 16f words
+    (div-FFT 3 + f, two solves' spectral passes, two inverses f + 1, the
+    residual 4 + f, the final gradient 9)."""
     f = spectral_words(nx)
-    return (19 + 16 * f) * 4.0 if mixed else (11 + 8 * f) * 8.0
+    return (18 + 16 * f) * 4.0 if mixed else (11 + 8 * f) * 8.0
 
 
 def kernel_source_hash():
@@ -570,7 +570,7 @@ def kernel_launch_bytes(kernel, nx, points, mixed):
     (ifftx and its correction pass separately)."""
     f = spectral_words(nx)
     wb = 4.0 if mixed else 8.0
-    per = {"ifftx": (f + 1) * wb, "ifftx_corr": (f + 3) * wb}.get(kernel)
+    per = {"ifftx": (f + 1) * wb, "ifftx_corr": (f + 1) * wb}.get(kernel)
     if per is None:
         per = kernel_bytes_per_point(kernel, nx, mixed)
     return per * points
@@ -747,10 +747,12 @@ def main():
         ores, ofirst, oextra = run_path(other)
         key = "mixed" if other == "mixed" else "fp64"
         result[key] = dict(ores, **oextra)
-        mixed_v, fp64_v = (res, ores) if head == "mixed" else (ores, res)
+        head_cold = result["cold"]
+        mixed_v, fp64_v = (result, ores) if head == "mixed" else (ores, result)
         result["mixed_speedup_vs_fp64"] = mixed_v["value"] / fp64_v["value"]
-        if mixed_v.get("cold") and fp64_v.get("cold"):
-            result["mixed_speedup_vs_fp64_cold"] = fp64_v["cold"]["ms_per_step"] / mixed_v["cold"]["ms_per_step"]
+        if head_cold and ores.get("cold"):
+            mc, fc = (head_cold, ores["cold"]) if head == "mixed" else (ores["cold"], head_cold)
+            result["mixed_speedup_vs_fp64_cold"] = fc["ms_per_step"] / mc["ms_per_step"]
     del flush
     torch.cuda.empty_cache()
 

@@ -95,9 +95,14 @@ void monc_plan_destroy(monc_plan* plan);
  *   p       : device array (nz, ny, nx), output only, gauge sum dz*p = 0;
  *   stream  : a hipStream_t (NULL = the default stream).
  * All four pointers must be non-null, 16-byte aligned and non-overlapping.
- * The mixed path returns p = p1 + delta rounded to float, and u = u* -
- * G(p1) - G(delta) evaluated in FP64 before rounding, so differencing the
- * returned float p does not reproduce u to full accuracy.
+ * The mixed path (Sec. 4's single-precision solver with Sec. 5's
+ * double-precision restart, as one refinement step): a first solve with the
+ * FP32 divergence, FP32 transforms and the FP64 tridiagonal gives p1; the
+ * residual D(u*) - D(G p1) is formed in FP64 from the float inputs and
+ * solved the same way for a correction delta; p1 + delta is summed in FP64. It returns p = p1 + delta rounded to float, and u = u* - G(p1 +
+ * delta) evaluated in FP64 before rounding, so differencing the returned
+ * float p does not reproduce u to full accuracy. Scratch: two float fields
+ * of the plan's size, allocated with the plan.
  * Returns MONC_OK, MONC_EINVAL or MONC_EHIP.
  */
 int monc_project(monc_plan* plan, void* u, void* v, void* w, void* p, void* stream);
@@ -211,7 +216,8 @@ size_t monc_spectral_layout(const monc_plan* plan, int* row_len, int* col_block,
  *                       ignored); spec is overwritten;
  *   MONC_STAGE_GRADIENT bufs = {p, u, v, w}: u -= G p (in place), w lid = 0;
  *   MONC_STAGE_RESIDUAL bufs = {u, v, w, p, spec} (MIXED only): spec = FFT of
- *                       the FP64 residual D(u) - D(G p) rounded to float.
+ *                       the FP64 residual D(u) - D(G p) rounded to float
+ *                       (the refinement's right-hand side).
  * Returns MONC_OK, MONC_EINVAL or MONC_EHIP. */
 enum {
   MONC_STAGE_FORWARD = 1,

@@ -93,7 +93,8 @@ struct monc_plan {
   MemberDesc* d_desc = nullptr;            // device copy
   void* d_tables = nullptr;
   void* d_spec = nullptr;
-  float* d_prem = nullptr;
+  float* d_s1 = nullptr;     // mixed path scratch: divergence, then the correction
+  float* d_s2 = nullptr;     // mixed path scratch: first-pass pressure
   size_t spec_elems = 0;
   void* d_var = nullptr;     // work vectors of monc_project_var (allocated at its first call)
   MemberDesc h_pre{};        // the preconditioner's descriptor: h plus the solver's done flag
@@ -371,14 +372,16 @@ extern "C" monc_plan* monc_plan_create(int nx, int ny, int nz, double dx, double
   auto release = [&]() {
     if (pl->d_tables) (void)hipFree(pl->d_tables);
     if (pl->d_spec) (void)hipFree(pl->d_spec);
-    if (pl->d_prem) (void)hipFree(pl->d_prem);
+    if (pl->d_s1) (void)hipFree(pl->d_s1);
+    if (pl->d_s2) (void)hipFree(pl->d_s2);
     if (pl->d_desc) (void)hipFree(pl->d_desc);
   };
   if (hipMalloc(&pl->d_tables, tables_bytes) != hipSuccess ||
       hipMalloc(&pl->d_spec, pl->spec_elems * cplx_bytes(dtype)) != hipSuccess ||
       hipMalloc((void**)&pl->d_desc, sizeof(MemberDesc)) != hipSuccess ||
       (dtype == MONC_MIXED &&
-       hipMalloc((void**)&pl->d_prem, (size_t)nx * ny * nz * sizeof(float)) != hipSuccess)) {
+       (hipMalloc((void**)&pl->d_s1, (size_t)nx * ny * nz * sizeof(float)) != hipSuccess ||
+        hipMalloc((void**)&pl->d_s2, (size_t)nx * ny * nz * sizeof(float)) != hipSuccess))) {
     (void)hipGetLastError();
     release();
     fail(MONC_ENOMEM, "device allocation failed for a %dx%dx%d plan", nx, ny, nz);
@@ -410,7 +413,6 @@ extern "C" monc_plan* monc_plan_create(int nx, int ny, int nz, double dx, double
   h.twx = base + o_tx;
   h.twy = base + o_ty;
   h.spec = pl->d_spec;
-  h.prem = pl->d_prem;
   if (upload_desc(pl.get()) != MONC_OK) {
     release();
     return nullptr;
@@ -426,7 +428,8 @@ extern "C" void monc_plan_destroy(monc_plan* pl) {
   drop_batch_cache_for(pl->id);
   if (pl->d_tables) (void)hipFree(pl->d_tables);
   if (pl->d_spec) (void)hipFree(pl->d_spec);
-  if (pl->d_prem) (void)hipFree(pl->d_prem);
+  if (pl->d_s1) (void)hipFree(pl->d_s1);
+  if (pl->d_s2) (void)hipFree(pl->d_s2);
   if (pl->d_desc) (void)hipFree(pl->d_desc);
   if (pl->d_var) (void)hipFree(pl->d_var);
   delete pl;
@@ -465,7 +468,9 @@ struct Group {
   bool fp64 = true;
 };
 
-enum Phase { PH_XFWD, PH_XPRE, PH_RESID, PH_YFWD, PH_TRI, PH_YINV, PH_XINV, PH_XINV_CORR, PH_GRAD, PH_GRAD_MIXED };
+enum Phase {
+  PH_XFWD, PH_XPRE, PH_RESID, PH_YFWD, PH_TRI, PH_YINV, PH_XINV, PH_XINV_P1, PH_XINV_CORR, PH_GRAD, PH_GRAD_MIXED
+};
 
 static int phase_kernel_id(Phase ph) {
   switch (ph) {
@@ -474,14 +479,16 @@ static int phase_kernel_id(Phase ph) {
     case PH_YFWD: return MONC_K_FFTY_FWD;
     case PH_TRI: return MONC_K_TRIDIAG;
     case PH_YINV: return MONC_K_FFTY_INV;
-    case PH_XINV: case PH_XINV_CORR: return MONC_K_IFFTX;
+    case PH_XINV: case PH_XINV_P1: case PH_XINV_CORR: return MONC_K_IFFTX;
     case PH_GRAD: return MONC_K_GRAD;
     case PH_GRAD_MIXED: return MONC_K_GRAD_FINAL;
   }
   return 0;
 }
 
-static bool is_xphase(Phase ph) { return ph == PH_XFWD || ph == PH_XPRE || ph == PH_RESID || ph == PH_XINV || ph == PH_XINV_CORR; }
+static bool is_xphase(Phase ph) {
+  return ph == PH_XFWD || ph == PH_XPRE || ph == PH_RESID || ph == PH_XINV || ph == PH_XINV_P1 || ph == PH_XINV_CORR;
+}
 static bool is_yphase(Phase ph) { return ph == PH_YFWD || ph == PH_YINV; }
 
 // Launch shape of one member in one phase. Members whose shapes agree share
@@ -585,6 +592,7 @@ static int launch_one(const Group& g, const std::vector<int>& idx, Phase ph, con
     case PH_YINV: launch_ffty(a, grid, block, lds, g.fp64, true, v, stream); break;
     case PH_TRI: launch_tridiag(a, grid, block, lds, g.fp64, v, stream); break;
     case PH_XINV: launch_xinv(a, grid, block, lds, g.fp64, 0, v, stream); break;
+    case PH_XINV_P1: launch_xinv(a, grid, block, lds, false, 2, v, stream); break;
     case PH_XINV_CORR: launch_xinv(a, grid, block, lds, false, 1, v, stream); break;
     case PH_GRAD:
     case PH_GRAD_MIXED: {
@@ -646,9 +654,26 @@ static int run_phases(const std::vector<Group>& groups, const std::vector<Phase>
 
 static const std::vector<Phase>& full_sequence(bool fp64) {
   static const std::vector<Phase> f64 = {PH_XFWD, PH_YFWD, PH_TRI, PH_YINV, PH_XINV, PH_GRAD};
-  static const std::vector<Phase> mixed = {PH_XFWD, PH_YFWD, PH_TRI, PH_YINV, PH_XINV, PH_RESID,
+  // mixed: the first solve leaves p1 in s2; the residual D(u*) - L p1
+  // (FP64) is solved for the correction delta (into s1); the gradient kernel
+  // forms p1 + delta in FP64, corrects u, v, w with it and writes p
+  static const std::vector<Phase> mixed = {PH_XFWD, PH_YFWD, PH_TRI, PH_YINV, PH_XINV_P1, PH_RESID,
                                            PH_YFWD, PH_TRI,  PH_YINV, PH_XINV_CORR, PH_GRAD_MIXED};
   return fp64 ? f64 : mixed;
+}
+
+// The launch pointers of one member: caller fields, the plan's spectral
+// workspace and (mixed plans) its two scratch fields.
+static IoPtrs plan_io(const monc_plan* pl, void* u, void* v, void* w, void* p) {
+  IoPtrs io;
+  io.u = u;
+  io.v = v;
+  io.w = w;
+  io.p = p;
+  io.spec = pl->d_spec;
+  io.s1 = pl->d_s1;
+  io.s2 = pl->d_s2;
+  return io;
 }
 
 // ---------------------------------------------------------------------------
@@ -689,7 +714,7 @@ extern "C" int monc_project(monc_plan* pl, void* u, void* v, void* w, void* p, v
   if (rc != MONC_OK) return rc;
   Group g;
   g.fp64 = pl->dtype == MONC_FP64;
-  g.mem.push_back({&pl->h, pl->d_desc, IoPtrs{u, v, w, p, pl->d_spec}});
+  g.mem.push_back({&pl->h, pl->d_desc, plan_io(pl, u, v, w, p)});
   std::vector<Group> groups{g};
   return run_phases(groups, full_sequence(g.fp64), stream, pl->prof.mask ? &pl->prof : nullptr);
 }
@@ -713,7 +738,7 @@ extern "C" int monc_project_reduce(monc_plan* pl, void* u, void* v, void* w, voi
   if (rc != MONC_OK) return rc;
   Group g;
   g.fp64 = pl->dtype == MONC_FP64;
-  IoPtrs io{u, v, w, p, pl->d_spec};
+  IoPtrs io = plan_io(pl, u, v, w, p);
   io.stats = stats;
   g.mem.push_back({&pl->h, pl->d_desc, io});
   std::vector<Group> groups{g};
@@ -853,7 +878,11 @@ extern "C" int monc_project_var(monc_plan* pl, const double* rho, double* u, dou
     return fail(MONC_EHIP, "monc_project_var: descriptor upload failed");
   Group pre;
   pre.fp64 = z64;
-  pre.mem.push_back({&pl->h_pre, ws.desc, IoPtrs{ws.r, nullptr, nullptr, ws.z, pl->d_spec}});
+  IoPtrs pio;
+  pio.u = ws.r;
+  pio.p = ws.z;
+  pio.spec = pl->d_spec;
+  pre.mem.push_back({&pl->h_pre, ws.desc, pio});
   static const std::vector<Phase> pre_seq = {PH_XPRE, PH_YFWD, PH_TRI, PH_YINV, PH_XINV};
   const std::vector<Group> pre_groups{pre};
   // z_it = M^-1 r_it, <r_it, z_it>, <z_it, q_{it-1}>, then d_it
@@ -938,7 +967,7 @@ extern "C" int monc_project_var(monc_plan* pl, const double* rho, double* u, dou
   // u = u* - G p, w = 0 on the lid: the FP64 gradient kernel
   Group gr;
   gr.fp64 = true;
-  gr.mem.push_back({&pl->h, pl->d_desc, IoPtrs{u, v, w, p, pl->d_spec}});
+  gr.mem.push_back({&pl->h, pl->d_desc, plan_io(pl, u, v, w, p)});
   const std::vector<Group> grad_groups{gr};
   static const std::vector<Phase> grad_seq = {PH_GRAD};
   return run_phases(grad_groups, grad_seq, stream, prof);
@@ -956,12 +985,15 @@ extern "C" int monc_debug_stage(monc_plan* pl, int stage, void* const* bufs, int
   auto need = [&](int n) { return nbufs == n ? MONC_OK : fail(MONC_EINVAL, "stage %d takes %d buffers (got %d)", stage, n, nbufs); };
   for (int i = 0; i < nbufs; ++i)
     if (!bufs[i] || reinterpret_cast<uintptr_t>(bufs[i]) % 16) return fail(MONC_EINVAL, "buffer %d is null or misaligned", i);
-  IoPtrs io{nullptr, nullptr, nullptr, nullptr, nullptr};
+  IoPtrs io;
   std::vector<Phase> seq;
   switch (stage) {
     case MONC_STAGE_FORWARD:
       if ((rc = need(4))) return rc;
-      io = IoPtrs{bufs[0], bufs[1], bufs[2], nullptr, bufs[3]};
+      io.u = bufs[0];
+      io.v = bufs[1];
+      io.w = bufs[2];
+      io.spec = bufs[3];
       seq = {PH_XFWD, PH_YFWD};
       break;
     case MONC_STAGE_SOLVE:
@@ -978,13 +1010,20 @@ extern "C" int monc_debug_stage(monc_plan* pl, int stage, void* const* bufs, int
     case MONC_STAGE_GRADIENT:
       if ((rc = need(4))) return rc;
       if (!fp64) return fail(MONC_EINVAL, "the gradient stage takes an FP64 pressure (FP64 plans only)");
-      io = IoPtrs{bufs[1], bufs[2], bufs[3], bufs[0], nullptr};
+      io.u = bufs[1];
+      io.v = bufs[2];
+      io.w = bufs[3];
+      io.p = bufs[0];
       seq = {PH_GRAD};
       break;
     case MONC_STAGE_RESIDUAL:
       if ((rc = need(5))) return rc;
       if (fp64) return fail(MONC_EINVAL, "the residual stage exists on MIXED plans only");
-      io = IoPtrs{bufs[0], bufs[1], bufs[2], bufs[3], bufs[4]};
+      io.u = bufs[0];
+      io.v = bufs[1];
+      io.w = bufs[2];
+      io.s2 = static_cast<float*>(bufs[3]);
+      io.spec = bufs[4];
       seq = {PH_RESID, PH_YFWD};
       break;
     default:
@@ -1049,7 +1088,7 @@ static int build_groups(monc_plan* const* plans, int count, void* const* u, void
   g.fp64 = plans[0]->dtype == MONC_FP64;
   for (int t = 0; t < count; ++t) {
     const int i = ord[t];
-    g.mem.push_back({&plans[i]->h, d_array + t, IoPtrs{u[i], v[i], w[i], p[i], plans[i]->d_spec}});
+    g.mem.push_back({&plans[i]->h, d_array + t, plan_io(plans[i], u[i], v[i], w[i], p[i])});
   }
   groups.push_back(std::move(g));
   return MONC_OK;

@@ -18,20 +18,20 @@ inline int ct_threads_host(int n) { return ct_threads_x_n(n); }
 inline int ct_threads_y_host(int n) { return ct_threads_y_n(n); }
 
 // ct_n: the compile-time length, or 0 for the runtime-length kernel.
-// mode 0: divergence of (u, v, w); mode 1 (float only): FP64 residual
-// D(u) - D(G p) with p the first-pass pressure; mode 2: the FP64 field at
-// io.u (nz, ny, nx), rounded to the storage type.
+// mode 0: divergence of (u, v, w); mode 1 (float only): the FP64 residual
+// D(u) - D(G p1) with the first-pass pressure p1 in io.s2; mode 2: the FP64
+// field at io.u (nz, ny, nx), rounded to the storage type.
 void launch_xfwd(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, int mode, int ct_n, void* stream);
 void launch_ffty(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, bool inverse, int ct_n,
                  void* stream);
 // rows: rows per lane, one of kTriRows (the member's tris)
 void launch_tridiag(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, int rows, void* stream);
-// mode 0: write p; mode 1 (float only): p = fl32(p1 + delta) and its FP32
-// remainder in MemberDesc::prem
+// the result goes to io.p (mode 0), io.s1 (mode 1, float only: the
+// correction delta) or io.s2 (mode 2, float only: the first-pass pressure)
 void launch_xinv(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, int mode, int ct_n, void* stream);
-// fp64: pressure from io.p (FP64); else (mixed path) p1 + delta from the
-// float pair io.p + MemberDesc::prem. vec: points per thread (2 needs an even
-// nx, 4 a multiple of 4; else 1)
+// fp64: pressure from io.p (FP64); else (mixed path) p1 + delta summed in
+// FP64 from io.s2 + io.s1, and written rounded to io.p. vec: points per
+// thread (2 needs an even nx, 4 a multiple of 4; else 1)
 // red: also the per-level horizontal mean and max of u, v, w, p into io.stats
 // (after launch_stats_init on the same stream)
 void launch_grad(const LaunchArgs& a, int grid, bool fp64, int vec, bool red, void* stream);

@@ -169,28 +169,57 @@ __device__ __forceinline__ float div_at<float>(const MemberDesc& d, const RowCtx
   return c.rho0f * hor + (ft - fb) * c.rdzf;
 }
 
-// FP64 residual r = D(u* - G p1) of the mixed path, from float u*, p1.
-__device__ __forceinline__ double resid_at(const MemberDesc& d, const RowCtx& c, const float* __restrict__ u,
-                                           const float* __restrict__ v, const float* __restrict__ w,
-                                           const float* __restrict__ p, int i) {
+// Global-address-space views of a generic pointer (the scratch fields and
+// the output pressure come from a by-value argument struct, so the compiler
+// cannot infer their address space and would emit flat accesses).
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gptr(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
+// FP64 operator L p1 = D(G p1) at one point from the float first-pass
+// pressure p1 and its six neighbours (pE, pW along x, pN, pS along y, pU, pD
+// along z; pU, pD ignored on the lid and bottom rows).
+__device__ __forceinline__ double lap_at(const MemberDesc& d, const RowCtx& c, double p0, double pE, double pW,
+                                         double pN, double pS, double pU, double pD) {
+  const double gxe = (pE - p0) * d.rdx, gxw = (p0 - pW) * d.rdx;
+  const double gyn = (pN - p0) * d.rdy, gys = (p0 - pS) * d.rdy;
+  const double ft = c.top ? c.rhow * ((pU - p0) * c.rdzc) : 0.0;
+  const double fb = c.bot ? c.rhowm * ((p0 - pD) * c.rdzcm) : 0.0;
+  return c.rho0 * ((gxe - gxw) * d.rdx + (gyn - gys) * d.rdy) + (ft - fb) * c.rdz;
+}
+
+// FP64 divergence D(u*) of float fields at one point
+__device__ __forceinline__ double div64_at(const MemberDesc& d, const RowCtx& c, const float* __restrict__ u,
+                                           const float* __restrict__ v, const float* __restrict__ w, int i) {
+  const int im = (i == 0) ? d.nx - 1 : i - 1;
+  const double hor = ((double)u[c.off + i] - (double)u[c.off + im]) * d.rdx +
+                     ((double)v[c.off + i] - (double)v[c.soff + i]) * d.rdy;
+  const double ft = c.top ? c.rhow * (double)w[c.off + i] : 0.0;
+  const double fb = c.bot ? c.rhowm * (double)w[c.off - c.plane + i] : 0.0;
+  return c.rho0 * hor + (ft - fb) * c.rdz;
+}
+
+// FP64 residual r = D(u*) - L p1 of the mixed path at one point, from the
+// float inputs u*, v*, w* and the first-pass pressure p1 (io.s2).
+__device__ __forceinline__ double resid_at(const MemberDesc& d, const RowCtx& c, const IoPtrs& io, int i) {
+  const float* __restrict__ p = io.s2;
   const int nx = d.nx;
   const int im = (i == 0) ? nx - 1 : i - 1;
   const int ip = (i == nx - 1) ? 0 : i + 1;
   const double pc = p[c.off + i];
-  const double ue = (double)u[c.off + i] - ((double)p[c.off + ip] - pc) * d.rdx;
-  const double uw = (double)u[c.off + im] - (pc - (double)p[c.off + im]) * d.rdx;
-  const double vn = (double)v[c.off + i] - ((double)p[c.noff + i] - pc) * d.rdy;
-  const double vs = (double)v[c.soff + i] - (pc - (double)p[c.soff + i]) * d.rdy;
-  double ft = 0.0, fb = 0.0;
-  if (c.top) ft = c.rhow * ((double)w[c.off + i] - ((double)p[c.off + c.plane + i] - pc) * c.rdzc);
-  if (c.bot) fb = c.rhowm * ((double)w[c.off - c.plane + i] - (pc - (double)p[c.off - c.plane + i]) * c.rdzcm);
-  return c.rho0 * ((ue - uw) * d.rdx + (vn - vs) * d.rdy) + (ft - fb) * c.rdz;
+  const double pu = c.top ? (double)p[c.off + c.plane + i] : pc;
+  const double pd = c.bot ? (double)p[c.off - c.plane + i] : pc;
+  const double b = div64_at(d, c, reinterpret_cast<const float*>(io.u), reinterpret_cast<const float*>(io.v),
+                            reinterpret_cast<const float*>(io.w), i);
+  return b - lap_at(d, c, pc, p[c.off + ip], p[c.off + im], p[c.noff + i], p[c.soff + i], pu, pd);
 }
 
 // Sources of the x-forward transform: MODE 0 the divergence D(u*), MODE 1
-// the mixed path's FP64 residual, MODE 2 a given FP64 field (io.u) rounded to
-// T, i.e. the spectral solve applied to an arbitrary right-hand side (the
-// preconditioner of the variable-density Krylov solver).
+// the mixed path's FP64 residual D(u*) - L p1, MODE 2 a given FP64 field
+// (io.u) rounded to T, i.e. the spectral solve applied to an arbitrary
+// right-hand side (the preconditioner of the variable-density Krylov
+// solver).
 template <typename T, int MODE>
 __device__ __forceinline__ T source_at(const MemberDesc& d, const RowCtx& c, const IoPtrs& io, int i) {
   if constexpr (MODE == 0) {
@@ -199,8 +228,7 @@ __device__ __forceinline__ T source_at(const MemberDesc& d, const RowCtx& c, con
   } else if constexpr (MODE == 2) {
     return (T)reinterpret_cast<const double*>(io.u)[c.off + i];
   } else {
-    return (T)resid_at(d, c, reinterpret_cast<const float*>(io.u), reinterpret_cast<const float*>(io.v),
-                       reinterpret_cast<const float*>(io.w), reinterpret_cast<const float*>(io.p), i);
+    return (T)resid_at(d, c, io, i);
   }
 }
 
@@ -313,29 +341,25 @@ __device__ __forceinline__ void div_pair_vec(const MemberDesc& d, const RowCtx& 
   }
 }
 
-// FP64 residual D(u* - G p1) at points i0 .. i0+3 of a row (float data)
 typedef float f4v __attribute__((ext_vector_type(4)));
 
-// The residual of one row from its loaded neighbourhood (pc: the row,
-// pn/ps: rows j +- 1, pu/pd: levels k +- 1, pe/pw: x-neighbours outside the
-// vector, um: u west of the vector).
+// FP64 residual D(u*) - L p1 at points i0 .. i0+3 of a row from the loaded
+// neighbourhood (float data; pc: p1 of the row, pn/ps: rows j +- 1, pu/pd:
+// levels k +- 1, pe/pw: x-neighbours outside the vector, um: u west of the
+// vector; pu/pd, wc/wb ignored on the lid and bottom rows).
 __device__ __forceinline__ void resid_core(const MemberDesc& d, const RowCtx& c, f4v pc, f4v pn, f4v ps, f4v pu,
                                            f4v pd, float pw, float pe, f4v uc, float um, f4v vc, f4v vs, f4v wc,
                                            f4v wb, float* out) {
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
-    const double p0 = pc[e];
+    const double uW = (e > 0) ? (double)uc[(e + 3) & 3] : (double)um;
+    const double hor = ((double)uc[e] - uW) * d.rdx + ((double)vc[e] - (double)vs[e]) * d.rdy;
+    const double ft = c.top ? c.rhow * (double)wc[e] : 0.0;
+    const double fb = c.bot ? c.rhowm * (double)wb[e] : 0.0;
+    const double b = c.rho0 * hor + (ft - fb) * c.rdz;
     const double pE = (e < 3) ? (double)pc[(e + 1) & 3] : (double)pe;
     const double pW = (e > 0) ? (double)pc[(e + 3) & 3] : (double)pw;
-    const double uW = (e > 0) ? (double)uc[(e + 3) & 3] : (double)um;
-    const double ue = (double)uc[e] - (pE - p0) * d.rdx;
-    const double uw = uW - (p0 - pW) * d.rdx;
-    const double vn = (double)vc[e] - ((double)pn[e] - p0) * d.rdy;
-    const double vv = (double)vs[e] - (p0 - (double)ps[e]) * d.rdy;
-    double ft = 0.0, fb = 0.0;
-    if (c.top) ft = c.rhow * ((double)wc[e] - ((double)pu[e] - p0) * c.rdzc);
-    if (c.bot) fb = c.rhowm * ((double)wb[e] - (p0 - (double)pd[e]) * c.rdzcm);
-    out[e] = (float)(c.rho0 * ((ue - uw) * d.rdx + (vn - vv) * d.rdy) + (ft - fb) * c.rdz);
+    out[e] = (float)(b - lap_at(d, c, pc[e], pE, pW, pn[e], ps[e], pu[e], pd[e]));
   }
 }
 
@@ -344,7 +368,7 @@ __device__ __forceinline__ void resid_vec(const MemberDesc& d, const RowCtx& c, 
   const float* __restrict__ u = reinterpret_cast<const float*>(io.u);
   const float* __restrict__ v = reinterpret_cast<const float*>(io.v);
   const float* __restrict__ w = reinterpret_cast<const float*>(io.w);
-  const float* __restrict__ p = reinterpret_cast<const float*>(io.p);
+  const float* __restrict__ p = io.s2;
   const int nx = d.nx;
   const int iw = (i0 == 0) ? nx - 1 : i0 - 1, ie = (i0 + 4 == nx) ? 0 : i0 + 4;
   const f4v pc = ldv(p + c.off + i0);
@@ -365,14 +389,14 @@ __device__ __forceinline__ void resid_vec(const MemberDesc& d, const RowCtx& c, 
   resid_core(d, c, pc, pn, ps, pu, pd, pw, pe, uc, um, vc, vs, wc, wb, out);
 }
 
-// Both rows of a pair (k, j) and (k, j+1) of one level: they share p rows j
+// Both rows of a pair (k, j) and (k, j+1) of one level: they share p1 rows j
 // and j+1 and v row j, so 17 vector loads serve the two rows instead of 20.
 __device__ __forceinline__ void resid_pair_vec(const MemberDesc& d, const RowCtx& c0, const RowCtx& c1,
                                                const IoPtrs& io, int i0, float* out0, float* out1) {
   const float* __restrict__ u = reinterpret_cast<const float*>(io.u);
   const float* __restrict__ v = reinterpret_cast<const float*>(io.v);
   const float* __restrict__ w = reinterpret_cast<const float*>(io.w);
-  const float* __restrict__ p = reinterpret_cast<const float*>(io.p);
+  const float* __restrict__ p = io.s2;
   const int nx = d.nx;
   const int iw = (i0 == 0) ? nx - 1 : i0 - 1, ie = (i0 + 4 == nx) ? 0 : i0 + 4;
   const f4v ps = ldv(p + c0.soff + i0), p0 = ldv(p + c0.off + i0), p1 = ldv(p + c1.off + i0);
@@ -411,7 +435,7 @@ __device__ __forceinline__ void source_vec(const MemberDesc& d, const RowCtx& c,
       out[e + 1] = (T)x[1];
     }
   } else {
-    resid_vec(d, c, io, i0, out);
+    resid_vec(d, c, io, i0, reinterpret_cast<float*>(out));
   }
 }
 
@@ -524,29 +548,35 @@ __global__ void __launch_bounds__(512) k_xfwd_ct(LaunchArgs a) {
   auto stencil = [&](int t) {
     const int i0 = (q + t * NT) * V;
     T s0[V], s1[V];
-    if (MODE == 0 && !(d.ny & 1) && v1) {
-      // divergence of a full pair within one level (even ny): shared loads
-      div_pair_vec<T>(d, c0, c1, io, i0, s0, s1);
-    } else if constexpr (sizeof(T) == 8) {
-      // FP64: both rows unconditionally (an invalid row's context points at
-      // row 0), so all loads of the chunk issue together; invalid rows zeroed
-      source_vec<T, MODE>(d, c0, io, i0, s0);
-      source_vec<T, MODE>(d, c1, io, i0, s1);
+    // a full pair within one level (even ny): the two rows share loads
+    const bool pair = !(d.ny & 1) && v1;
+    if constexpr (sizeof(T) == 8) {
+      if (MODE == 0 && pair) {
+        div_pair_vec<T>(d, c0, c1, io, i0, s0, s1);
+      } else {
+        // both rows unconditionally (an invalid row's context points at row
+        // 0), so all loads of the chunk issue together; invalid rows zeroed
+        source_vec<T, MODE>(d, c0, io, i0, s0);
+        source_vec<T, MODE>(d, c1, io, i0, s1);
 #pragma unroll
-      for (int e = 0; e < V; ++e) {
-        s0[e] = v0 ? s0[e] : (T)0;
-        s1[e] = v1 ? s1[e] : (T)0;
+        for (int e = 0; e < V; ++e) {
+          s0[e] = v0 ? s0[e] : (T)0;
+          s1[e] = v1 ? s1[e] : (T)0;
+        }
       }
-    } else if (MODE == 1 && !(d.ny & 1) && v1) {
-      // residual of a full pair within one level (even ny): shared loads
-      resid_pair_vec(d, c0, c1, io, i0, s0, s1);
     } else {
-      if (v0) source_vec<T, MODE>(d, c0, io, i0, s0);
-      else
-        for (int e = 0; e < V; ++e) s0[e] = (T)0;
-      if (v1) source_vec<T, MODE>(d, c1, io, i0, s1);
-      else
-        for (int e = 0; e < V; ++e) s1[e] = (T)0;
+      if (pair && MODE == 0) {
+        div_pair_vec<T>(d, c0, c1, io, i0, s0, s1);
+      } else if (pair && MODE == 1) {
+        resid_pair_vec(d, c0, c1, io, i0, s0, s1);
+      } else {
+        if (v0) source_vec<T, MODE>(d, c0, io, i0, s0);
+        else
+          for (int e = 0; e < V; ++e) s0[e] = (T)0;
+        if (v1) source_vec<T, MODE>(d, c1, io, i0, s1);
+        else
+          for (int e = 0; e < V; ++e) s1[e] = (T)0;
+      }
     }
 #pragma unroll
     for (int e = 0; e < V; ++e) lds[xpad<T, N>(i0 + e)] = cx<T>{s0[e], s1[e]};
@@ -717,10 +747,10 @@ __global__ void __launch_bounds__(1024) k_ffty_gen(LaunchArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// x-direction inverse (complex-to-real) FFT of row pairs.
-// MODE 0: write p (storage type T).
-// MODE 1 (mixed, T = float): the transform is the correction delta; read p1
-//         from p, write p1 + delta to p (float) and its remainder to prem.
+// x-direction inverse (complex-to-real) FFT of row pairs, written to
+// MODE 0: io.p (storage type T), the pressure;
+// MODE 1 (mixed, T = float): io.s1, the refinement's correction delta;
+// MODE 2 (mixed, T = float): io.s2, the first-pass pressure p1.
 // Z[m] = X_a[m] + i X_b[m], Z[N-m] = conj X_a[m] + i conj X_b[m]; the
 // imaginary parts of the self-conjugate bins (m = 0, m = N/2) are dropped.
 // ---------------------------------------------------------------------------
@@ -750,27 +780,19 @@ __device__ __forceinline__ void pack_rows(cx<T>* buf, const Idx& idx, const cx<T
 }
 
 template <typename T, int MODE>
+__device__ __forceinline__ __attribute__((address_space(1))) T* xinv_dest(const IoPtrs& io) {
+  if constexpr (MODE == 0) return gptr(reinterpret_cast<T*>(io.p));
+  else if constexpr (MODE == 1) return gptr(reinterpret_cast<T*>(io.s1));
+  else return gptr(reinterpret_cast<T*>(io.s2));
+}
+
+template <typename T, int MODE>
 __device__ __forceinline__ void store_rows(const MemberDesc& d, const IoPtrs& io, long long r0, long long r1, bool v0,
                                            bool v1, int i, cx<T> z) {
   const int N = d.nx;
-  T* p = reinterpret_cast<T*>(io.p);
-  if constexpr (MODE == 0) {
-    if (v0) p[r0 * N + i] = z.x;
-    if (v1) p[r1 * N + i] = z.y;
-  } else {
-    if (v0) {
-      const double s = (double)p[r0 * N + i] + (double)z.x;
-      const float f = (float)s;
-      d.prem[r0 * N + i] = (float)(s - (double)f);
-      p[r0 * N + i] = f;
-    }
-    if (v1) {
-      const double s = (double)p[r1 * N + i] + (double)z.y;
-      const float f = (float)s;
-      d.prem[r1 * N + i] = (float)(s - (double)f);
-      p[r1 * N + i] = f;
-    }
-  }
+  auto p = xinv_dest<T, MODE>(io);
+  if (v0) p[r0 * N + i] = z.x;
+  if (v1) p[r1 * N + i] = z.y;
 }
 
 template <typename T, int MODE, int N>
@@ -837,7 +859,7 @@ __global__ void __launch_bounds__(512) k_xinv_ct(LaunchArgs a) {
   // vector phase: 16-byte chunks of both rows
   constexpr int V = Vec<T>::n;
   using vt = typename Vec<T>::type;
-  T* __restrict__ p = reinterpret_cast<T*>(io.p);
+  auto p = reinterpret_cast<__attribute__((address_space(1))) vt*>(xinv_dest<T, MODE>(io));
 #pragma unroll
   for (int t = 0; t < N / (V * NT); ++t) {
     const int i0 = (q + t * NT) * V;
@@ -848,31 +870,8 @@ __global__ void __launch_bounds__(512) k_xinv_ct(LaunchArgs a) {
       a0[e] = z.x;
       a1[e] = z.y;
     }
-    if constexpr (MODE == 0) {
-      if (v0) stv(p + r0 * N + i0, a0);
-      if (v1) stv(p + r1 * N + i0, a1);
-    } else {
-      // p1 + delta formed in FP64 and kept as a float pair: p = fl32(sum)
-      // and the remainder sum - p (exact in FP64, rounded to FP32: the pair
-      // carries the sum to about 2^-48 relative)
-#pragma unroll
-      for (int row = 0; row < 2; ++row) {
-        const bool ok = row ? v1 : v0;
-        if (!ok) continue;
-        const long long o = (row ? r1 : r0) * N + i0;
-        const vt p1 = ldv(p + o);
-        const vt dl = row ? a1 : a0;
-        vt pf, pr;
-#pragma unroll
-        for (int e = 0; e < V; ++e) {
-          const double sum = (double)p1[e] + (double)dl[e];
-          pf[e] = (T)sum;
-          pr[e] = (T)(sum - (double)pf[e]);
-        }
-        *(__attribute__((address_space(1))) vt*)(d.prem + o) = pr;
-        stv(p + o, pf);
-      }
-    }
+    if (v0) p[(r0 * N + i0) / V] = a0;
+    if (v1) p[(r1 * N + i0) / V] = a1;
   }
 }
 
@@ -1292,9 +1291,9 @@ k_tridiag(LaunchArgs a) {
 
 // ---------------------------------------------------------------------------
 // Pressure-gradient correction u -= G p, evaluated in FP64 from an FP64
-// pressure (p itself on the FP64 path, p1 + delta rebuilt from the float
-// pair p + remainder on the mixed path); the
-// fields are T. A thread owns VEC consecutive points of one row of one
+// pressure (p itself on the FP64 path; on the mixed path p1 + delta, summed
+// in FP64 from the two float scratch fields, and written rounded to float as
+// the output p); the fields are T. A thread owns VEC consecutive points of one row of one
 // level (vector loads and stores need nx % VEC == 0); w[nz-1] = 0.
 // ---------------------------------------------------------------------------
 // Per-level horizontal reductions of the projection's outputs (the
@@ -1391,16 +1390,16 @@ __global__ void __launch_bounds__(256) k_grad(LaunchArgs a) {
   T* __restrict__ v = reinterpret_cast<T*>(io.v);
   T* __restrict__ w = reinterpret_cast<T*>(io.w);
   const bool top = k == nz - 1;
-  // p in FP64: the FP64 path's p, or on the mixed path the float pair
-  // (p, remainder) = p1 + delta written by the correction pass. Loads go
-  // through global-address-space pointers (the remainder buffer comes from
-  // the descriptor, a generic pointer).
+  // p in FP64: the FP64 path's p, or on the mixed path p1 + delta from the
+  // first-pass pressure (io.s2) and the correction (io.s1), summed in FP64.
+  // Loads go through global-address-space pointers (the pointers come from a
+  // by-value argument struct).
   auto ldp = [&](long long o) -> dv {
     if constexpr (sizeof(T) == 8) {
       return ldg(reinterpret_cast<const dv*>(reinterpret_cast<const double*>(io.p) + o));
     } else {
-      const tv hi = ldg(reinterpret_cast<const tv*>(reinterpret_cast<const float*>(io.p) + o));
-      const tv lo = ldg(reinterpret_cast<const tv*>(d.prem + o));
+      const tv hi = ldg(reinterpret_cast<const tv*>(io.s2 + o));
+      const tv lo = ldg(reinterpret_cast<const tv*>(io.s1 + o));
       dv r;
 #pragma unroll
       for (int e = 0; e < VEC; ++e) r[e] = (double)hi[e] + (double)lo[e];
@@ -1409,7 +1408,7 @@ __global__ void __launch_bounds__(256) k_grad(LaunchArgs a) {
   };
   auto ldp1 = [&](long long o) -> double {
     if constexpr (sizeof(T) == 8) return ldg(reinterpret_cast<const double*>(io.p) + o);
-    else return (double)ldg(reinterpret_cast<const float*>(io.p) + o) + (double)ldg(d.prem + o);
+    else return (double)ldg(io.s2 + o) + (double)ldg(io.s1 + o);
   };
   const dv pc = ldp(g);
   const dv pn = ldp(hn);
@@ -1435,6 +1434,13 @@ __global__ void __launch_bounds__(256) k_grad(LaunchArgs a) {
     *reinterpret_cast<tv*>(u + g) = uu;
     *reinterpret_cast<tv*>(v + g) = vv;
     *reinterpret_cast<tv*>(w + g) = ww;
+    if constexpr (sizeof(T) == 4) {
+      // the mixed path's pressure output: p1 + delta rounded to float
+      tv po;
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) po[e] = (T)pc[e];
+      *reinterpret_cast<__attribute__((address_space(1))) tv*>(gptr(reinterpret_cast<T*>(io.p) + g)) = po;
+    }
   }
   if constexpr (RED) {
     double st[8];
@@ -1497,6 +1503,7 @@ void init_kernel_attributes() {
   set_lds_limit(k_xinv_gen<double, 0>);
   set_lds_limit(k_xinv_gen<float, 0>);
   set_lds_limit(k_xinv_gen<float, 1>);
+  set_lds_limit(k_xinv_gen<float, 2>);
 #define MONC_TRI_ATTR(S)                   \
   set_lds_limit(k_tridiag<double, S, 256>); \
   set_lds_limit(k_tridiag<float, S, 256>);  \
@@ -1516,7 +1523,8 @@ void init_kernel_attributes() {
   set_lds_limit(k_ffty_ct<float, true, N>);   \
   set_lds_limit(k_xinv_ct<double, 0, N>);     \
   set_lds_limit(k_xinv_ct<float, 0, N>);      \
-  set_lds_limit(k_xinv_ct<float, 1, N>);
+  set_lds_limit(k_xinv_ct<float, 1, N>);      \
+  set_lds_limit(k_xinv_ct<float, 2, N>);
   MONC_CT_SIZES(MONC_ATTR)
 #undef MONC_ATTR
 }
@@ -1576,14 +1584,16 @@ void launch_xinv(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64
   case N:                                                   \
     if (fp64) MONC_GO((k_xinv_ct<double, 0, N>));           \
     else if (mode == 0) MONC_GO((k_xinv_ct<float, 0, N>));  \
-    else MONC_GO((k_xinv_ct<float, 1, N>));                 \
+    else if (mode == 1) MONC_GO((k_xinv_ct<float, 1, N>));  \
+    else MONC_GO((k_xinv_ct<float, 2, N>));                 \
     return;
     MONC_CT_SIZES(MONC_CASE)
 #undef MONC_CASE
     default:
       if (fp64) MONC_GO((k_xinv_gen<double, 0>));
       else if (mode == 0) MONC_GO((k_xinv_gen<float, 0>));
-      else MONC_GO((k_xinv_gen<float, 1>));
+      else if (mode == 1) MONC_GO((k_xinv_gen<float, 1>));
+      else MONC_GO((k_xinv_gen<float, 2>));
   }
 }
 

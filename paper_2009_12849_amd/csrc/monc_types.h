@@ -5,7 +5,7 @@
 // monc_project_batched). Static per-member data (sizes, metric tables,
 // twiddles, FFT plans, tile parameters, workspace) lives in a device array of
 // MemberDesc; the per-call field pointers and the block ranges of the members
-// travel by value in LaunchArgs (about 3.3 KB, under the 4 KB kernel-argument
+// travel by value in LaunchArgs (about 3.6 KB, under the 4 KB kernel-argument
 // limit).
 #pragma once
 #include <stdint.h>
@@ -13,7 +13,7 @@
 namespace monc {
 
 constexpr int kMaxPass = 16;            // radix passes of one FFT (3^8 needs 8)
-constexpr int kMaxLaunchMembers = 64;   // members per grouped launch
+constexpr int kMaxLaunchMembers = 48;   // members per grouped launch (LaunchArgs under 4 KB)
 constexpr int kTriSmax = 16;            // rows per lane in the tridiagonal solver
 constexpr int kTriPmax = 64;            // lanes per column (one wave)
 constexpr int kBig = 1 << 30;           // "inactive" lane index
@@ -121,16 +121,19 @@ struct MemberDesc {
   // solver's converged flag: while *skip != 0 the FFT and tridiagonal
   // kernels do nothing
   const double* skip;
-  float* prem;            // mixed path: remainder (p1 + delta) - fl32(p1 + delta) in FP32, (nz, ny, nx)
 };
 
 struct IoPtrs {
-  void* u;
-  void* v;
-  void* w;
-  void* p;
-  void* spec;             // spectral buffer used by this launch
-  double* stats;          // per-level horizontal mean and max of u, v, w, p, or null
+  void* u = nullptr;
+  void* v = nullptr;
+  void* w = nullptr;
+  void* p = nullptr;
+  void* spec = nullptr;     // spectral buffer used by this launch
+  double* stats = nullptr;  // per-level horizontal mean and max of u, v, w, p, or null
+  // mixed path, two float fields (nz, ny, nx) of scratch: s2 holds the
+  // first-pass pressure p1, s1 the refinement's correction delta
+  float* s1 = nullptr;
+  float* s2 = nullptr;
 };
 
 struct LaunchArgs {
@@ -139,5 +142,6 @@ struct LaunchArgs {
   const MemberDesc* mem[kMaxLaunchMembers];  // device descriptors
   IoPtrs io[kMaxLaunchMembers];
 };
+static_assert(sizeof(LaunchArgs) <= 4096, "kernel arguments are limited to 4 KB");
 
 }  // namespace monc
