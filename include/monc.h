@@ -108,6 +108,22 @@ void monc_plan_destroy(monc_plan* plan);
 int monc_project(monc_plan* plan, void* u, void* v, void* w, void* p, void* stream);
 
 /*
+ * monc_project without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc. Same arguments, results (bit for bit) and errors as
+ * monc_project, plus MONC_EUNSUPPORTED for a plan whose workspace does not fit
+ * the limit below. The workspace (the spectral buffer, and on MIXED plans
+ * the two float scratch fields) comes from a static device array of 128 MiB
+ * per GPU (enough for a 256x256x128 grid on either path), held until the
+ * process ends; the plan's own workspace is left untouched. No part of it
+ * needs clearing: every call writes what it reads. All calls on one GPU
+ * share that array, so calls that overlap in time on one GPU race (serialise
+ * them, e.g. on one stream). Its device address is resolved when a plan is
+ * created on the device (else at the first call). No profiling events.
+ */
+int monc_project_noalloc(monc_plan* plan, void* u, void* v, void* w, void* p, void* stream);
+
+/*
  * Project `count` independent members in one go. plans[i] is member i's
  * plan; u[i], v[i], w[i], p[i] are its arrays as in monc_project. All plans
  * must share one dtype and one device. The whole batch is validated before

@@ -54,6 +54,8 @@ def lib() -> ctypes.CDLL:
     L.monc_plan_destroy.argtypes = [vp]
     L.monc_project.restype = ip
     L.monc_project.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.monc_project_noalloc.restype = ip
+    L.monc_project_noalloc.argtypes = [vp, vp, vp, vp, vp, vp]
     L.monc_project_reduce.restype = ip
     L.monc_project_reduce.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.monc_project_var.restype = ip
@@ -177,6 +179,12 @@ class Plan:
                 or not stats.is_contiguous():
             raise ValueError(f"stats must be a contiguous float64 device tensor of {8 * self.nz} values")
         _check(lib().monc_project_reduce(self._h, *args, ctypes.c_void_p(stats.data_ptr()), st))
+
+    def project_noalloc(self, u, v, w, p, stream=None):
+        """project() with its workspace in the library's static device array
+        (see monc_project_noalloc): no device allocation."""
+        args = [self._field(t, n) for t, n in ((u, "u"), (v, "v"), (w, "w"), (p, "p"))]
+        _check(lib().monc_project_noalloc(self._h, *args, ctypes.c_void_p(_stream_handle(stream))))
 
     def project_var(self, rho, u, v, w, p, tol=1e-12, maxit=200, stream=None):
         """Projection with the density field rho(x, y, z) (see

@@ -248,6 +248,37 @@ static void write_cache(const char* path, const std::map<std::string, std::vecto
 }
 
 // ---------------------------------------------------------------------------
+// static workspace of the allocation-free entry point (monc_project_noalloc)
+// ---------------------------------------------------------------------------
+// One array per GPU, held until the process ends. In host code the name
+// `scratch` only stands for the symbol: its device address (different on
+// every device) comes from hipGetSymbolAddress, resolved once per device with
+// that device current and kept in g_scratch_ptr.
+static constexpr size_t kStaticScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the static workspace on the current device.
+static int static_scratch(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(MONC_EHIP, "hipGetDevice failed");
+  if (dev < 0 || dev >= kMaxDevices) return fail(MONC_EUNSUPPORTED, "device %d is beyond the %d supported", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(MONC_EHIP, "hipGetSymbolAddress of the static workspace failed on device %d: %s", dev,
+                  hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return MONC_OK;
+}
+
+// ---------------------------------------------------------------------------
 // plan creation
 // ---------------------------------------------------------------------------
 extern "C" monc_plan* monc_plan_create(int nx, int ny, int nz, double dx, double dy, const double* dz,
@@ -367,6 +398,12 @@ extern "C" monc_plan* monc_plan_create(int nx, int ny, int nz, double dx, double
   if (hipGetDevice(&pl->device) != hipSuccess) {
     fail(MONC_EHIP, "hipGetDevice failed (no usable HIP device)");
     return nullptr;
+  }
+  {
+    // set-up of the allocation-free entry point on this device (its first
+    // call retries and reports a failure)
+    void* unused = nullptr;
+    (void)static_scratch(&unused);
   }
   pl->spec_elems = (size_t)nz * h.plane;
   auto release = [&]() {
@@ -743,6 +780,43 @@ extern "C" int monc_project_reduce(monc_plan* pl, void* u, void* v, void* w, voi
   g.mem.push_back({&pl->h, pl->d_desc, io});
   std::vector<Group> groups{g};
   return run_phases(groups, full_sequence(g.fp64), stream, pl->prof.mask ? &pl->prof : nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// allocation-free projection
+// ---------------------------------------------------------------------------
+static size_t align256(size_t x);
+
+extern "C" int monc_project_noalloc(monc_plan* pl, void* u, void* v, void* w, void* p, void* stream) {
+  if (!pl) return fail(MONC_EINVAL, "plan is null");
+  void* ptrs[4] = {u, v, w, p};
+  int rc = check_fields(pl, ptrs, 4, "monc_project_noalloc");
+  if (rc != MONC_OK) return rc;
+  rc = check_device(pl);
+  if (rc != MONC_OK) return rc;
+  const bool fp64 = pl->dtype == MONC_FP64;
+  const size_t spec = align256(pl->spec_elems * cplx_bytes(pl->dtype));
+  const size_t field = align256((size_t)pl->nx * pl->ny * pl->nz * sizeof(float));
+  const size_t need = spec + (fp64 ? 0 : 2 * field);
+  if (need > kStaticScratchBytes)
+    return fail(MONC_EUNSUPPORTED,
+                "monc_project_noalloc: a %dx%dx%d %s plan needs %zu bytes of workspace, above the static %zu",
+                pl->nx, pl->ny, pl->nz, fp64 ? "FP64" : "MIXED", need, kStaticScratchBytes);
+  void* base = nullptr;
+  rc = static_scratch(&base);
+  if (rc != MONC_OK) return rc;
+  // the plan's own workspace is not touched: every kernel takes its
+  // workspace pointers from the launch arguments
+  unsigned char* b = static_cast<unsigned char*>(base);
+  IoPtrs io = plan_io(pl, u, v, w, p);
+  io.spec = b;
+  io.s1 = fp64 ? nullptr : reinterpret_cast<float*>(b + spec);
+  io.s2 = fp64 ? nullptr : reinterpret_cast<float*>(b + spec + field);
+  Group g;
+  g.fp64 = fp64;
+  g.mem.push_back({&pl->h, pl->d_desc, io});
+  std::vector<Group> groups{g};
+  return run_phases(groups, full_sequence(fp64), stream, nullptr);  // no profiling events
 }
 
 // ---------------------------------------------------------------------------

@@ -76,6 +76,7 @@ def test_null_plan_calls_are_errors():
     L = monc.lib()
     assert L.monc_project(None, None, None, None, None, None) == monc.EINVAL
     assert L.monc_project_reduce(None, None, None, None, None, None, None) == monc.EINVAL
+    assert L.monc_project_noalloc(None, None, None, None, None, None) == monc.EINVAL
     assert L.monc_project_var(None, None, None, None, None, None, 1e-10, 10, None, None, None) == monc.EINVAL
     assert "plan is null" in monc.last_error()
     assert L.monc_spectral_layout(None, None, None, None, None) == 0
