@@ -780,10 +780,22 @@ def main():
                                                            m.grid.rho0)).max()))
                 del o64
             worst = [max(e[t] for e in errs) for t in range(4)]
-            acc["fp64" if path == "f64" else "mixed"] = {
-                "max_rel_err": max(worst), "rel_err_u_v_w_p": worst, "max_abs_divergence": max(divs),
-                "members_checked": n,
-                "reference": "the FP64 oracle" + (" on the FP32-rounded inputs" if path == "mixed" else "")}
+            rec = {"max_rel_err": max(worst), "rel_err_u_v_w_p": worst, "max_abs_divergence": max(divs),
+                   "members_checked": n,
+                   "reference": "the FP64 oracle" + (" on the FP32-rounded inputs" if path == "mixed" else "")}
+            if path == "f64" and len(members) == 1:
+                # the round-off floor of p on this input: the spread of two
+                # FP64 column solves (bottom-up and top-down elimination) of
+                # the oracle's spectrum
+                from tests.tolerances import reference_noise
+                m = members[0]
+                b_spec = oracle.forward_spectrum(oracle.divergence(m.u, m.v, m.w, m.grid.dx, m.grid.dy,
+                                                                   m.grid.dz, m.grid.rho0))
+                floor = reference_noise(b_spec, refs[0][3], m.grid)
+                del b_spec
+                rec["p_roundoff_floor"] = floor
+                rec["p_err_over_floor"] = worst[3] / floor if floor > 0 else None
+            acc["fp64" if path == "f64" else "mixed"] = rec
         result["accuracy"] = acc
     else:
         result["cpu_baseline"] = None

@@ -343,6 +343,11 @@ extern "C" monc_plan* monc_plan_create(int nx, int ny, int nz, double dx, double
   // host tables
   VerticalTables vt = vertical_tables(nz, dz, rho0);
   h.rH = vt.rH;
+  {
+    double sr = 0.0;
+    for (int k = 0; k < nz; ++k) sr += dz[k] * rho0[k];
+    h.rSr = 1.0 / sr;
+  }
   std::vector<double> lamx = modified_wavenumbers(nx, h.nxh, dx);
   std::vector<double> lamy = modified_wavenumbers(ny, ny, dy);
   std::vector<double> twx = twiddles(nx), twy = twiddles(ny);

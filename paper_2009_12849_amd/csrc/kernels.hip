@@ -1108,6 +1108,37 @@ __device__ __forceinline__ void tri_tile(const MemberDesc& d, const IoPtrs& io, 
     }
   }
 
+  // Deflation of the near-null direction (FP64 storage). The dz-weighted sum
+  // of a column's rows cancels its vertical fluxes, which leaves
+  // sum_k dz_k B_k = -lam sum_k dz_k rho0_k P_k: the component of P along
+  // the constants, c = -sum dz B / (lam sum dz rho0), is known in closed
+  // form. With P = c + Q the elimination solves T Q = B - rho0 sum dz B /
+  // sum dz rho0 for the part orthogonal to it, so round-off amplified by the
+  // near-singularity of the low-wavenumber columns (lam -> 0) acts on Q, not
+  // on the large c ~ 1/lam. The (0,0) column (lam = 0) keeps its own gauge
+  // treatment; padding columns have B = 0, so c = 0.
+  double2 cdef = make_double2(0.0, 0.0);
+  if constexpr (!F32) {
+    double2 sb = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int r = 0; r < S; ++r) {
+      const double dzr = (k0 + r < nz) ? ldg(d.dz + (k0 + r)) : 0.0;
+      sb.x += dzr * D[r].x;
+      sb.y += dzr * D[r].y;
+    }
+    sb = column_sum(sb, P);  // every lane of the column takes part
+    if (!singular) {
+      const double gx = sb.x * d.rSr, gy = sb.y * d.rSr;
+#pragma unroll
+      for (int r = 0; r < S; ++r) {  // R0 = rho0 on real rows, 0 past nz
+        D[r].x -= R0[r] * gx;
+        D[r].y -= R0[r] * gy;
+      }
+      const double il = 1.0 / lam;
+      cdef = make_double2(-gx * il, -gy * il);
+    }
+  }
+
   // 1. chunk elimination: x_r + al_r x_0 + ga_r x_{r+1} = de_r (r >= 1), then
   //    backward to x_r = e_r - f_r x_0 - g_r x_{S-1}, kept in (de, al, ga)
   double al[S], ga[S];
@@ -1215,6 +1246,14 @@ __device__ __forceinline__ void tri_tile(const MemberDesc& d, const IoPtrs& io, 
     else {
       const double2 e = scol[q * SP + r - PK0];
       X[r] = make_double2(e.x - al[r] * F.x - ga[r] * L.x, e.y - al[r] * F.y - ga[r] * L.y);
+    }
+  }
+  // the deflated constant back (0 for the (0,0) and padding columns)
+  if constexpr (!F32) {
+#pragma unroll
+    for (int r = 0; r < S; ++r) {
+      X[r].x += cdef.x;
+      X[r].y += cdef.y;
     }
   }
   // (0,0) column: gauge sum_k dz_k P_k = 0

@@ -75,6 +75,7 @@ struct MemberDesc {
   double rdx, rdy;        // 1/dx, 1/dy
   double inv_nxny;        // 1/(nx ny), the inverse-FFT normalisation
   double rH;              // 1 / sum(dz)
+  double rSr;             // 1 / sum(dz rho0), the near-null deflation of the column solves
   float rdxf, rdyf;       // FP32 copies for the FP32 stencil
   // FP64 vertical tables, all of length nz
   const double* rho0;     // reference density at centres

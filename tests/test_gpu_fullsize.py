@@ -157,3 +157,64 @@ def test_full_ensemble_batched_manufactured(dtype):
         _check(mf.errors(*f, s), mf.g, dtype, f"member {mi} {mf.g.nx}x{mf.g.ny}x{mf.g.nz}")
     for pl in plans:
         pl.close()
+
+
+# ---------------------------------------------------------------------------
+# The benchmark's own inputs, element by element against the oracle
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def bench1024():
+    """The 1024^2 x 256 workload (seeded, as bench.py draws it), the FP64
+    oracle's answer on it, the spread of two FP64 column solves on it (the
+    round-off floor of p) and the oracle's answer on its FP32 rounding."""
+    import oracle
+    from tests.tolerances import reference_noise
+    m = synth.make_workload("1024x1024x256").members[0]
+    g = m.grid
+    print("bench1024: oracle (FP64 inputs)", flush=True)
+    ref = oracle.project(m.u, m.v, m.w, g.dx, g.dy, g.dz, g.rho0, intermediates=True)
+    noise = reference_noise(ref["B"], ref["p"], g)
+    ref64 = (ref["u"], ref["v"], ref["w"], ref["p"])
+    del ref
+    print("bench1024: oracle (FP32-rounded inputs)", flush=True)
+    u32, v32, w32 = (a.astype(np.float32) for a in (m.u, m.v, m.w))
+    ref32 = oracle.project(u32.astype(np.float64), v32.astype(np.float64), w32.astype(np.float64),
+                           g.dx, g.dy, g.dz, g.rho0)
+    return {"g": g, "in64": (m.u, m.v, m.w), "ref64": ref64, "noise": noise,
+            "in32": (u32, v32, w32), "ref32": ref32}
+
+
+@pytest.mark.parametrize("dtype", ["f64", "mixed"])
+def test_benchmark_inputs_1024_against_oracle(bench1024, dtype):
+    """Both paths on the 1024^2 x 256 benchmark inputs, compared with the
+    oracle at every point. FP64: u, v, w within 1e-12 of the input scale and
+    p within 16 times the spread of two FP64 column solves of the same
+    spectrum (reference_noise: the round-off floor this input's conditioning
+    allows; the GPU's elimination deflates the near-null mode of every
+    column, so it stays within a few times that floor). Mixed: every field
+    within 1e-6 of the oracle on the FP32-rounded inputs."""
+    b = bench1024
+    g = b["g"]
+    ins = b["in64"] if dtype == "f64" else b["in32"]
+    ref = b["ref64"] if dtype == "f64" else b["ref32"]
+    plan = monc.Plan.from_grid(g, dtype)
+    print(f"case bench1024 {dtype}: autotune", flush=True)
+    tuned = _tune([plan])
+    fields = [torch.from_numpy(np.ascontiguousarray(a)).to(DEV) for a in ins]
+    fields.append(torch.empty_like(fields[0]))
+    print(f"case bench1024 {dtype}: project with {tuned}", flush=True)
+    plan.project(*fields)
+    torch.cuda.synchronize()
+    out = [t.cpu().numpy() for t in fields]
+    del fields
+    vs = max(float(np.abs(a).max()) for a in ins)
+    errs = [float(np.abs(out[t].astype(np.float64) - ref[t]).max()) / vs for t in range(3)]
+    errs.append(float(np.abs(out[3].astype(np.float64) - ref[3]).max()) / float(np.abs(ref[3]).max()))
+    print(f"bench1024 {dtype} errors u, v, w, p: {errs}; FP64 round-off floor of p {b['noise']:.3e}", flush=True)
+    assert float(np.abs(out[2][-1]).max()) == 0.0
+    if dtype == "f64":
+        assert max(errs[:3]) <= TOL64, errs
+        assert errs[3] <= max(1e-13, 16.0 * b["noise"]), (errs, b["noise"])
+    else:
+        assert max(errs) <= TOL_MIXED, errs
+    plan.close()

@@ -24,7 +24,10 @@ import paper_2009_12849_amd as monc  # noqa: E402
 
 DEV = "cuda:0"
 TOL = 1e-12
-SHAPES = [(32, 32, 16), (48, 27, 13), (24, 18, 9), (4, 4, 1), (1, 6, 5), (1, 1, 4)]
+# odd nx (27, 81) takes the one-point operator kernel with real x neighbours;
+# nx = 384 leaves a partial 256-point x tile in every stencil kernel
+SHAPES = [(32, 32, 16), (48, 27, 13), (24, 18, 9), (4, 4, 1), (1, 6, 5), (1, 1, 4), (27, 9, 6), (81, 6, 4),
+          (384, 4, 3)]
 
 
 def _case(shape, seed, amp=0.3):
@@ -183,14 +186,24 @@ def test_full_size_variable_density(name):
         pw = np.abs(o[3]).max() * np.sum(dz) * g.nx * g.ny
         assert abs(np.sum(dz[:, None, None] * o[3])) <= 1e-12 * pw
         outs[dtype] = o
-    # the two answers differ by at most the solver tolerance times the
-    # operator's condition number (density contrast 1.2/0.8)
-    cond = _cond_estimate(g.nx, g.ny, g.dx, g.dy, dz)
+    # Both stop at relative residual 1e-10. A tighter FP64 solve (1e-12)
+    # serves as the reference: the FP64-preconditioned answer's distance from
+    # it measures the error a 1e-10 stop leaves on this input, and the FP32-
+    # preconditioned answer must lie within a small multiple of that.
+    o, it, rel = _run(g, rho, u, v, w, "f64", tol=1e-12, maxit=500)
+    print(f"  tight FP64 reference: iterations {it}, relative residual {rel:.3e}", flush=True)
+    assert rel <= 1e-11
     scale = max(np.abs(a).max() for a in (u, v, w))
-    du = max(np.abs(outs["f64"][f] - outs["mixed"][f]).max() for f in range(3)) / scale
-    dp = np.abs(outs["f64"][3] - outs["mixed"][3]).max() / np.abs(outs["f64"][3]).max()
-    print(f"  cond estimate {cond:.2e}; FP64 vs FP32 preconditioner: u, v, w {du:.2e}, p {dp:.2e}", flush=True)
-    assert dp <= 1e-10 * cond and du <= 1e-10 * cond
+    pref = np.abs(o[3]).max()
+    dist = {}
+    for dtype in ("f64", "mixed"):
+        du = max(np.abs(outs[dtype][f] - o[f]).max() for f in range(3)) / scale
+        dp = np.abs(outs[dtype][3] - o[3]).max() / pref
+        dist[dtype] = (du, dp)
+    print(f"  distance from the tight solve (u, v, w; p): FP64 preconditioner {dist['f64']}, "
+          f"FP32 preconditioner {dist['mixed']}", flush=True)
+    for i in range(2):
+        assert dist["mixed"][i] <= 10.0 * dist["f64"][i] + 1e-13, dist
 
 
 @pytest.mark.parametrize("dtype", ["f64", "mixed"])

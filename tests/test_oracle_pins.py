@@ -361,6 +361,41 @@ def test_golden_single_column():
     assert np.allclose(wo.ravel(), 0.0, atol=1e-15)
 
 
+def test_golden_face_density_column_pair():
+    # the separable oracle and the variable-density oracle with rho = rho0(z)
+    # both reproduce the hand-derived overturning cell, which depends on the
+    # w-face density
+    gd = _read_golden("face_density_column_pair.txt")
+    dx, dy, dz, rho0 = float(gd["dx"][0]), float(gd["dy"][0]), gd["dz"], gd["rho0"]
+    shape = (2, 1, 2)
+    z = np.zeros(shape)
+    w = gd["w_in"].reshape(shape)
+    out_sep = oracle.project(z, z, w, dx, dy, dz, rho0)
+    rho = np.broadcast_to(rho0[:, None, None], shape).copy()
+    out_var = oracle.project_var(z, z, w, dx, dy, dz, rho)
+    for uo, vo, wo, p in (out_sep, out_var):
+        assert np.allclose(uo.ravel(), gd["u83"] / 83.0, rtol=0, atol=1e-14)
+        assert np.allclose(vo, 0.0, atol=1e-15)
+        assert np.allclose(wo.ravel(), gd["w83"] / 83.0, rtol=0, atol=1e-14)
+        assert np.allclose(p.ravel(), gd["p83"] / 83.0, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("axis", ["x", "y"])
+def test_golden_face_density_ring(axis):
+    gd = _read_golden("face_density_x_ring.txt")
+    shape = (1, 1, 3) if axis == "x" else (1, 3, 1)
+    rho = gd["rho"].reshape(shape)
+    z = np.zeros(shape)
+    f_in = gd["u_in"].reshape(shape)
+    u_in, v_in = (f_in, z) if axis == "x" else (z, f_in)
+    uo, vo, wo, p = oracle.project_var(u_in, v_in, z, 1.0, 1.0, np.ones(1), rho)
+    got = uo if axis == "x" else vo
+    other = vo if axis == "x" else uo
+    assert np.allclose(got.ravel(), gd["u21"] / 21.0, rtol=0, atol=1e-14)
+    assert np.allclose(other, 0.0, atol=1e-15)
+    assert np.allclose(p.ravel(), gd["p63"] / 63.0, rtol=0, atol=1e-14)
+
+
 # ----------------------------------------------------------------------------
 # The pins catch plausible mistakes planted in the oracle (CPU only)
 # ----------------------------------------------------------------------------
@@ -422,6 +457,33 @@ def test_pins_catch_planted_mistake(mutant, monkeypatch):
     monkeypatch.setattr(op, name, fn)
     worst = max(brute_error(6, 4, 5, seed=1), brute_error(5, 3, 4, seed=2))
     assert worst > 1e-6, f"planted mistake {mutant} went unnoticed ({worst})"
+
+
+def test_golden_catches_midpoint_face_density(monkeypatch):
+    # the hand-derived w-face fixture fails when rhow is the plain mean
+    monkeypatch.setattr(op, "vertical_grid", _plain_mean_rhow)
+    with pytest.raises(AssertionError):
+        test_golden_face_density_column_pair()
+
+
+import oracle.variable as _ov  # noqa: E402
+
+_ORIG_FACES = _ov.face_densities
+
+
+def _cell_value_faces(rho, dz):
+    # a plausible slip: an x or y face takes the density of the cell on its
+    # west / south side instead of the mean of the two cells
+    rx, ry, rz = _ORIG_FACES(rho, dz)
+    rho = np.asarray(rho, dtype=np.float64)
+    return rho.copy(), rho.copy(), rz
+
+
+@pytest.mark.parametrize("axis", ["x", "y"])
+def test_golden_catches_cell_value_face_density(axis, monkeypatch):
+    monkeypatch.setattr(_ov, "face_densities", _cell_value_faces)
+    with pytest.raises(AssertionError):
+        test_golden_face_density_ring(axis)
 
 
 def test_level_stats_closed_form():
