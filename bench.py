@@ -162,7 +162,23 @@ def cached_params(nx, ny, nz, dtype):
             data = json.load(fh)
         except ValueError:
             return None
-    return data.get(f"gfx950:{nx},{ny},{nz}:{'fp64' if dtype == 'f64' else 'mixed'}")
+    val = data.get(f"gfx950:{nx},{ny},{nz}:{'fp64' if dtype == 'f64' else 'mixed'}")
+    return val if isinstance(val, list) and len(val) == 6 else None   # the library reads 6 values
+
+
+def cached_batch(count, dtype):
+    """Whether the tuning cache holds a batch schedule for `count` members of
+    this dtype."""
+    path = os.environ.get("MONC_TUNE_CACHE")
+    if not path or not os.path.exists(path):
+        return False
+    with open(path) as fh:
+        try:
+            data = json.load(fh)
+        except ValueError:
+            return False
+    tag = "fp64" if dtype == "f64" else "mixed"
+    return any(k.startswith(f"gfx950:batch:{count}:") and k.endswith(tag) for k in data)
 
 
 class Runner:
@@ -177,20 +193,31 @@ class Runner:
         self.plans = [monc.Plan.from_grid(m.grid, dtype) for m in members]
         self.tuned = {}
         self.tuning = {}
+        self.schedule = None
         # tile parameters: the tuning cache's (read by the library at plan
         # creation), else the library's autotuner once per distinct grid
-        # (untimed); plans of the same grid share them
-        for pl in self.plans:
-            key = (pl.nx, pl.ny, pl.nz)
-            if key in self.tuned:
-                pl.params = self.tuned[key]
-                continue
-            if tune and (retune or cached_params(pl.nx, pl.ny, pl.nz, dtype) is None):
-                pl.autotune()
-                self.tuning[key] = "autotuned"
-            else:
-                self.tuning[key] = "cache" if cached_params(pl.nx, pl.ny, pl.nz, dtype) else "default"
-            self.tuned[key] = pl.params
+        # (untimed); plans of the same grid share them. A batch is tuned as a
+        # whole (tile parameters of its grids, then its member order and
+        # grouping) unless the cache holds it.
+        missing = any(cached_params(pl.nx, pl.ny, pl.nz, dtype) is None for pl in self.plans)
+        if len(self.plans) > 1:
+            if tune and (retune or missing or not cached_batch(len(self.plans), dtype)):
+                monc.autotune_batched(self.plans)
+                for pl in self.plans:
+                    self.tuning[(pl.nx, pl.ny, pl.nz)] = "autotuned"
+            for pl in self.plans:
+                self.tuned.setdefault((pl.nx, pl.ny, pl.nz), pl.params)
+                self.tuning.setdefault((pl.nx, pl.ny, pl.nz), "cache")
+            self.schedule = dict(zip(("order", "budget_mb", "groups"), monc.batch_schedule(self.plans)))
+        else:
+            for pl in self.plans:
+                key = (pl.nx, pl.ny, pl.nz)
+                if tune and (retune or cached_params(pl.nx, pl.ny, pl.nz, dtype) is None):
+                    pl.autotune()
+                    self.tuning[key] = "autotuned"
+                else:
+                    self.tuning[key] = "cache" if cached_params(pl.nx, pl.ny, pl.nz, dtype) else "default"
+                self.tuned[key] = pl.params
         self.fields = []
         for m in members:
             f = [torch.from_numpy(a.astype(cast, copy=False)).to("cuda:0") for a in (m.u, m.v, m.w)]
@@ -700,6 +727,8 @@ def main():
         res = measure(r, args.steps, args.warmup, args.workload, args.cold_steps, flush)
         res["tile_params"] = {f"{k[0]}x{k[1]}x{k[2]}": v for k, v in r.tuned.items()}
         res["tuning"] = {f"{k[0]}x{k[1]}x{k[2]}": v for k, v in r.tuning.items()}
+        if r.schedule is not None:
+            res["batch_schedule"] = r.schedule
         extra = {}
         if not r.batched:
             # the same projections with the per-level horizontal reductions fused in
@@ -731,7 +760,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": DESCRIPTIONS[args.workload], "grid_points": sum(m.grid.points for m in members),
                    "members": len(members), "path": "fp64" if head == "f64" else "mixed",
-                   "tile_params": res.pop("tile_params"), "tuning": res.pop("tuning")},
+                   "tile_params": res.pop("tile_params"), "tuning": res.pop("tuning"),
+                   "batch_schedule": res.pop("batch_schedule", None)},
         "roofline": res.pop("roofline"),
         "cold": res.pop("cold", None),
         "path": res.pop("path"),

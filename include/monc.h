@@ -129,8 +129,12 @@ int monc_project_noalloc(monc_plan* plan, void* u, void* v, void* w, void* p, vo
  * must share one dtype and one device. The whole batch is validated before
  * anything is enqueued (all or nothing). The first call for a given set of
  * plans and pointers builds a schedule (grouped per-phase launches covering
- * every member) and captures it in a HIP graph; later calls with the same
- * plans and pointers replay the graph, others re-capture.
+ * every member, in the member order and grouping that monc_autotune chose
+ * for this set of grids, else largest first in one group) and captures it in
+ * a HIP graph; later calls with the same plans and pointers replay the
+ * graph, others re-capture. The batch is the ensemble workload of the
+ * paper's self-tuning proposal (Sec. 5): many independent solves scheduled
+ * together on one device.
  */
 int monc_project_batched(monc_plan* const* plans, int count,
                          void* const* u, void* const* v, void* const* w,
@@ -267,13 +271,33 @@ int monc_profile_enable(monc_plan* plan, unsigned mask);
  * ms[MONC_K_COUNT] and launches[MONC_K_COUNT], and clear the record. */
 int monc_profile_read(monc_plan* plan, double* ms, int* launches);
 
-/* Autotune the tile parameters of a plan (FFT elements per thread, y-FFT
- * columns per workgroup, tridiagonal lanes per column and columns per
- * workgroup) by timing the candidates on scratch buffers on `stream`; the
- * choice is stored in the plan and in the JSON cache named by the
- * MONC_TUNE_CACHE environment variable (if set). Synchronises the stream.
- * Returns MONC_OK or an error. */
-int monc_autotune(monc_plan* plan, void* stream);
+/* Self-tuning (the paper's Sec. 5 proposes performance tuning done
+ * dynamically by the model): time candidate schedules on this device and
+ * keep the fastest. For every distinct grid among plans[0..count-1], the tile
+ * parameters (FFT elements per thread, y-FFT columns per workgroup,
+ * tridiagonal lanes per column and columns per workgroup, x transforms per
+ * workgroup) are tuned on the grid's first plan, one parameter after the
+ * other, and copied to its other plans. For count > 1 the batch schedule
+ * of monc_project_batched over these plans is then tuned as a whole: each
+ * member order (largest or smallest first) and grouping (all members per
+ * phase, or groups of at most 1024, 512, 256, 128 or 64 MB of working set
+ * run one after the other) is captured and its graph replayed on scratch
+ * fields.
+ * Results are stored in the plans / the schedule table and in the JSON cache
+ * named by the MONC_TUNE_CACHE environment variable (if set), which plans and
+ * batches of the same grids read back. Allocates scratch fields, synchronises
+ * the stream. Returns MONC_OK or an error (MONC_EINVAL for a bad batch as in
+ * monc_project_batched, MONC_ENOMEM). */
+int monc_autotune(monc_plan* const* plans, int count, void* stream);
+
+/* The batch schedule monc_project_batched uses for these plans (tuned, read
+ * from the cache, or the default): out[0] = member order (0 largest first,
+ * 1 smallest first), out[1] = working-set budget per group in MB (0 = one
+ * group, every phase over all members), out[2] = number of groups. */
+int monc_batch_schedule(monc_plan* const* plans, int count, int* out);
+/* Set that schedule by hand (order 0 or 1, budget_mb >= 0); the next
+ * monc_project_batched call over these plans captures it. */
+int monc_batch_set_schedule(monc_plan* const* plans, int count, int order, int budget_mb);
 
 /* Streaming-bandwidth probes: one launch of the plainest kernel that moves
  * a known number of bytes, to measure the bandwidth a streaming kernel
@@ -292,7 +316,7 @@ enum { MONC_PROBE_READ = 0, MONC_PROBE_WRITE = 1, MONC_PROBE_COPY = 2, MONC_PROB
 int monc_stream_probe(int kind, void* a, void* b, void* c, void* d, size_t bytes, void* stream);
 
 /* Number of tile parameters. */
-#define MONC_NPARAMS 5
+#define MONC_NPARAMS 6
 
 /* Current tile parameters of a plan, out[MONC_NPARAMS]:
  *   out[0] = x-FFT elements per thread (runtime-length FFTs only),
@@ -300,7 +324,10 @@ int monc_stream_probe(int kind, void* a, void* b, void* c, void* d, size_t bytes
  *   out[2] = y-FFT columns per workgroup,
  *   out[3] = tridiagonal lanes per column (power of 2, <= 64),
  *   out[4] = tridiagonal columns per workgroup (power of 2, times out[3]
- *            at most 1024 threads). */
+ *            at most 1024 threads),
+ *   out[5] = x-direction transforms (row pairs) per workgroup of the
+ *            compile-time x-FFT kernels (at most 512 threads and 160 KB of
+ *            LDS per workgroup; default 256 threads' worth). */
 int monc_plan_params(const monc_plan* plan, int* out);
 /* Set them from in[MONC_NPARAMS] (values are checked; 0 keeps the current
  * value). Synchronises the device. */

@@ -17,15 +17,16 @@ from typing import Optional, Sequence
 
 import numpy as np
 
-__all__ = ["Plan", "project_batched", "stream_probe", "lib", "last_error", "MoncError",
+__all__ = ["Plan", "project_batched", "stream_probe", "autotune_batched", "batch_schedule", "set_batch_schedule", "lib", "last_error", "MoncError",
            "FP64", "MIXED", "STAGE_FORWARD", "STAGE_SOLVE", "STAGE_INVERSE",
            "STAGE_GRADIENT", "STAGE_RESIDUAL", "KERNELS"]
 
 FP64, MIXED = 0, 1
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP = 0, -1, -2, -3, -4
 STAGE_FORWARD, STAGE_SOLVE, STAGE_INVERSE, STAGE_GRADIENT, STAGE_RESIDUAL = 1, 2, 3, 4, 5
-NPARAMS = 5  # tile parameters: x/y FFT elements per thread, y-FFT columns,
-             # tridiagonal lanes per column, tridiagonal columns per workgroup
+NPARAMS = 6  # tile parameters: x/y FFT elements per thread, y-FFT columns,
+             # tridiagonal lanes per column, tridiagonal columns per workgroup,
+             # x transforms per workgroup
 KERNELS = ["div_fftx", "ffty_fwd", "tridiag", "ffty_inv", "ifftx", "grad",
            "resid_fftx", "grad_final"]
 
@@ -77,7 +78,11 @@ def lib() -> ctypes.CDLL:
     L.monc_profile_read.restype = ip
     L.monc_profile_read.argtypes = [vp, dp, ctypes.POINTER(ip)]
     L.monc_autotune.restype = ip
-    L.monc_autotune.argtypes = [vp, vp]
+    L.monc_autotune.argtypes = [ctypes.POINTER(vp), ip, vp]
+    L.monc_batch_schedule.restype = ip
+    L.monc_batch_schedule.argtypes = [ctypes.POINTER(vp), ip, ctypes.POINTER(ip)]
+    L.monc_batch_set_schedule.restype = ip
+    L.monc_batch_set_schedule.argtypes = [ctypes.POINTER(vp), ip, ip, ip]
     L.monc_plan_params.restype = ip
     L.monc_plan_params.argtypes = [vp, ctypes.POINTER(ip)]
     L.monc_plan_set_params.restype = ip
@@ -257,7 +262,9 @@ class Plan:
         return {KERNELS[i]: (ms[i], cnt[i]) for i in range(len(KERNELS)) if cnt[i]}
 
     def autotune(self, stream=None):
-        _check(lib().monc_autotune(self._h, ctypes.c_void_p(_stream_handle(stream))))
+        """Tune this plan's tile parameters (monc_autotune of one plan)."""
+        arr = (ctypes.c_void_p * 1)(self._h)
+        _check(lib().monc_autotune(arr, 1, ctypes.c_void_p(_stream_handle(stream))))
 
     @property
     def params(self):
@@ -272,6 +279,27 @@ class Plan:
             raise ValueError(f"expected at most {NPARAMS} tile parameters")
         arr = (ctypes.c_int * NPARAMS)(*[int(x) for x in vals])
         _check(lib().monc_plan_set_params(self._h, arr))
+
+
+def autotune_batched(plans: Sequence[Plan], stream=None):
+    """Tune the tile parameters of every distinct grid and the batch schedule
+    (member order, grouping) of these plans (monc_autotune)."""
+    arr = (ctypes.c_void_p * len(plans))(*[pl.handle for pl in plans])
+    _check(lib().monc_autotune(arr, len(plans), ctypes.c_void_p(_stream_handle(stream))))
+
+
+def batch_schedule(plans: Sequence[Plan]):
+    """(order, budget_mb, groups) of the batch schedule of these plans."""
+    arr = (ctypes.c_void_p * len(plans))(*[pl.handle for pl in plans])
+    out = (ctypes.c_int * 3)()
+    _check(lib().monc_batch_schedule(arr, len(plans), out))
+    return tuple(out)
+
+
+def set_batch_schedule(plans: Sequence[Plan], order: int, budget_mb: int):
+    """Set the batch schedule of these plans by hand (monc_batch_set_schedule)."""
+    arr = (ctypes.c_void_p * len(plans))(*[pl.handle for pl in plans])
+    _check(lib().monc_batch_set_schedule(arr, len(plans), int(order), int(budget_mb)))
 
 
 PROBES = {"read": 0, "write": 1, "copy": 2, "update": 3}

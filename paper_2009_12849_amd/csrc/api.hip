@@ -88,7 +88,7 @@ struct monc_plan {
   int nx = 0, ny = 0, nz = 0, dtype = 0, device = 0;
   double dx = 0, dy = 0;
   std::vector<double> dz, rho0;
-  int ex = 8, ey = 8, ymt = 0, triP = 0, tricw = 0;  // tile parameters (tricw 0 = automatic)
+  int ex = 8, ey = 8, ymt = 0, triP = 0, tricw = 0, xpw = 0;  // tile parameters (0 = automatic)
   MemberDesc h{};                          // host copy with device pointers
   MemberDesc* d_desc = nullptr;            // device copy
   void* d_tables = nullptr;
@@ -121,8 +121,9 @@ static int tri_rows(int nz, int P) {
   return 0;
 }
 
-// Derive FFT plans and tile parameters from (ex, ey, ymt, triP, tricw); 0 = default.
-static int configure_tiles(monc_plan* pl, int ex, int ey, int ymt, int triP, int tricw) {
+// Derive FFT plans and tile parameters from (ex, ey, ymt, triP, tricw, xpw);
+// 0 = default.
+static int configure_tiles(monc_plan* pl, int ex, int ey, int ymt, int triP, int tricw, int xpw) {
   MemberDesc& h = pl->h;
   FftPlan fx{}, fy{};
   if (!radix_plan(pl->nx, fx) || !radix_plan(pl->ny, fy))
@@ -162,9 +163,23 @@ static int configure_tiles(monc_plan* pl, int ex, int ey, int ymt, int triP, int
   if (cw & (cw - 1) || cw * triP > 512)
     return fail(MONC_EINVAL, "tridiagonal columns per workgroup must be a power of 2 with %d lanes <= 512 threads (got %d)",
                 triP, cw);
+  // x transforms per workgroup of the compile-time x kernels (default: 256
+  // threads); at most 512 threads and 160 KB of LDS
+  if (xpw <= 0) xpw = pl->xpw;
+  int xeff = 1;
+  if (ct_supported(pl->nx)) {
+    const int nt = ct_threads_host(pl->nx);
+    const size_t per = (size_t)xlds_len(pl->nx, (int)cb) * cb;
+    xeff = xpw > 0 ? xpw : std::max(1, 256 / nt);
+    if (xeff * nt > 512 || xeff * per > 160 * 1024)
+      return fail(MONC_EINVAL, "%d x transforms of %d points per workgroup exceed 512 threads or 160 KB of LDS", xeff,
+                  pl->nx);
+  }
   pl->ex = ex;
   pl->ey = ey;
   pl->ymt = ymt;
+  pl->xpw = xpw;
+  h.xpw = xeff;
   // spectral column blocks as wide as a y-FFT tile (up to kSpecBlockMax), so
   // that the tile is one contiguous run of each level
   h.sbw = std::min(kSpecBlockMax, pow2_floor(ymt));
@@ -189,7 +204,7 @@ static int upload_desc(monc_plan* pl) {
 }
 
 // ---------------------------------------------------------------------------
-// tuning cache (flat JSON object: "arch:nx,ny,nz:dtype" -> [ex, ey, ymt, triP, tricw])
+// tuning cache (flat JSON object: "arch:nx,ny,nz:dtype" -> [ex, ey, ymt, triP, tricw, xpw])
 // ---------------------------------------------------------------------------
 static std::mutex g_cache_mu;
 
@@ -323,7 +338,7 @@ extern "C" monc_plan* monc_plan_create(int nx, int ny, int nz, double dx, double
   h.rdxf = (float)h.rdx;
   h.rdyf = (float)h.rdy;
   // tile parameters (cached tuning first)
-  int ex = 0, ey = 0, ymt = 0, triP = 0, tricw = 0;
+  int ex = 0, ey = 0, ymt = 0, triP = 0, tricw = 0, xpw = 0;
   if (const char* path = std::getenv("MONC_TUNE_CACHE")) {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     auto m = read_cache(path);
@@ -334,10 +349,11 @@ extern "C" monc_plan* monc_plan_create(int nx, int ny, int nz, double dx, double
       ymt = it->second[2];
       triP = it->second[3];
       tricw = it->second[4];
+      xpw = it->second[5];
     }
   }
-  if (configure_tiles(pl.get(), ex, ey, ymt, triP, tricw) != MONC_OK &&
-      configure_tiles(pl.get(), 8, 8, 0, 0, 0) != MONC_OK)
+  if (configure_tiles(pl.get(), ex, ey, ymt, triP, tricw, xpw) != MONC_OK &&
+      configure_tiles(pl.get(), 8, 8, 0, 0, 0, 0) != MONC_OK)
     return nullptr;
 
   // host tables
@@ -551,7 +567,7 @@ static Shape member_shape(const MemberDesc& d, Phase ph, bool fp64) {
     const long long pairs = (d.nrow + 1) / 2;
     if (ct_supported(d.nx)) {
       const int nt = ct_threads_host(d.nx);
-      const int ipw = std::max(1, 256 / nt);
+      const int ipw = d.xpw > 0 ? d.xpw : std::max(1, 256 / nt);
       s.variant = d.nx;
       s.block = ipw * nt;
       s.lds = (size_t)ipw * xlds_len(d.nx, (int)cb) * cb;
@@ -1146,58 +1162,159 @@ static void drop_batch_cache_for(unsigned long long plan_id) {
                   g_batches.end());
 }
 
-// Members ordered by size (largest first) so the big members' workgroups
-// start first and the small ones fill the tail.
-static std::vector<int> batch_order(monc_plan* const* plans, int count) {
+// ---------------------------------------------------------------------------
+// batch schedule: member order and grouping (tuned by monc_autotune)
+// ---------------------------------------------------------------------------
+// order 0 puts the largest members first (their workgroups start first, the
+// small ones fill the tail), order 1 the smallest first. budget_mb 0 runs
+// every phase over all members (one launch per kernel instance and phase);
+// otherwise members, in order, are packed into groups whose working set
+// (fields, spectral workspace, scratch) stays under budget_mb MB, and the
+// groups run one after the other, all phases of a group before the next, so
+// that a group's intermediates can stay in the 256 MB Infinity Cache.
+struct BatchSchedule {
+  int order = 0;
+  int budget_mb = 0;
+};
+
+static std::mutex g_sched_mu;
+static std::map<std::string, BatchSchedule> g_sched;
+
+// Key of a batch for the tuned schedule: the multiset of member grids and
+// the dtype (FNV-1a hash of the sorted grid list).
+static std::string batch_key(monc_plan* const* plans, int count) {
+  std::vector<std::string> grids;
+  for (int i = 0; i < count; ++i) {
+    char b[64];
+    std::snprintf(b, sizeof b, "%d,%d,%d;", plans[i]->nx, plans[i]->ny, plans[i]->nz);
+    grids.push_back(b);
+  }
+  std::sort(grids.begin(), grids.end());
+  unsigned long long h = 1469598103934665603ull;
+  for (const auto& g : grids)
+    for (char c : g) {
+      h ^= (unsigned char)c;
+      h *= 1099511628211ull;
+    }
+  char key[128];
+  std::snprintf(key, sizeof key, "gfx950:batch:%d:%016llx:%s", count, h,
+                plans[0]->dtype == MONC_FP64 ? "fp64" : "mixed");
+  return key;
+}
+
+static BatchSchedule lookup_schedule(monc_plan* const* plans, int count) {
+  const std::string key = batch_key(plans, count);
+  {
+    std::lock_guard<std::mutex> lk(g_sched_mu);
+    auto it = g_sched.find(key);
+    if (it != g_sched.end()) return it->second;
+  }
+  BatchSchedule sc;
+  if (const char* path = std::getenv("MONC_TUNE_CACHE")) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto m = read_cache(path);
+    auto it = m.find(key);
+    if (it != m.end() && it->second.size() == 2 && (it->second[0] == 0 || it->second[0] == 1) && it->second[1] >= 0) {
+      sc.order = it->second[0];
+      sc.budget_mb = it->second[1];
+    }
+  }
+  std::lock_guard<std::mutex> lk(g_sched_mu);
+  g_sched[key] = sc;
+  return sc;
+}
+
+static size_t member_bytes(const monc_plan* pl) {
+  const size_t n = (size_t)pl->nx * pl->ny * pl->nz;
+  return 4 * n * elem_bytes(pl->dtype) + pl->spec_elems * cplx_bytes(pl->dtype) +
+         (pl->dtype == MONC_FP64 ? 0 : 2 * n * sizeof(float));
+}
+
+static std::vector<int> batch_order(monc_plan* const* plans, int count, int order) {
   std::vector<int> ord(count);
   for (int i = 0; i < count; ++i) ord[i] = i;
   std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
     const long long pa = (long long)plans[a]->nx * plans[a]->ny * plans[a]->nz;
     const long long pb = (long long)plans[b]->nx * plans[b]->ny * plans[b]->nz;
-    return pa > pb;
+    return order == 0 ? pa > pb : pa < pb;
   });
   return ord;
 }
 
-static int build_groups(monc_plan* const* plans, int count, void* const* u, void* const* v, void* const* w,
-                        void* const* p, const MemberDesc* d_array, const std::vector<int>& ord,
-                        std::vector<Group>& groups) {
+static void build_groups(monc_plan* const* plans, int count, void* const* u, void* const* v, void* const* w,
+                         void* const* p, const MemberDesc* d_array, const std::vector<int>& ord,
+                         const BatchSchedule& sc, std::vector<Group>& groups) {
   groups.clear();
+  const size_t budget = (size_t)sc.budget_mb << 20;
   Group g;
   g.fp64 = plans[0]->dtype == MONC_FP64;
+  size_t used = 0;
   for (int t = 0; t < count; ++t) {
     const int i = ord[t];
+    const size_t mb = member_bytes(plans[i]);
+    if (budget && !g.mem.empty() && used + mb > budget) {
+      groups.push_back(std::move(g));
+      g = Group();
+      g.fp64 = plans[0]->dtype == MONC_FP64;
+      used = 0;
+    }
     g.mem.push_back({&plans[i]->h, d_array + t, plan_io(plans[i], u[i], v[i], w[i], p[i])});
+    used += mb;
   }
   groups.push_back(std::move(g));
+}
+
+// Every phase over all groups (phase-major), or all phases of each group in
+// turn (group-major, the grouped schedules).
+static int run_batch(const std::vector<Group>& groups, const std::vector<Phase>& seq, bool group_major,
+                     void* stream, Profiler* prof) {
+  if (!group_major) return run_phases(groups, seq, stream, prof);
+  for (const auto& g : groups)
+    for (Phase ph : seq) {
+      const int rc = launch_phase(g, ph, stream, prof);
+      if (rc != MONC_OK) return rc;
+    }
+  return MONC_OK;
+}
+
+static int check_batch(monc_plan* const* plans, int count, const char* what) {
+  if (!plans) return fail(MONC_EINVAL, "%s: plans is null", what);
+  if (count < 1 || count > MONC_MAX_BATCH)
+    return fail(MONC_EINVAL, "%s: count must be in [1, %d] (got %d)", what, MONC_MAX_BATCH, count);
+  for (int i = 0; i < count; ++i) {
+    if (!plans[i]) return fail(MONC_EINVAL, "%s: plans[%d] is null", what, i);
+    if (plans[i]->dtype != plans[0]->dtype) return fail(MONC_EINVAL, "batch mixes dtypes (member %d)", i);
+    if (plans[i]->device != plans[0]->device) return fail(MONC_EINVAL, "batch spans devices (member %d)", i);
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == plans[i]) return fail(MONC_EINVAL, "plan of member %d repeats member %d (one workspace per plan)", i, j);
+  }
   return MONC_OK;
 }
 
 extern "C" int monc_project_batched(monc_plan* const* plans, int count, void* const* u, void* const* v,
                                     void* const* w, void* const* p, void* stream) {
   if (!plans || !u || !v || !w || !p) return fail(MONC_EINVAL, "null argument array");
-  if (count < 1 || count > MONC_MAX_BATCH) return fail(MONC_EINVAL, "count must be in [1, %d] (got %d)", MONC_MAX_BATCH, count);
+  int rc = check_batch(plans, count, "monc_project_batched");
+  if (rc != MONC_OK) return rc;
   for (int i = 0; i < count; ++i) {
-    if (!plans[i]) return fail(MONC_EINVAL, "plans[%d] is null", i);
-    if (plans[i]->dtype != plans[0]->dtype) return fail(MONC_EINVAL, "batch mixes dtypes (member %d)", i);
-    if (plans[i]->device != plans[0]->device) return fail(MONC_EINVAL, "batch spans devices (member %d)", i);
-    for (int j = 0; j < i; ++j)
-      if (plans[j] == plans[i]) return fail(MONC_EINVAL, "plan of member %d repeats member %d (one workspace per plan)", i, j);
     void* ptrs[4] = {u[i], v[i], w[i], p[i]};
     char what[64];
     std::snprintf(what, sizeof what, "batch member %d", i);
-    const int rc = check_fields(plans[i], ptrs, 4, what);
+    rc = check_fields(plans[i], ptrs, 4, what);
     if (rc != MONC_OK) return rc;
   }
-  int rc = check_device(plans[0]);
+  rc = check_device(plans[0]);
   if (rc != MONC_OK) return rc;
   const bool fp64 = plans[0]->dtype == MONC_FP64;
   Profiler* prof = plans[0]->prof.mask ? &plans[0]->prof : nullptr;
-  const std::vector<int> ord = batch_order(plans, count);
+  const BatchSchedule sc = lookup_schedule(plans, count);
+  const std::vector<int> ord = batch_order(plans, count, sc.order);
 
-  // key: plan ids, versions and field pointers
+  // key: schedule, plan ids, versions and field pointers
   std::vector<unsigned long long> key;
-  key.reserve(6 * count);
+  key.reserve(6 * count + 2);
+  key.push_back((unsigned long long)sc.order);
+  key.push_back((unsigned long long)sc.budget_mb);
   for (int i = 0; i < count; ++i) {
     key.push_back(plans[i]->id);
     key.push_back(plans[i]->version);
@@ -1231,9 +1348,10 @@ extern "C" int monc_project_batched(monc_plan* const* plans, int count, void* co
   }
   ent->last_use = ++g_batch_clock;
   std::vector<Group> groups;
-  build_groups(plans, count, u, v, w, p, ent->d_array, ord, groups);
+  build_groups(plans, count, u, v, w, p, ent->d_array, ord, sc, groups);
+  const bool group_major = sc.budget_mb > 0;
   const auto& seq = full_sequence(fp64);
-  if (prof) return run_phases(groups, seq, stream, prof);  // eager launches when timing kernels
+  if (prof) return run_batch(groups, seq, group_major, stream, prof);  // eager launches when timing kernels
   if (!ent->exec) {
     hipStream_t cs = nullptr;
     HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -1242,7 +1360,7 @@ extern "C" int monc_project_batched(monc_plan* const* plans, int count, void* co
       (void)hipStreamDestroy(cs);
       return fail(MONC_EHIP, "hipStreamBeginCapture failed: %s", hipGetErrorString(e));
     }
-    rc = run_phases(groups, seq, cs, nullptr);
+    rc = run_batch(groups, seq, group_major, cs, nullptr);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(cs, &graph);
     (void)hipStreamDestroy(cs);
@@ -1255,6 +1373,42 @@ extern "C" int monc_project_batched(monc_plan* const* plans, int count, void* co
     HIP_TRY(hipGraphInstantiate(&ent->exec, graph, nullptr, nullptr, 0));
   }
   HIP_TRY(hipGraphLaunch(ent->exec, (hipStream_t)stream));
+  return MONC_OK;
+}
+
+extern "C" int monc_batch_schedule(monc_plan* const* plans, int count, int* out) {
+  int rc = check_batch(plans, count, "monc_batch_schedule");
+  if (rc != MONC_OK) return rc;
+  if (!out) return fail(MONC_EINVAL, "monc_batch_schedule: out is null");
+  const BatchSchedule sc = lookup_schedule(plans, count);
+  const std::vector<int> ord = batch_order(plans, count, sc.order);
+  size_t used = 0;
+  int ngroups = 1;
+  const size_t budget = (size_t)sc.budget_mb << 20;
+  for (int t = 0, n = 0; t < count; ++t, ++n) {
+    const size_t mb = member_bytes(plans[ord[t]]);
+    if (budget && n > 0 && used + mb > budget) {
+      ++ngroups;
+      used = 0;
+    }
+    used += mb;
+  }
+  out[0] = sc.order;
+  out[1] = sc.budget_mb;
+  out[2] = ngroups;
+  return MONC_OK;
+}
+
+extern "C" int monc_batch_set_schedule(monc_plan* const* plans, int count, int order, int budget_mb) {
+  int rc = check_batch(plans, count, "monc_batch_set_schedule");
+  if (rc != MONC_OK) return rc;
+  if (order != 0 && order != 1) return fail(MONC_EINVAL, "monc_batch_set_schedule: order must be 0 or 1 (got %d)", order);
+  if (budget_mb < 0) return fail(MONC_EINVAL, "monc_batch_set_schedule: budget_mb must be >= 0 (got %d)", budget_mb);
+  BatchSchedule sc;
+  sc.order = order;
+  sc.budget_mb = budget_mb;
+  std::lock_guard<std::mutex> lk(g_sched_mu);
+  g_sched[batch_key(plans, count)] = sc;
   return MONC_OK;
 }
 
@@ -1297,6 +1451,7 @@ extern "C" int monc_plan_params(const monc_plan* pl, int* out) {
   out[2] = pl->ymt;
   out[3] = pl->triP;
   out[4] = pl->h.tricw;
+  out[5] = pl->h.xpw;
   return MONC_OK;
 }
 
@@ -1305,11 +1460,11 @@ extern "C" int monc_plan_set_params(monc_plan* pl, const int* in) {
   for (int i = 0; i < MONC_NPARAMS; ++i)
     if (in[i] < 0) return fail(MONC_EINVAL, "parameter %d is negative", i);
   const MemberDesc saved = pl->h;
-  const int sv[MONC_NPARAMS] = {pl->ex, pl->ey, pl->ymt, pl->triP, pl->tricw};
-  int rc = configure_tiles(pl, in[0], in[1], in[2], in[3], in[4]);
+  const int sv[MONC_NPARAMS] = {pl->ex, pl->ey, pl->ymt, pl->triP, pl->tricw, pl->xpw};
+  int rc = configure_tiles(pl, in[0], in[1], in[2], in[3], in[4], in[5]);
   if (rc != MONC_OK) {
     pl->h = saved;
-    pl->ex = sv[0]; pl->ey = sv[1]; pl->ymt = sv[2]; pl->triP = sv[3]; pl->tricw = sv[4];
+    pl->ex = sv[0]; pl->ey = sv[1]; pl->ymt = sv[2]; pl->triP = sv[3]; pl->tricw = sv[4]; pl->xpw = sv[5];
     return rc;
   }
   HIP_TRY(hipDeviceSynchronize());  // in-flight work may still read the old descriptor
@@ -1318,8 +1473,9 @@ extern "C" int monc_plan_set_params(monc_plan* pl, const int* in) {
   return rc;
 }
 
-extern "C" int monc_autotune(monc_plan* pl, void* stream) {
-  if (!pl) return fail(MONC_EINVAL, "plan is null");
+// Tile parameters of one plan: time every candidate value of one parameter,
+// all else fixed, one parameter after the other.
+static int tune_plan(monc_plan* pl, void* stream) {
   int rc = check_device(pl);
   if (rc != MONC_OK) return rc;
   const size_t bytes = (size_t)pl->nx * pl->ny * pl->nz * elem_bytes(pl->dtype);
@@ -1354,7 +1510,7 @@ extern "C" int monc_autotune(monc_plan* pl, void* stream) {
     for (int k = 0; k < MONC_K_COUNT; ++k) cost += ms[k];
     return MONC_OK;
   };
-  int best[MONC_NPARAMS] = {pl->ex, pl->ey, pl->ymt, pl->triP, pl->tricw};
+  int best[MONC_NPARAMS] = {pl->ex, pl->ey, pl->ymt, pl->triP, pl->tricw, pl->h.xpw};
   {
     double whole = 0.0;
     const int r = measure(best, (1u << MONC_K_COUNT) - 1, whole);
@@ -1386,6 +1542,7 @@ extern "C" int monc_autotune(monc_plan* pl, void* stream) {
   axes.push_back({2, {1, 2, 4, 8, 16, 32}, ymask | xmask});
   axes.push_back({3, pvals, tmask});
   axes.push_back({4, {4, 8, 16, 32}, tmask});
+  if (ct_supported(pl->nx)) axes.push_back({5, {1, 2, 4}, xmask});
   for (const auto& ax : axes) {
     double best_cost = 1e300;
     int best_val = best[ax.idx];
@@ -1412,8 +1569,106 @@ extern "C" int monc_autotune(monc_plan* pl, void* stream) {
   if (const char* path = std::getenv("MONC_TUNE_CACHE")) {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     auto m = read_cache(path);
-    m[cache_key(pl)] = {pl->ex, pl->ey, pl->ymt, pl->triP, pl->tricw};
+    m[cache_key(pl)] = {pl->ex, pl->ey, pl->ymt, pl->triP, pl->tricw, pl->h.xpw};
     write_cache(path, m);
   }
   return MONC_OK;
+}
+
+// The batch schedule: every candidate (member order x grouping budget) is
+// captured and replayed on scratch fields; the fastest replay wins.
+static int tune_schedule(monc_plan* const* plans, int count, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const size_t eb = elem_bytes(plans[0]->dtype);
+  std::vector<void*> bufs;
+  auto release = [&]() {
+    for (void* b : bufs) (void)hipFree(b);
+    bufs.clear();
+  };
+  std::vector<void*> f[4];
+  for (int i = 0; i < count; ++i) {
+    const size_t bytes = (size_t)plans[i]->nx * plans[i]->ny * plans[i]->nz * eb;
+    for (int t = 0; t < 4; ++t) {
+      void* b = nullptr;
+      if (hipMalloc(&b, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        release();
+        return fail(MONC_ENOMEM, "autotune: scratch fields for the batch do not fit");
+      }
+      (void)hipMemset(b, 0, bytes);
+      bufs.push_back(b);
+      f[t].push_back(b);
+    }
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    release();
+    return fail(MONC_EHIP, "autotune: event creation failed");
+  }
+  size_t total = 0;
+  for (int i = 0; i < count; ++i) total += member_bytes(plans[i]);
+  const int budgets[] = {0, 1024, 512, 256, 128, 64};
+  BatchSchedule best;
+  double best_ms = 1e300;
+  int rc = MONC_OK;
+  for (int order = 0; order < 2 && rc == MONC_OK; ++order)
+    for (int budget : budgets) {
+      if (budget && ((size_t)budget << 20) >= total) continue;  // one group anyway
+      rc = monc_batch_set_schedule(plans, count, order, budget);
+      if (rc != MONC_OK) break;
+      for (int r = 0; r < 2 && rc == MONC_OK; ++r)  // capture, then one warm replay
+        rc = monc_project_batched(plans, count, f[0].data(), f[1].data(), f[2].data(), f[3].data(), stream);
+      if (rc != MONC_OK) break;
+      const int reps = 5;
+      (void)hipEventRecord(e0, st);
+      for (int r = 0; r < reps && rc == MONC_OK; ++r)
+        rc = monc_project_batched(plans, count, f[0].data(), f[1].data(), f[2].data(), f[3].data(), stream);
+      (void)hipEventRecord(e1, st);
+      float ms = 0.0f;
+      if (rc == MONC_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = fail(MONC_EHIP, "autotune: event timing failed");
+      if (rc == MONC_OK && ms < best_ms) {
+        best_ms = ms;
+        best.order = order;
+        best.budget_mb = budget;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  // the candidates' graphs hold the scratch pointers: drop them with the fields
+  if (hipStreamSynchronize(st) != hipSuccess && rc == MONC_OK) rc = fail(MONC_EHIP, "autotune: stream failed");
+  for (int i = 0; i < count; ++i) drop_batch_cache_for(plans[i]->id);
+  release();
+  if (rc != MONC_OK) return rc;
+  rc = monc_batch_set_schedule(plans, count, best.order, best.budget_mb);
+  if (rc != MONC_OK) return rc;
+  if (const char* path = std::getenv("MONC_TUNE_CACHE")) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto m = read_cache(path);
+    m[batch_key(plans, count)] = {best.order, best.budget_mb};
+    write_cache(path, m);
+  }
+  return MONC_OK;
+}
+
+extern "C" int monc_autotune(monc_plan* const* plans, int count, void* stream) {
+  int rc = check_batch(plans, count, "monc_autotune");
+  if (rc != MONC_OK) return rc;
+  // tile parameters: the first plan of every distinct grid is tuned, the
+  // others of that grid take its parameters
+  for (int i = 0; i < count; ++i) {
+    int j = 0;
+    while (j < i && !(plans[j]->nx == plans[i]->nx && plans[j]->ny == plans[i]->ny && plans[j]->nz == plans[i]->nz))
+      ++j;
+    if (j == i) {
+      rc = tune_plan(plans[i], stream);
+    } else {
+      int prm[MONC_NPARAMS];
+      monc_plan_params(plans[j], prm);
+      rc = monc_plan_set_params(plans[i], prm);
+    }
+    if (rc != MONC_OK) return rc;
+  }
+  if (count == 1) return MONC_OK;
+  return tune_schedule(plans, count, stream);
 }

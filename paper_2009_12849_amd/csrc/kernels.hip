@@ -1457,9 +1457,12 @@ __global__ void __launch_bounds__(256) k_grad(LaunchArgs a) {
   dv pu;
   if constexpr (sizeof(T) == 8) pu = ldp(top ? g : g + nh);
   else pu = top ? pc : ldp(g + nh);
-  tv uu = *reinterpret_cast<const tv*>(u + g);
-  tv vv = *reinterpret_cast<const tv*>(v + g);
-  tv ww = *reinterpret_cast<const tv*>(w + g);
+  // u, v, w are read and written once per point: nontemporal accesses (the
+  // pressure fields, re-read as neighbours by other workgroups, keep the
+  // normal cache policy)
+  tv uu = __builtin_nontemporal_load(reinterpret_cast<const tv*>(u + g));
+  tv vv = __builtin_nontemporal_load(reinterpret_cast<const tv*>(v + g));
+  tv ww = __builtin_nontemporal_load(reinterpret_cast<const tv*>(w + g));
   const double rz = ldg(d.rdzc + k);  // 0 on the lid row
   const double rdx = d.rdx, rdy = d.rdy;
 #pragma unroll
@@ -1470,15 +1473,15 @@ __global__ void __launch_bounds__(256) k_grad(LaunchArgs a) {
     ww[e] = top ? (T)0 : (T)((double)ww[e] - (pu[e] - pc[e]) * rz);
   }
   if (live) {
-    *reinterpret_cast<tv*>(u + g) = uu;
-    *reinterpret_cast<tv*>(v + g) = vv;
-    *reinterpret_cast<tv*>(w + g) = ww;
+    __builtin_nontemporal_store(uu, reinterpret_cast<tv*>(u + g));
+    __builtin_nontemporal_store(vv, reinterpret_cast<tv*>(v + g));
+    __builtin_nontemporal_store(ww, reinterpret_cast<tv*>(w + g));
     if constexpr (sizeof(T) == 4) {
       // the mixed path's pressure output: p1 + delta rounded to float
       tv po;
 #pragma unroll
       for (int e = 0; e < VEC; ++e) po[e] = (T)pc[e];
-      *reinterpret_cast<__attribute__((address_space(1))) tv*>(gptr(reinterpret_cast<T*>(io.p) + g)) = po;
+      __builtin_nontemporal_store(po, reinterpret_cast<tv*>(reinterpret_cast<T*>(io.p) + g));
     }
   }
   if constexpr (RED) {

@@ -109,6 +109,7 @@ struct MemberDesc {
   int tris;               // rows per lane (>= 2)
   int tricw;              // columns per workgroup (blockDim / triP)
   int ptk;                // levels per (level, row pair) tile of the stencil kernels (1 = row order)
+  int xpw;                // x-direction transforms (row pairs) per workgroup of the compile-time kernels
   // Spectral layout: a level's half spectrum sits in column blocks of sbw
   // consecutive m (the y-FFT tile width), each block row-major over n:
   // element (k, n, m) at k*plane + (m >> lbw)*bst + n*sbw + (m & (sbw-1)).

@@ -110,3 +110,14 @@ def test_stream_probe_argument_checks_run_before_the_device():
     assert L.monc_stream_probe(1, fake, None, None, None, 1000, None) == monc.EINVAL    # not a multiple of 16
     assert L.monc_stream_probe(1, vp((1 << 20) + 8), None, None, None, 1024, None) == monc.EINVAL  # misaligned
     assert L.monc_stream_probe(0, fake, None, None, None, 1024, None) == monc.EINVAL    # read needs its sink
+
+
+def test_batch_schedule_argument_checks_run_before_the_device():
+    L = monc.lib()
+    VP = ctypes.c_void_p * 1
+    z = VP(None)
+    out = (ctypes.c_int * 3)()
+    assert L.monc_batch_schedule(z, 0, out) == monc.EINVAL
+    assert L.monc_batch_set_schedule(z, 1, 0, 0) == monc.EINVAL
+    assert L.monc_autotune(z, 0, None) == monc.EINVAL
+    assert "count" in monc.last_error()
