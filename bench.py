@@ -662,6 +662,37 @@ def summarize_counters(rd_csv, wr_csv, workload, command):
     return "\n".join(lines) + "\n"
 
 
+def summarize_trace(stats_csv, workload, command, bench_log=None):
+    """Per-kernel summary of a rocprofv3 --kernel-trace --stats run of
+    bench.py (its kernel_stats CSV): calls, average and total time per
+    kernel instance, the library's kernel name beside it; with the bench's
+    JSON line (bench_log), the event-timed average of its dominant kernels
+    for comparison."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv, newline="")))
+    lines = [f"# rocprofv3 kernel statistics, {workload}",
+             f"# command: {command}",
+             "# kernel instance | library kernel (path) | calls | average us | total ms | share of GPU time",
+             f"kernels_sha256_16: {kernel_source_hash()}"]
+    for r in rows:
+        cls = classify_kernel(r["Name"])
+        tag = f"{cls[1]} ({cls[0]})" if cls else "-"
+        lines.append(f"{r['Name']} | {tag} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.3f} | {float(r['Percentage']):.2f} %")
+    if bench_log:
+        with open(bench_log) as fh:
+            txt = fh.read()
+        start = txt.find('{"metric"')
+        if start >= 0:
+            d = json.loads(txt[start:txt.index("\n", start)] if "\n" in txt[start:] else txt[start:])
+            for path in (d, d.get("fp64") or {}, d.get("mixed") or {}):
+                rf = path.get("roofline") if isinstance(path, dict) else None
+                if rf:
+                    lines.append(f"# bench events, same run: {rf['kernel']} average {rf['avg_launch_ms'] * 1e3:.1f} us "
+                                 f"per launch ({rf['achieved']:.0f} GB/s algorithmic)")
+    return "\n".join(lines) + "\n"
+
+
 # ---------------------------------------------------------------------------
 DESCRIPTIONS = {
     "256x256x128": "plain FP64 projection 256x256x128, dx=dy=25 m, dz=min(10*1.015^k,60) m, rho0=1.2exp(-z/8 km), "
@@ -690,6 +721,8 @@ def main():
     ap.add_argument("--pmc-run", action="store_true", help="the short run that the counter passes profile")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("RD_CSV", "WR_CSV"),
                     help="print the per-kernel traffic summary of two counter passes over --pmc-run")
+    ap.add_argument("--summarize-trace", nargs="+", metavar=("STATS_CSV", "BENCH_LOG"),
+                    help="print the per-kernel summary of a rocprofv3 --kernel-trace --stats run")
     ap.add_argument("--command", default="", help="command line recorded in the counter summary")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -698,6 +731,10 @@ def main():
         sys.exit(2)
     if args.summarize_counters:
         sys.stdout.write(summarize_counters(*args.summarize_counters, args.workload, args.command))
+        return
+    if args.summarize_trace:
+        sys.stdout.write(summarize_trace(args.summarize_trace[0], args.workload, args.command,
+                                         args.summarize_trace[1] if len(args.summarize_trace) > 1 else None))
         return
 
     import torch
