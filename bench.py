@@ -163,7 +163,7 @@ def cached_params(nx, ny, nz, dtype):
         except ValueError:
             return None
     val = data.get(f"gfx950:{nx},{ny},{nz}:{'fp64' if dtype == 'f64' else 'mixed'}")
-    return val if isinstance(val, list) and len(val) == 6 else None   # the library reads 6 values
+    return val if isinstance(val, list) and len(val) in (6, 7) else None   # as the library reads them
 
 
 def cached_batch(count, dtype):

@@ -276,7 +276,8 @@ int monc_profile_read(monc_plan* plan, double* ms, int* launches);
  * keep the fastest. For every distinct grid among plans[0..count-1], the tile
  * parameters (FFT elements per thread, y-FFT columns per workgroup,
  * tridiagonal lanes per column and columns per workgroup, x transforms per
- * workgroup) are tuned on the grid's first plan, one parameter after the
+ * workgroup, the radix plan of the compile-time y-FFT) are tuned on the
+ * grid's first plan, one parameter after the
  * other, and copied to its other plans. For count > 1 the batch schedule
  * of monc_project_batched over these plans is then tuned as a whole: each
  * member order (largest or smallest first) and grouping (all members per
@@ -316,7 +317,7 @@ enum { MONC_PROBE_READ = 0, MONC_PROBE_WRITE = 1, MONC_PROBE_COPY = 2, MONC_PROB
 int monc_stream_probe(int kind, void* a, void* b, void* c, void* d, size_t bytes, void* stream);
 
 /* Number of tile parameters. */
-#define MONC_NPARAMS 6
+#define MONC_NPARAMS 7
 
 /* Current tile parameters of a plan, out[MONC_NPARAMS]:
  *   out[0] = x-FFT elements per thread (runtime-length FFTs only),
@@ -327,7 +328,10 @@ int monc_stream_probe(int kind, void* a, void* b, void* c, void* d, size_t bytes
  *            at most 1024 threads),
  *   out[5] = x-direction transforms (row pairs) per workgroup of the
  *            compile-time x-FFT kernels (at most 512 threads and 160 KB of
- *            LDS per workgroup; default 256 threads' worth). */
+ *            LDS per workgroup; default 256 threads' worth),
+ *   out[6] = elements per thread of the compile-time y-FFT kernels, i.e.
+ *            their radix plan: 8 (radix-8 passes) or 16 (radix-16 passes);
+ *            default 16 from ny = 2048 on, else 8. */
 int monc_plan_params(const monc_plan* plan, int* out);
 /* Set them from in[MONC_NPARAMS] (values are checked; 0 keeps the current
  * value). Synchronises the device. */

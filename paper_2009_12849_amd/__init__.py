@@ -24,9 +24,9 @@ __all__ = ["Plan", "project_batched", "stream_probe", "autotune_batched", "batch
 FP64, MIXED = 0, 1
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP = 0, -1, -2, -3, -4
 STAGE_FORWARD, STAGE_SOLVE, STAGE_INVERSE, STAGE_GRADIENT, STAGE_RESIDUAL = 1, 2, 3, 4, 5
-NPARAMS = 6  # tile parameters: x/y FFT elements per thread, y-FFT columns,
+NPARAMS = 7  # tile parameters: x/y FFT elements per thread, y-FFT columns,
              # tridiagonal lanes per column, tridiagonal columns per workgroup,
-             # x transforms per workgroup
+             # x transforms per workgroup, y-FFT elements per thread
 KERNELS = ["div_fftx", "ffty_fwd", "tridiag", "ffty_inv", "ifftx", "grad",
            "resid_fftx", "grad_final"]
 

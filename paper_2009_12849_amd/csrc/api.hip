@@ -88,7 +88,7 @@ struct monc_plan {
   int nx = 0, ny = 0, nz = 0, dtype = 0, device = 0;
   double dx = 0, dy = 0;
   std::vector<double> dz, rho0;
-  int ex = 8, ey = 8, ymt = 0, triP = 0, tricw = 0, xpw = 0;  // tile parameters (0 = automatic)
+  int ex = 8, ey = 8, ymt = 0, triP = 0, tricw = 0, xpw = 0, yept = 0;  // tile parameters (0 = automatic)
   MemberDesc h{};                          // host copy with device pointers
   MemberDesc* d_desc = nullptr;            // device copy
   void* d_tables = nullptr;
@@ -121,9 +121,9 @@ static int tri_rows(int nz, int P) {
   return 0;
 }
 
-// Derive FFT plans and tile parameters from (ex, ey, ymt, triP, tricw, xpw);
-// 0 = default.
-static int configure_tiles(monc_plan* pl, int ex, int ey, int ymt, int triP, int tricw, int xpw) {
+// Derive FFT plans and tile parameters from (ex, ey, ymt, triP, tricw, xpw,
+// yept); 0 = default.
+static int configure_tiles(monc_plan* pl, int ex, int ey, int ymt, int triP, int tricw, int xpw, int yept) {
   MemberDesc& h = pl->h;
   FftPlan fx{}, fy{};
   if (!radix_plan(pl->nx, fx) || !radix_plan(pl->ny, fy))
@@ -135,10 +135,18 @@ static int configure_tiles(monc_plan* pl, int ex, int ey, int ymt, int triP, int
   if (!fft_threads(fx, ex) || !fft_threads(fy, ey))
     return fail(MONC_EUNSUPPORTED, "FFT of nx=%d or ny=%d needs more than 1024 threads", pl->nx, pl->ny);
   const size_t cb = cplx_bytes(pl->dtype);
+  // elements per thread of the compile-time y-FFT (its radix plan): 8 or 16
+  if (yept <= 0) yept = pl->yept;
+  if (yept != 0 && yept != 8 && yept != 16)
+    return fail(MONC_EINVAL, "y-FFT elements per thread must be 8 or 16 (got %d)", yept);
+  const int yeff = yept > 0 ? yept : ct_yept_default(pl->ny);
   // y-FFT columns per workgroup (also the width of the spectral column
   // blocks, up to 8): 128 bytes of a row by default, bounded by the
   // workgroup size (1024) and 128 KB of LDS
-  const int nty = ct_supported(pl->ny) ? ct_threads_y_host(pl->ny) : fy.nt;
+  const int nty = ct_supported(pl->ny) ? ct_threads_y_host(pl->ny, yeff) : fy.nt;
+  if (nty > 1024)
+    return fail(MONC_EUNSUPPORTED, "a %d-point y-FFT with %d elements per thread needs more than 1024 threads", pl->ny,
+                yeff);
   const int mt_cap = std::max(1, std::min(1024 / nty, (int)(131072 / (pl->ny * cb))));
   if (ymt <= 0) ymt = pl->ymt > 0 ? pl->ymt : (int)(128 / cb);
   if (ymt > 64) return fail(MONC_EINVAL, "y-FFT columns per workgroup must be <= 64 (got %d)", ymt);
@@ -180,6 +188,8 @@ static int configure_tiles(monc_plan* pl, int ex, int ey, int ymt, int triP, int
   pl->ymt = ymt;
   pl->xpw = xpw;
   h.xpw = xeff;
+  pl->yept = yept;
+  h.yept = yeff;
   // spectral column blocks as wide as a y-FFT tile (up to kSpecBlockMax), so
   // that the tile is one contiguous run of each level
   h.sbw = std::min(kSpecBlockMax, pow2_floor(ymt));
@@ -204,7 +214,8 @@ static int upload_desc(monc_plan* pl) {
 }
 
 // ---------------------------------------------------------------------------
-// tuning cache (flat JSON object: "arch:nx,ny,nz:dtype" -> [ex, ey, ymt, triP, tricw, xpw])
+// tuning cache (flat JSON object: "arch:nx,ny,nz:dtype" -> [ex, ey, ymt, triP, tricw, xpw, yept];
+// entries without the last value read it as 0, the default)
 // ---------------------------------------------------------------------------
 static std::mutex g_cache_mu;
 
@@ -338,31 +349,38 @@ extern "C" monc_plan* monc_plan_create(int nx, int ny, int nz, double dx, double
   h.rdxf = (float)h.rdx;
   h.rdyf = (float)h.rdy;
   // tile parameters (cached tuning first)
-  int ex = 0, ey = 0, ymt = 0, triP = 0, tricw = 0, xpw = 0;
+  int ex = 0, ey = 0, ymt = 0, triP = 0, tricw = 0, xpw = 0, yept = 0;
   if (const char* path = std::getenv("MONC_TUNE_CACHE")) {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     auto m = read_cache(path);
     auto it = m.find(cache_key(pl.get()));
-    if (it != m.end() && it->second.size() == MONC_NPARAMS) {
+    if (it != m.end() && (it->second.size() == MONC_NPARAMS || it->second.size() == MONC_NPARAMS - 1)) {
       ex = it->second[0];
       ey = it->second[1];
       ymt = it->second[2];
       triP = it->second[3];
       tricw = it->second[4];
       xpw = it->second[5];
+      yept = it->second.size() > 6 ? it->second[6] : 0;
     }
   }
-  if (configure_tiles(pl.get(), ex, ey, ymt, triP, tricw, xpw) != MONC_OK &&
-      configure_tiles(pl.get(), 8, 8, 0, 0, 0, 0) != MONC_OK)
+  if (configure_tiles(pl.get(), ex, ey, ymt, triP, tricw, xpw, yept) != MONC_OK &&
+      configure_tiles(pl.get(), 8, 8, 0, 0, 0, 0, 0) != MONC_OK)
     return nullptr;
 
   // host tables
   VerticalTables vt = vertical_tables(nz, dz, rho0);
   h.rH = vt.rH;
   {
-    double sr = 0.0;
-    for (int k = 0; k < nz; ++k) sr += dz[k] * rho0[k];
+    double sr = 0.0, cmax = 0.0;
+    for (int k = 0; k < nz; ++k) {
+      sr += dz[k] * rho0[k];
+      cmax = std::max(cmax, (vt.ta[k] + vt.tc[k]) / rho0[k]);
+    }
     h.rSr = 1.0 / sr;
+    // a column with lam >= 1e-4 max_k (a_k + c_k)/rho0_k has a condition
+    // number below ~1e4 and gains nothing from the deflation
+    h.lamdef = 1e-4 * cmax;
   }
   std::vector<double> lamx = modified_wavenumbers(nx, h.nxh, dx);
   std::vector<double> lamy = modified_wavenumbers(ny, ny, dy);
@@ -580,7 +598,7 @@ static Shape member_shape(const MemberDesc& d, Phase ph, bool fp64) {
     }
   } else if (is_yphase(ph)) {
     if (ct_supported(d.ny)) {
-      const int nt = ct_threads_y_host(d.ny);
+      const int nt = ct_threads_y_host(d.ny, d.yept);
       const int mt = std::max(1, std::min(d.ymt, 1024 / nt));
       s.variant = d.ny;
       s.block = mt * nt;
@@ -646,8 +664,8 @@ static int launch_one(const Group& g, const std::vector<int>& idx, Phase ph, con
     case PH_XFWD: launch_xfwd(a, grid, block, lds, g.fp64, 0, v, stream); break;
     case PH_XPRE: launch_xfwd(a, grid, block, lds, g.fp64, 2, v, stream); break;
     case PH_RESID: launch_xfwd(a, grid, block, lds, false, 1, v, stream); break;
-    case PH_YFWD: launch_ffty(a, grid, block, lds, g.fp64, false, v, stream); break;
-    case PH_YINV: launch_ffty(a, grid, block, lds, g.fp64, true, v, stream); break;
+    case PH_YFWD: launch_ffty(a, grid, block, lds, g.fp64, false, v, g.mem[idx[0]].h->yept, stream); break;
+    case PH_YINV: launch_ffty(a, grid, block, lds, g.fp64, true, v, g.mem[idx[0]].h->yept, stream); break;
     case PH_TRI: launch_tridiag(a, grid, block, lds, g.fp64, v, stream); break;
     case PH_XINV: launch_xinv(a, grid, block, lds, g.fp64, 0, v, stream); break;
     case PH_XINV_P1: launch_xinv(a, grid, block, lds, false, 2, v, stream); break;
@@ -1452,6 +1470,7 @@ extern "C" int monc_plan_params(const monc_plan* pl, int* out) {
   out[3] = pl->triP;
   out[4] = pl->h.tricw;
   out[5] = pl->h.xpw;
+  out[6] = pl->h.yept;
   return MONC_OK;
 }
 
@@ -1460,11 +1479,12 @@ extern "C" int monc_plan_set_params(monc_plan* pl, const int* in) {
   for (int i = 0; i < MONC_NPARAMS; ++i)
     if (in[i] < 0) return fail(MONC_EINVAL, "parameter %d is negative", i);
   const MemberDesc saved = pl->h;
-  const int sv[MONC_NPARAMS] = {pl->ex, pl->ey, pl->ymt, pl->triP, pl->tricw, pl->xpw};
-  int rc = configure_tiles(pl, in[0], in[1], in[2], in[3], in[4], in[5]);
+  const int sv[MONC_NPARAMS] = {pl->ex, pl->ey, pl->ymt, pl->triP, pl->tricw, pl->xpw, pl->yept};
+  int rc = configure_tiles(pl, in[0], in[1], in[2], in[3], in[4], in[5], in[6]);
   if (rc != MONC_OK) {
     pl->h = saved;
     pl->ex = sv[0]; pl->ey = sv[1]; pl->ymt = sv[2]; pl->triP = sv[3]; pl->tricw = sv[4]; pl->xpw = sv[5];
+    pl->yept = sv[6];
     return rc;
   }
   HIP_TRY(hipDeviceSynchronize());  // in-flight work may still read the old descriptor
@@ -1510,7 +1530,7 @@ static int tune_plan(monc_plan* pl, void* stream) {
     for (int k = 0; k < MONC_K_COUNT; ++k) cost += ms[k];
     return MONC_OK;
   };
-  int best[MONC_NPARAMS] = {pl->ex, pl->ey, pl->ymt, pl->triP, pl->tricw, pl->h.xpw};
+  int best[MONC_NPARAMS] = {pl->ex, pl->ey, pl->ymt, pl->triP, pl->tricw, pl->h.xpw, pl->h.yept};
   {
     double whole = 0.0;
     const int r = measure(best, (1u << MONC_K_COUNT) - 1, whole);
@@ -1537,8 +1557,11 @@ static int tune_plan(monc_plan* pl, void* stream) {
   std::vector<Axis> axes;
   if (!ct_supported(pl->nx)) axes.push_back({0, {2, 4, 8}, xmask});
   if (!ct_supported(pl->ny)) axes.push_back({1, {2, 4, 8}, ymask});
-  // the y tile width also sets the spectral column blocks, which shape the
-  // x kernels' spectral traffic: timed over both
+  // the radix plan of the compile-time y-FFT (8 or 16 elements per thread),
+  // timed together with the y tile width, which it bounds (threads per
+  // workgroup) and which sets the spectral column blocks that shape the x
+  // kernels' spectral traffic
+  if (ct_supported(pl->ny) && pl->ny >= 16) axes.push_back({6, {8, 16}, ymask | xmask});
   axes.push_back({2, {1, 2, 4, 8, 16, 32}, ymask | xmask});
   axes.push_back({3, pvals, tmask});
   axes.push_back({4, {4, 8, 16, 32}, tmask});
@@ -1569,7 +1592,7 @@ static int tune_plan(monc_plan* pl, void* stream) {
   if (const char* path = std::getenv("MONC_TUNE_CACHE")) {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     auto m = read_cache(path);
-    m[cache_key(pl)] = {pl->ex, pl->ey, pl->ymt, pl->triP, pl->tricw, pl->h.xpw};
+    m[cache_key(pl)] = {pl->ex, pl->ey, pl->ymt, pl->triP, pl->tricw, pl->h.xpw, pl->h.yept};
     write_cache(path, m);
   }
   return MONC_OK;

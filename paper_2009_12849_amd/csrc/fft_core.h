@@ -205,7 +205,7 @@ constexpr int ct_vmax(int n, int nt, bool r16) {
 // threads per compile-time transform: ct_threads / ct_threads_y (shared
 // with the host, in monc_types.h)
 constexpr int ct_threads(int n) { return ct_threads_x_n(n); }
-constexpr int ct_threads_y(int n) { return ct_threads_y_n(n); }
+constexpr int ct_threads_y(int n, int ept) { return ct_threads_y_n(n, ept); }
 
 // LDS index of element i of an x-direction transform of length N (bank
 // rows permuted by XOR, or padded; see xlds_len)

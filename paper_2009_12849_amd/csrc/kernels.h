@@ -15,14 +15,15 @@ void init_kernel_attributes();
 // columns per workgroup) * that.
 bool ct_supported(int n);
 inline int ct_threads_host(int n) { return ct_threads_x_n(n); }
-inline int ct_threads_y_host(int n) { return ct_threads_y_n(n); }
+inline int ct_threads_y_host(int n, int ept) { return ct_threads_y_n(n, ept); }
 
 // ct_n: the compile-time length, or 0 for the runtime-length kernel.
 // mode 0: divergence of (u, v, w); mode 1 (float only): the FP64 residual
 // D(u) - D(G p1) with the first-pass pressure p1 in io.s2; mode 2: the FP64
 // field at io.u (nz, ny, nx), rounded to the storage type.
 void launch_xfwd(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, int mode, int ct_n, void* stream);
-void launch_ffty(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, bool inverse, int ct_n,
+// ept: elements per thread of the compile-time kernel (8 or 16)
+void launch_ffty(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, bool inverse, int ct_n, int ept,
                  void* stream);
 // rows: rows per lane, one of kTriRows (the member's tris)
 void launch_tridiag(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, int rows, void* stream);

@@ -664,9 +664,9 @@ __global__ void __launch_bounds__(1024) k_xfwd_gen(LaunchArgs a) {
 // one level and MT = blockDim / NT consecutive m columns; LDS holds them as
 // [j][c] so that consecutive lanes touch consecutive columns (128-byte rows).
 // ---------------------------------------------------------------------------
-template <typename T, bool INV, int N>
+template <typename T, bool INV, int N, int EPT>
 __global__ void __launch_bounds__(1024) k_ffty_ct(LaunchArgs a) {
-  constexpr int NT = ct_threads_y(N);
+  constexpr int NT = ct_threads_y(N, EPT);
   using F = CtFft<T, N, NT, INV>;
   extern __shared__ unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
@@ -1117,8 +1117,12 @@ __device__ __forceinline__ void tri_tile(const MemberDesc& d, const IoPtrs& io, 
   // near-singularity of the low-wavenumber columns (lam -> 0) acts on Q, not
   // on the large c ~ 1/lam. The (0,0) column (lam = 0) keeps its own gauge
   // treatment; padding columns have B = 0, so c = 0.
+  // Only waves holding a column with lam < lamdef (condition number above
+  // ~1e4: the lowest wavenumbers, a few columns in a million) do it; the
+  // branch is uniform over the wave, so the lane reduction sees every lane.
   double2 cdef = make_double2(0.0, 0.0);
   if constexpr (!F32) {
+    if (__any(lam < d.lamdef)) {
     double2 sb = make_double2(0.0, 0.0);
 #pragma unroll
     for (int r = 0; r < S; ++r) {
@@ -1136,6 +1140,7 @@ __device__ __forceinline__ void tri_tile(const MemberDesc& d, const IoPtrs& io, 
       }
       const double il = 1.0 / lam;
       cdef = make_double2(-gx * il, -gy * il);
+    }
     }
   }
 
@@ -1559,10 +1564,14 @@ void init_kernel_attributes() {
   set_lds_limit(k_xfwd_ct<float, 1, N>);      \
   set_lds_limit(k_xfwd_ct<double, 2, N>);     \
   set_lds_limit(k_xfwd_ct<float, 2, N>);      \
-  set_lds_limit(k_ffty_ct<double, false, N>); \
-  set_lds_limit(k_ffty_ct<double, true, N>);  \
-  set_lds_limit(k_ffty_ct<float, false, N>);  \
-  set_lds_limit(k_ffty_ct<float, true, N>);   \
+  set_lds_limit(k_ffty_ct<double, false, N, 8>); \
+  set_lds_limit(k_ffty_ct<double, true, N, 8>);  \
+  set_lds_limit(k_ffty_ct<float, false, N, 8>);  \
+  set_lds_limit(k_ffty_ct<float, true, N, 8>);   \
+  set_lds_limit(k_ffty_ct<double, false, N, 16>); \
+  set_lds_limit(k_ffty_ct<double, true, N, 16>);  \
+  set_lds_limit(k_ffty_ct<float, false, N, 16>);  \
+  set_lds_limit(k_ffty_ct<float, true, N, 16>);   \
   set_lds_limit(k_xinv_ct<double, 0, N>);     \
   set_lds_limit(k_xinv_ct<float, 0, N>);      \
   set_lds_limit(k_xinv_ct<float, 1, N>);      \
@@ -1594,18 +1603,28 @@ void launch_xfwd(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64
   }
 }
 
-void launch_ffty(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, bool inverse, int ct_n,
+void launch_ffty(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, bool inverse, int ct_n, int ept,
                  void* stream) {
   switch (ct_n) {
-#define MONC_CASE(N)                                                  \
-  case N:                                                             \
-    if (fp64) {                                                       \
-      if (inverse) MONC_GO((k_ffty_ct<double, true, N>));             \
-      else MONC_GO((k_ffty_ct<double, false, N>));                    \
-    } else {                                                          \
-      if (inverse) MONC_GO((k_ffty_ct<float, true, N>));              \
-      else MONC_GO((k_ffty_ct<float, false, N>));                     \
-    }                                                                 \
+#define MONC_CASE(N)                                                                  \
+  case N:                                                                             \
+    if (ept == 16) {                                                                  \
+      if (fp64) {                                                                     \
+        if (inverse) MONC_GO((k_ffty_ct<double, true, N, 16>));                       \
+        else MONC_GO((k_ffty_ct<double, false, N, 16>));                              \
+      } else {                                                                        \
+        if (inverse) MONC_GO((k_ffty_ct<float, true, N, 16>));                        \
+        else MONC_GO((k_ffty_ct<float, false, N, 16>));                               \
+      }                                                                               \
+    } else {                                                                          \
+      if (fp64) {                                                                     \
+        if (inverse) MONC_GO((k_ffty_ct<double, true, N, 8>));                        \
+        else MONC_GO((k_ffty_ct<double, false, N, 8>));                               \
+      } else {                                                                        \
+        if (inverse) MONC_GO((k_ffty_ct<float, true, N, 8>));                         \
+        else MONC_GO((k_ffty_ct<float, false, N, 8>));                                \
+      }                                                                               \
+    }                                                                                 \
     return;
     MONC_CT_SIZES(MONC_CASE)
 #undef MONC_CASE

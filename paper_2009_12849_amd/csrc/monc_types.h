@@ -33,7 +33,10 @@ constexpr int tri_lane_slots(int s, bool f32) {
 // along y sixteen from length 2048 on, so that a 1024-thread workgroup still
 // holds several columns of the longest transforms, eight below.
 constexpr int ct_threads_x_n(int n) { return n >= 512 ? n / 16 : (n >= 8 ? n / 8 : 1); }
-constexpr int ct_threads_y_n(int n) { return n >= 2048 ? n / 16 : (n >= 8 ? n / 8 : 1); }
+// Along y the elements per thread (8: radix-8 passes, 16: radix-16 passes)
+// are a tile parameter: default sixteen from length 2048 on, eight below.
+constexpr int ct_yept_default(int n) { return n >= 2048 ? 16 : 8; }
+constexpr int ct_threads_y_n(int n, int ept) { return n >= ept ? n / ept : 1; }
 
 // x-FFT LDS layout (shared by the kernels and the host's LDS sizes). For
 // transforms with radix-16 passes (16 elements per thread), a bank row (256
@@ -76,6 +79,7 @@ struct MemberDesc {
   double inv_nxny;        // 1/(nx ny), the inverse-FFT normalisation
   double rH;              // 1 / sum(dz)
   double rSr;             // 1 / sum(dz rho0), the near-null deflation of the column solves
+  double lamdef;          // columns with a smaller horizontal eigenvalue are deflated
   float rdxf, rdyf;       // FP32 copies for the FP32 stencil
   // FP64 vertical tables, all of length nz
   const double* rho0;     // reference density at centres
@@ -110,6 +114,7 @@ struct MemberDesc {
   int tricw;              // columns per workgroup (blockDim / triP)
   int ptk;                // levels per (level, row pair) tile of the stencil kernels (1 = row order)
   int xpw;                // x-direction transforms (row pairs) per workgroup of the compile-time kernels
+  int yept;               // elements per thread of the compile-time y-FFT kernels (8 or 16)
   // Spectral layout: a level's half spectrum sits in column blocks of sbw
   // consecutive m (the y-FFT tile width), each block row-major over n:
   // element (k, n, m) at k*plane + (m >> lbw)*bst + n*sbw + (m & (sbw-1)).
