@@ -331,7 +331,13 @@ int monc_stream_probe(int kind, void* a, void* b, void* c, void* d, size_t bytes
  *            LDS per workgroup; default 256 threads' worth),
  *   out[6] = elements per thread of the compile-time y-FFT kernels, i.e.
  *            their radix plan: 8 (radix-8 passes) or 16 (radix-16 passes);
- *            default 16 from ny = 2048 on, else 8. */
+ *            default 16 from ny = 2048 on, else 8. On MONC_MIXED plans with
+ *            ny = 1024, 1536, 2048 or 4096 also 32: a persistent kernel
+ *            (one workgroup per CU, 512 columns' worth of threads, each
+ *            workgroup loading its next tile while transforming the
+ *            current one) whose tile width is fixed by ny; out[2] then
+ *            only sets the spectral column blocks. Other values or plans:
+ *            MONC_EINVAL. */
 int monc_plan_params(const monc_plan* plan, int* out);
 /* Set them from in[MONC_NPARAMS] (values are checked; 0 keeps the current
  * value). Synchronises the device. */

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cmath>
 #include <cstdarg>
@@ -135,10 +136,15 @@ static int configure_tiles(monc_plan* pl, int ex, int ey, int ymt, int triP, int
   if (!fft_threads(fx, ex) || !fft_threads(fy, ey))
     return fail(MONC_EUNSUPPORTED, "FFT of nx=%d or ny=%d needs more than 1024 threads", pl->nx, pl->ny);
   const size_t cb = cplx_bytes(pl->dtype);
-  // elements per thread of the compile-time y-FFT (its radix plan): 8 or 16
+  // elements per thread of the compile-time y-FFT (its radix plan): 8 or 16,
+  // or 32 = the persistent FP32 kernel (mixed plans, lengths of
+  // pp_supported)
   if (yept <= 0) yept = pl->yept;
-  if (yept != 0 && yept != 8 && yept != 16)
-    return fail(MONC_EINVAL, "y-FFT elements per thread must be 8 or 16 (got %d)", yept);
+  if (yept != 0 && yept != 8 && yept != 16 && yept != 32)
+    return fail(MONC_EINVAL, "y-FFT elements per thread must be 8, 16 or 32 (got %d)", yept);
+  if (yept == 32 && (pl->dtype == MONC_FP64 || !pp_supported(pl->ny)))
+    return fail(MONC_EINVAL, "32 y-FFT elements per thread (the persistent kernel) need a mixed plan and ny of "
+                             "1024, 1536, 2048 or 4096 (got ny=%d)", pl->ny);
   const int yeff = yept > 0 ? yept : ct_yept_default(pl->ny);
   // y-FFT columns per workgroup (also the width of the spectral column
   // blocks, up to 8): 128 bytes of a row by default, bounded by the
@@ -574,9 +580,23 @@ struct Shape {
   int variant = 0;   // compile-time length, or 0 for the runtime-length kernel
   int block = 256;
   size_t lds = 0;
-  long long blocks = 0;
+  long long blocks = 0;       // tiles of the phase
+  bool persistent = false;    // the grid covers the CUs once and walks the tiles
 };
 
+
+// compute units of the current device (queried once per device)
+static int cu_count() {
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  int n = cache[dev].load();
+  if (n <= 0) {
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cache[dev].store(n);
+  }
+  return n;
+}
 
 static Shape member_shape(const MemberDesc& d, Phase ph, bool fp64) {
   const size_t cb = fp64 ? 16 : 8;
@@ -597,7 +617,17 @@ static Shape member_shape(const MemberDesc& d, Phase ph, bool fp64) {
       s.blocks = (pairs + ipw - 1) / ipw;
     }
   } else if (is_yphase(ph)) {
-    if (ct_supported(d.ny)) {
+    if (ct_supported(d.ny) && d.yept == 32) {
+      // the persistent kernel: a fixed number of columns per tile (ymt then
+      // only sets the spectral column blocks)
+      const int nt = ct_threads_y_host(d.ny, 32);
+      const int mt = pp_columns(d.ny);
+      s.variant = d.ny;
+      s.block = mt * nt;
+      s.lds = (size_t)d.ny * (mt + 1) * cb;  // the tile and the twiddle table
+      s.blocks = (long long)d.nz * ((d.nxh + mt - 1) / mt);
+      s.persistent = true;
+    } else if (ct_supported(d.ny)) {
       const int nt = ct_threads_y_host(d.ny, d.yept);
       const int mt = std::max(1, std::min(d.ymt, 1024 / nt));
       s.variant = d.ny;
@@ -649,7 +679,9 @@ static int launch_one(const Group& g, const std::vector<int>& idx, Phase ph, con
   if (block > 1024) return fail(MONC_EUNSUPPORTED, "launch needs %d threads per workgroup", block);
   if (lds > 160 * 1024) return fail(MONC_EUNSUPPORTED, "phase needs %zu bytes of LDS", lds);
   if (blocks == 0) return MONC_OK;
-  const int grid = (int)blocks;
+  // a persistent kernel takes one workgroup per CU slot its LDS leaves
+  const int grid = sh.persistent ? (int)std::min<long long>(blocks, (long long)cu_count() * std::max<size_t>(1, (160 * 1024) / lds))
+                                 : (int)blocks;
   const int kid = phase_kernel_id(ph);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const bool timed = prof && (prof->mask >> kid & 1u);
@@ -697,12 +729,14 @@ static int launch_one(const Group& g, const std::vector<int>& idx, Phase ph, con
 // instance and workgroup size, and each partition (up to kMaxLaunchMembers
 // members) is one launch.
 static int launch_phase(const Group& g, Phase ph, void* stream, Profiler* prof) {
-  std::vector<std::pair<std::pair<int, int>, std::vector<int>>> parts;
+  std::vector<std::pair<std::array<int, 3>, std::vector<int>>> parts;
   std::vector<Shape> shapes;
   for (int i = 0; i < (int)g.mem.size(); ++i) {
     const Shape s = member_shape(*g.mem[i].h, ph, g.fp64);
-    // the compile-time kernels need blockDim to match each member exactly
-    const std::pair<int, int> key{s.variant, s.variant ? s.block : 0};
+    // the compile-time kernels need blockDim to match each member exactly,
+    // and the y kernels the member's elements per thread
+    const std::array<int, 3> key{s.variant, s.variant ? s.block : 0,
+                                 (s.variant && is_yphase(ph)) ? g.mem[i].h->yept : 0};
     size_t pi = 0;
     while (pi < parts.size() && (parts[pi].first != key || parts[pi].second.size() >= (size_t)kMaxLaunchMembers)) ++pi;
     if (pi == parts.size()) {
@@ -1557,11 +1591,15 @@ static int tune_plan(monc_plan* pl, void* stream) {
   std::vector<Axis> axes;
   if (!ct_supported(pl->nx)) axes.push_back({0, {2, 4, 8}, xmask});
   if (!ct_supported(pl->ny)) axes.push_back({1, {2, 4, 8}, ymask});
-  // the radix plan of the compile-time y-FFT (8 or 16 elements per thread),
+  // the radix plan of the compile-time y-FFT (8 or 16 elements per thread;
+  // on mixed plans of the lengths it covers also 32, the persistent kernel),
   // timed together with the y tile width, which it bounds (threads per
   // workgroup) and which sets the spectral column blocks that shape the x
   // kernels' spectral traffic
-  if (ct_supported(pl->ny) && pl->ny >= 16) axes.push_back({6, {8, 16}, ymask | xmask});
+  if (ct_supported(pl->ny) && pl->ny >= 16) {
+    if (pl->dtype != MONC_FP64 && pp_supported(pl->ny)) axes.push_back({6, {8, 16, 32}, ymask | xmask});
+    else axes.push_back({6, {8, 16}, ymask | xmask});
+  }
   axes.push_back({2, {1, 2, 4, 8, 16, 32}, ymask | xmask});
   axes.push_back({3, pvals, tmask});
   axes.push_back({4, {4, 8, 16, 32}, tmask});

@@ -236,8 +236,10 @@ struct CtFft {
     return q + t * NT + r * NB<P>();
   }
 
-  template <int P>
-  __device__ static __forceinline__ void butterflies(cx<T>* v, int q, const cx<T>* __restrict__ tw) {
+  // tw(i) returns the twiddle exp(-2 pi i i/N) (a global table, or a copy
+  // of it in LDS)
+  template <int P, class Tw>
+  __device__ static __forceinline__ void butterflies(cx<T>* v, int q, const Tw& tw) {
     constexpr int Rr = R<P>(), NS = ct_ns(N, R16, P), TSTEP = N / (NS * Rr);
 #pragma unroll
     for (int t = 0; t < BT<P>(); ++t) {
@@ -247,7 +249,7 @@ struct CtFft {
           const int kk = b % NS;
 #pragma unroll
           for (int r = 1; r < Rr; ++r) {
-            const cx<T> w = load_tw(tw + kk * r * TSTEP);
+            const cx<T> w = tw(kk * r * TSTEP);
             v[t * Rr + r] = INV ? cmulconj(v[t * Rr + r], w) : cmul(v[t * Rr + r], w);
           }
         }
@@ -283,9 +285,8 @@ struct CtFft {
     __syncthreads();
   }
 
-  template <int P, class Idx>
-  __device__ static __forceinline__ void run_from(cx<T>* v, cx<T>* lds, const Idx& li, int q,
-                                                  const cx<T>* __restrict__ tw) {
+  template <int P, class Idx, class Tw>
+  __device__ static __forceinline__ void run_from(cx<T>* v, cx<T>* lds, const Idx& li, int q, const Tw& tw) {
     butterflies<P>(v, q, tw);
     if constexpr (P + 1 < NP) {
       exchange<P>(v, lds, li, q);
@@ -295,9 +296,15 @@ struct CtFft {
 
   // Whole transform: v holds the inputs of pass 0 on entry and the outputs of
   // the last pass on exit (positions given by in_index<0> / out_index).
+  // Twiddles from the global table tw.
   template <class Idx>
   __device__ static __forceinline__ void run(cx<T>* v, cx<T>* lds, const Idx& li, int q,
                                              const cx<T>* __restrict__ tw) {
+    run_from<0>(v, lds, li, q, [tw](int i) { return load_tw(tw + i); });
+  }
+  // Twiddles from an accessor (e.g. an LDS copy of the table)
+  template <class Idx, class Tw>
+  __device__ static __forceinline__ void run_tw(cx<T>* v, cx<T>* lds, const Idx& li, int q, const Tw& tw) {
     run_from<0>(v, lds, li, q, tw);
   }
 

@@ -14,6 +14,8 @@ void init_kernel_attributes();
 // n < 8; along y n/16 from n = 2048 on) and need blockDim = (transforms or
 // columns per workgroup) * that.
 bool ct_supported(int n);
+// lengths with the persistent FP32 y-FFT kernel (32 elements per thread)
+bool pp_supported(int n);
 inline int ct_threads_host(int n) { return ct_threads_x_n(n); }
 inline int ct_threads_y_host(int n, int ept) { return ct_threads_y_n(n, ept); }
 
@@ -22,7 +24,8 @@ inline int ct_threads_y_host(int n, int ept) { return ct_threads_y_n(n, ept); }
 // D(u) - D(G p1) with the first-pass pressure p1 in io.s2; mode 2: the FP64
 // field at io.u (nz, ny, nx), rounded to the storage type.
 void launch_xfwd(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, int mode, int ct_n, void* stream);
-// ept: elements per thread of the compile-time kernel (8 or 16)
+// ept: elements per thread of the compile-time kernel (8 or 16; 32 = the
+// persistent FP32 kernel, whose grid covers the CUs once)
 void launch_ffty(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, bool inverse, int ct_n, int ept,
                  void* stream);
 // rows: rows per lane, one of kTriRows (the member's tris)

@@ -88,8 +88,9 @@ __device__ __forceinline__ RowCtx make_row(const MemberDesc& d, long long row, b
   RowCtx c;
   const int ny = d.ny, nz = d.nz;
   const long long r = valid ? row : 0;
-  const int k = (int)(r / ny);
-  const int j = (int)(r - (long long)k * ny);
+  // rows (ny nz of them) and their level and row index fit 32 bits
+  const int k = (int)r / ny;
+  const int j = (int)r - k * ny;
   c.k = k;
   c.off = r * d.nx;
   c.soff = ((long long)k * ny + (j == 0 ? ny - 1 : j - 1)) * d.nx;
@@ -454,8 +455,8 @@ __device__ __forceinline__ cx<T> split_bin(cx<T> z, cx<T> zr, int row) {
 // bytes); inside a block the rows are sbw apart, so a y-FFT tile of sbw
 // columns is one contiguous run and a row pair writes 2 sbw adjacent values.
 __device__ __forceinline__ long long spec_row(const MemberDesc& d, long long r) {
-  const int k = (int)(r / d.ny);
-  return (long long)k * d.plane + (r - (long long)k * d.ny) * d.sbw;
+  const int k = (int)r / d.ny;
+  return (long long)k * d.plane + (long long)((int)r - k * d.ny) * d.sbw;
 }
 __device__ __forceinline__ long long spec_col(const MemberDesc& d, int m) {
   return (long long)(m >> d.lbw) * d.bst + (m & (d.sbw - 1));
@@ -492,18 +493,20 @@ __device__ __forceinline__ void spec_nm(const MemberDesc& d, int x, int& n, int&
 // Bijection of [0, nz * per) that walks tiles of TJ consecutive items of TK
 // consecutive levels (per items per level), ragged tiles at the edges;
 // identity for TK <= 1 and beyond the grid.
+// (32-bit arithmetic: nz * per, a count of rows or row pairs, fits 32 bits)
 __device__ __forceinline__ long long tiled_index(long long p, long long per, int nz, int TK, int TJ) {
   if (TK <= 1 || p >= (long long)nz * per) return p;
-  const long long blk = (long long)TK * per;
-  const int kb = (int)(p / blk);
-  const long long rem = p - kb * blk;
+  const int pi = (int)p, pe = (int)per;
+  const int blk = TK * pe;
+  const int kb = pi / blk;
+  const int rem = pi - kb * blk;
   const int tk = min(TK, nz - kb * TK);          // levels in this block
-  const long long jt = rem / ((long long)tk * TJ);
-  const int tj = (int)min((long long)TJ, per - jt * TJ);
-  const int in = (int)(rem - jt * tk * TJ);
+  const int jt = rem / (tk * TJ);
+  const int tj = min(TJ, pe - jt * TJ);
+  const int in = rem - jt * tk * TJ;
   const int k = kb * TK + in / tj;
-  const long long jp = jt * TJ + in % tj;
-  return (long long)k * per + jp;
+  const int jp = jt * TJ + in % tj;
+  return (long long)k * pe + jp;
 }
 
 __device__ __forceinline__ long long tiled_pair(const MemberDesc& d, long long p) {
@@ -713,6 +716,126 @@ __global__ void __launch_bounds__(1024) k_ffty_ct(LaunchArgs a) {
         for (int r = 0; r < F::RL; ++r) S[F::out_index(q, t, r) * rs] = v[t * F::RL + r];
       }
     }
+  }
+}
+
+// y-direction complex FFT, persistent form (FP32, 32 elements per thread, so
+// that the 8 columns of a 2048-point tile take 512 threads and the prefetch
+// below fits the register budget of two waves per SIMD). The grid covers the
+// CUs once; workgroup w walks the launch's tiles w, w + gridDim.x, ... and
+// issues the loads of its next tile before transforming the current one, so
+// that the transform, its LDS exchanges and its stores overlap the next
+// tile's loads (a workgroup holds a CU's LDS alone, so nothing else would
+// cover them). Twiddles come from an LDS copy of the table: a global load
+// issued during the transform would wait behind the prefetched tile.
+// Columns past nxh load column 0 and are transformed but never stored.
+template <bool INV, int N>
+__global__ void __launch_bounds__(512) k_ffty_pp(LaunchArgs a) {
+  using T = float;
+  constexpr int NT = ct_threads_y(N, 32);
+  constexpr int MT = pp_columns(N);  // columns per tile
+  using F = CtFft<T, N, NT, INV>;
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* twl = lds + N * MT;
+  const int total = a.block_start[a.nmem];
+  if ((int)blockIdx.x >= total) return;
+  // every member of a launch has the same length N, hence the same table
+  {
+    const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.mem[0]->twy);
+    for (int i = threadIdx.x; i < N; i += blockDim.x) twl[i] = load_tw(tw + i);
+  }
+  // Tile tb of the launch: a workgroup-uniform base (the tile's first column
+  // in its level) and this lane's 32-bit element offset from it, so that every
+  // access is a scalar base plus one vector offset. A column past nxh takes
+  // the level's last column (transformed, never stored).
+  struct Tile {
+    cx<T>* base;
+    unsigned off;
+    int rs;
+    bool valid, live;
+  };
+  auto tile = [&](int tb, int c) {
+    const int mi = find_member(a, tb);
+    const MemberDesc& d = *a.mem[mi];
+    const int lb = tb - a.block_start[mi];
+    const int tiles = (d.nxh + MT - 1) / MT;
+    const int k = lb / tiles;
+    const int m0 = (lb - k * tiles) * MT;
+    const int m = m0 + c;
+    Tile t;
+    t.valid = m < d.nxh;
+    t.live = !skipped(d);
+    t.rs = wuni(d.sbw);
+    const long long b0 = (long long)k * d.plane + spec_col(d, m0);
+    t.base = reinterpret_cast<cx<T>*>(a.io[mi].spec) + b0;
+    t.off = (unsigned)(spec_col(d, t.valid ? m : d.nxh - 1) - spec_col(d, m0));
+    return t;
+  };
+  // element i of the lane's column (global-address-space accesses through
+  // the two-float vector type)
+  typedef T pair __attribute__((ext_vector_type(2)));
+  auto ld = [](const Tile& t, int i) -> cx<T> {
+    const pair x = ((const __attribute__((address_space(1))) pair*)t.base)[t.off + (unsigned)(i * t.rs)];
+    return cx<T>{x.x, x.y};
+  };
+  auto st = [](const Tile& t, int i, cx<T> x) {
+    ((__attribute__((address_space(1))) pair*)t.base)[t.off + (unsigned)(i * t.rs)] = pair{x.x, x.y};
+  };
+  cx<T> v[F::VMAX], nx[F::VMAX];
+  // The lane's column and row index are re-read through an empty asm at every
+  // tile: the LDS and twiddle addresses derived from them are then computed
+  // where they are used instead of being hoisted out of the loop, where they
+  // would hold registers the prefetched tile needs.
+  auto lane = [](int& c, int& q) {
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    c = t % MT;
+    q = t / MT;
+  };
+  int cur = blockIdx.x, c, q;
+  lane(c, q);
+  Tile tc = tile(cur, c);
+  auto load = [&](const Tile& t, int q, cx<T>* dst) {
+#pragma unroll
+    for (int u = 0; u < F::BT0; ++u) {
+      const int b = q + u * NT;
+      if (F::valid_first(b)) {
+#pragma unroll
+        for (int r = 0; r < F::R0; ++r) dst[u * F::R0 + r] = ld(t, b + r * F::NB0);
+      }
+    }
+  };
+  if (tc.live) load(tc, q, v);
+  __syncthreads();  // the twiddle table
+  while (true) {
+    const int nxt = cur + gridDim.x;
+    Tile tn;
+    tn.live = false;
+    lane(c, q);
+    if (nxt < total) {
+      tn = tile(nxt, c);
+      if (tn.live) load(tn, q, nx);
+    }
+    if (tc.live) {  // uniform over the workgroup (one member per tile)
+      lane(c, q);
+      F::run_tw(v, lds, [c](int i) { return i * MT + c; }, q, [twl](int i) { return twl[i]; });
+      if (tc.valid) {
+#pragma unroll
+        for (int u = 0; u < F::BTL; ++u) {
+          const int b = q + u * NT;
+          if (F::valid_last(b)) {
+#pragma unroll
+            for (int r = 0; r < F::RL; ++r) st(tc, F::out_index(q, u, r), v[u * F::RL + r]);
+          }
+        }
+      }
+    }
+    if (nxt >= total) break;
+    cur = nxt;
+    tc = tn;
+#pragma unroll
+    for (int i = 0; i < F::VMAX; ++i) v[i] = nx[i];
   }
 }
 
@@ -1414,7 +1537,8 @@ __global__ void __launch_bounds__(256) k_grad(LaunchArgs a) {
   // same tile, close in time, and hits the XCD's L2
   long long blk = lb;
   const int bpr = d.nx / (int)(blockDim.x * VEC);  // blocks per row
-  if (d.ptk > 1 && bpr >= 1 && bpr * (int)blockDim.x * VEC == d.nx) {
+  const bool rowblk = bpr >= 1 && bpr * (int)blockDim.x * VEC == d.nx;  // a block lies in one row
+  if (d.ptk > 1 && rowblk) {
     const long long row = tiled_index(lb / bpr, d.ny, d.nz, d.ptk, 8);
     blk = row * bpr + lb % bpr;
   }
@@ -1424,9 +1548,21 @@ __global__ void __launch_bounds__(256) k_grad(LaunchArgs a) {
   // with the reductions every thread reaches the workgroup reduction: one
   // past the grid reads point 0, stores nothing and contributes nothing
   const long long g = live ? g0 : 0;
-  const int k = (int)(g / nh);
-  const long long h = g - (long long)k * nh;
-  const int j = (int)(h / nx), i = (int)(h - (long long)j * nx);
+  int k, j, i;
+  if (rowblk) {
+    // the block's row (level k, row j) from its index: workgroup-uniform,
+    // so the divisions run on the scalar unit
+    const int row = (int)(blk / bpr);
+    const int rw = live ? row : 0;
+    k = rw / ny;
+    j = rw - k * ny;
+    i = live ? (int)(blk - (long long)row * bpr) * (int)blockDim.x * VEC + (int)threadIdx.x * VEC : 0;
+  } else {
+    k = (int)(g / nh);
+    const int h = (int)(g - (long long)k * nh);  // nx ny fits 32 bits
+    j = h / nx;
+    i = h - j * nx;
+  }
   const long long base = (long long)k * nh;
   const long long he = base + (long long)j * nx + ((i + VEC == nx) ? 0 : i + VEC);  // east of the last point
   const long long hn = base + (long long)((j == ny - 1) ? 0 : j + 1) * nx + i;
@@ -1525,11 +1661,24 @@ static void set_lds_limit(K kern) {
 
 #define MONC_TRI_ROWS(X) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(10) X(12) X(16)
 #define MONC_CT_SIZES(X) X(16) X(32) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(1536) X(2048) X(4096)
+// lengths with the persistent FP32 y kernel (32 elements per thread)
+#define MONC_PP_SIZES(X) X(1024) X(1536) X(2048) X(4096)
 
 bool ct_supported(int n) {
   switch (n) {
 #define MONC_CASE(N) case N:
     MONC_CT_SIZES(MONC_CASE)
+#undef MONC_CASE
+    return true;
+    default:
+      return false;
+  }
+}
+
+bool pp_supported(int n) {
+  switch (n) {
+#define MONC_CASE(N) case N:
+    MONC_PP_SIZES(MONC_CASE)
 #undef MONC_CASE
     return true;
     default:
@@ -1578,6 +1727,11 @@ void init_kernel_attributes() {
   set_lds_limit(k_xinv_ct<float, 2, N>);
   MONC_CT_SIZES(MONC_ATTR)
 #undef MONC_ATTR
+#define MONC_PP_ATTR(N)                  \
+  set_lds_limit(k_ffty_pp<false, N>);    \
+  set_lds_limit(k_ffty_pp<true, N>);
+  MONC_PP_SIZES(MONC_PP_ATTR)
+#undef MONC_PP_ATTR
 }
 
 #define MONC_GO(kern) hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, (hipStream_t)stream, a)
@@ -1605,6 +1759,19 @@ void launch_xfwd(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64
 
 void launch_ffty(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, bool inverse, int ct_n, int ept,
                  void* stream) {
+  if (ept == 32 && !fp64) {
+    switch (ct_n) {
+#define MONC_CASE(N)                                  \
+  case N:                                             \
+    if (inverse) MONC_GO((k_ffty_pp<true, N>));       \
+    else MONC_GO((k_ffty_pp<false, N>));              \
+    return;
+      MONC_PP_SIZES(MONC_CASE)
+#undef MONC_CASE
+      default: break;  // rejected by the plan's tile check
+    }
+    return;
+  }
   switch (ct_n) {
 #define MONC_CASE(N)                                                                  \
   case N:                                                                             \

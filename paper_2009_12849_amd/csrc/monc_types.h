@@ -37,6 +37,9 @@ constexpr int ct_threads_x_n(int n) { return n >= 512 ? n / 16 : (n >= 8 ? n / 8
 // are a tile parameter: default sixteen from length 2048 on, eight below.
 constexpr int ct_yept_default(int n) { return n >= 2048 ? 16 : 8; }
 constexpr int ct_threads_y_n(int n, int ept) { return n >= ept ? n / ept : 1; }
+// columns per tile of the persistent FP32 y kernel (32 elements per thread,
+// at most 512 threads)
+constexpr int pp_columns(int n) { return n >= 32 ? 512 / (n / 32) : 1; }
 
 // x-FFT LDS layout (shared by the kernels and the host's LDS sizes). For
 // transforms with radix-16 passes (16 elements per thread), a bank row (256
