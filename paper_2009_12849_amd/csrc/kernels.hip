@@ -348,19 +348,34 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 // neighbourhood (float data; pc: p1 of the row, pn/ps: rows j +- 1, pu/pd:
 // levels k +- 1, pe/pw: x-neighbours outside the vector, um: u west of the
 // vector; pu/pd, wc/wb ignored on the lid and bottom rows).
+// The same terms as div64_at - lap_at with the row's coefficients multiplied
+// out once (rho0/dx, rho0/dx^2, ...) and every pressure difference taken
+// before it is scaled: one FP64 fused multiply-add per term. The callers pass
+// wc = 0 and pu = pc on the lid row, wb = 0 and pd = pc on the bottom row,
+// where the row's rhow (lid) and rhowm (bottom) are 0 as well.
 __device__ __forceinline__ void resid_core(const MemberDesc& d, const RowCtx& c, f4v pc, f4v pn, f4v ps, f4v pu,
                                            f4v pd, float pw, float pe, f4v uc, float um, f4v vc, f4v vs, f4v wc,
                                            f4v wb, float* out) {
+  const double bx = c.rho0 * d.rdx, by = c.rho0 * d.rdy;      // D(u*) horizontal
+  const double wt = c.rdz * c.rhow, wm = c.rdz * c.rhowm;     // D(u*) vertical
+  const double ax = bx * d.rdx, ay = by * d.rdy;              // L p1 horizontal
+  const double cu = wt * c.rdzc, cd = wm * c.rdzcm;           // L p1 vertical
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const double uW = (e > 0) ? (double)uc[(e + 3) & 3] : (double)um;
-    const double hor = ((double)uc[e] - uW) * d.rdx + ((double)vc[e] - (double)vs[e]) * d.rdy;
-    const double ft = c.top ? c.rhow * (double)wc[e] : 0.0;
-    const double fb = c.bot ? c.rhowm * (double)wb[e] : 0.0;
-    const double b = c.rho0 * hor + (ft - fb) * c.rdz;
+    const double p0 = pc[e];
     const double pE = (e < 3) ? (double)pc[(e + 1) & 3] : (double)pe;
     const double pW = (e > 0) ? (double)pc[(e + 3) & 3] : (double)pw;
-    out[e] = (float)(b - lap_at(d, c, pc[e], pE, pW, pn[e], ps[e], pu[e], pd[e]));
+    const double dxx = (pE - p0) - (p0 - pW), dyy = ((double)pn[e] - p0) - (p0 - (double)ps[e]);
+    double r = bx * ((double)uc[e] - uW);
+    r = fma(by, (double)vc[e] - (double)vs[e], r);
+    r = fma(wt, (double)wc[e], r);
+    r = fma(-wm, (double)wb[e], r);
+    r = fma(-ax, dxx, r);
+    r = fma(-ay, dyy, r);
+    r = fma(-cu, (double)pu[e] - p0, r);
+    r = fma(cd, p0 - (double)pd[e], r);
+    out[e] = (float)r;
   }
 }
 
