@@ -550,10 +550,12 @@ def classify_kernel(name):
     import re
     if "k_probe_" in name:
         return ("probe", name.split("k_probe_", 1)[1].split("(", 1)[0].split("<", 1)[0])
-    m = re.search(r"k_(xfwd|ffty|xinv|tridiag|grad)(?:_ct|_gen)?<([^>]*)>", name)
+    m = re.search(r"k_(xfwd|ffty|xinv|tridiag|grad)(?:_ct|_gen|_pp)?<([^>]*)>", name)
     if not m:
         return None
     kind, args = m.group(1), [x.strip() for x in m.group(2).split(",")]
+    if kind == "ffty" and args[0] in ("true", "false"):  # the persistent FP32 y kernel <INV, N>
+        return ("mixed", "ffty_inv" if args[0] == "true" else "ffty_fwd")
     path = "fp64" if args[0] == "double" else "mixed"
     if kind == "xfwd":
         return (path, _MODES_X.get(args[1], "xfwd"))

@@ -15,6 +15,8 @@ import bench
     ("void monc::k_xfwd_gen<float, 0>(monc::LaunchArgs)", ("mixed", "div_fftx")),
     ("void monc::k_ffty_ct<double, true, 2048>(monc::LaunchArgs)", ("fp64", "ffty_inv")),
     ("void monc::k_ffty_ct<float, false, 1024>(monc::LaunchArgs)", ("mixed", "ffty_fwd")),
+    ("void monc::k_ffty_pp<true, 2048>(monc::LaunchArgs)", ("mixed", "ffty_inv")),
+    ("void monc::k_ffty_pp<false, 4096>(monc::LaunchArgs)", ("mixed", "ffty_fwd")),
     ("void monc::k_tridiag<float, 10, 256>(monc::LaunchArgs)", ("mixed", "tridiag")),
     ("void monc::k_xinv_ct<float, 1, 2048>(monc::LaunchArgs)", ("mixed", "ifftx_corr")),
     ("void monc::k_xinv_ct<float, 0, 2048>(monc::LaunchArgs)", ("mixed", "ifftx")),
