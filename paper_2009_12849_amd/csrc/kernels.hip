@@ -1558,16 +1558,17 @@ __global__ void __launch_bounds__(256) k_grad(LaunchArgs a) {
     blk = row * bpr + lb % bpr;
   }
   const long long g0 = (blk * blockDim.x + threadIdx.x) * VEC;  // first point
-  const bool live = g0 < nh * nz;
+  // a block inside one row: its row (level k, row j) and liveness follow from
+  // the block index, workgroup-uniform, so the divisions and the level's
+  // coefficient load run on the scalar unit
+  const int row = rowblk ? (int)(blk / bpr) : 0;
+  const bool live = rowblk ? row < ny * nz : g0 < nh * nz;
   if (!RED && !live) return;
   // with the reductions every thread reaches the workgroup reduction: one
   // past the grid reads point 0, stores nothing and contributes nothing
   const long long g = live ? g0 : 0;
   int k, j, i;
   if (rowblk) {
-    // the block's row (level k, row j) from its index: workgroup-uniform,
-    // so the divisions run on the scalar unit
-    const int row = (int)(blk / bpr);
     const int rw = live ? row : 0;
     k = rw / ny;
     j = rw - k * ny;
@@ -1608,11 +1609,9 @@ __global__ void __launch_bounds__(256) k_grad(LaunchArgs a) {
   const dv pc = ldp(g);
   const dv pn = ldp(hn);
   const double pel = ldp1(he);
-  // on the FP64 path p one level up is read unconditionally (clamped on the
-  // lid row) so that all loads issue together
-  dv pu;
-  if constexpr (sizeof(T) == 8) pu = ldp(top ? g : g + nh);
-  else pu = top ? pc : ldp(g + nh);
+  // p one level up is read unconditionally (clamped on the lid row, where w
+  // is set to 0 below) so that all loads issue together
+  const dv pu = ldp(top ? g : g + nh);
   // u, v, w are read and written once per point: nontemporal accesses (the
   // pressure fields, re-read as neighbours by other workgroups, keep the
   // normal cache policy)
