@@ -25,7 +25,7 @@ Prints one JSON line.
 
 Counter profiles (rocprofv3 --pmc, one pass per counter set):
   python bench.py --pmc-run [--workload NAME]      short run to profile
-  python bench.py --summarize-counters RD_CSV WR_CSV [--workload NAME]
+  python bench.py --summarize-counters RD_CSV WR_CSV [DRAM_CSV] [--workload NAME]
                                                    per-kernel HBM bytes
 """
 from __future__ import annotations
@@ -605,15 +605,19 @@ def kernel_launch_bytes(kernel, nx, points, mixed):
     return per * points
 
 
-def summarize_counters(rd_csv, wr_csv, workload, command):
+def summarize_counters(rd_csv, wr_csv, workload, command, dram_csv=None):
     """Per-kernel HBM traffic from two counter passes over `pmc_run`: read
     bytes from the L2's 32/64/128-byte read requests, write bytes from its
     64/32-byte write requests, each scaled by the factor that makes the
     calibration copy (CALIB_MIB MiB read, CALIB_MIB MiB written) exact. The
     median over a kernel's launches; all launches of a kernel have one shape
-    (no autotuning in the profiled run)."""
+    (no autotuning in the profiled run). With a third pass (dram_csv:
+    TCC_EA0_RDREQ_DRAM, TCC_EA0_WRREQ_DRAM, the requests addressed to local
+    memory), a cross-check: those request counts in bytes, each scaled by the
+    bytes per request of the calibration copy."""
     import synth
     rd, wr = _read_counter_csv(rd_csv), _read_counter_csv(wr_csv)
+    dr = _read_counter_csv(dram_csv) if dram_csv else None
     known = CALIB_MIB * float(1 << 20)
 
     def collect(table, fn):
@@ -661,6 +665,24 @@ def summarize_counters(rd_csv, wr_csv, workload, command):
         lines.append(f"{path}.{kern}.write_bytes_per_launch: {ww:.0f}")
         lines.append(f"{path}.{kern}.bytes_per_launch: {rr + ww:.0f}   # algorithmic {alg:.0f}, "
                      f"ratio {(rr + ww) / alg:.3f}, launches {len(r_all[key])}")
+    if dr is not None:
+        def cnt(name):
+            return lambda c: float(c.get(name, 0.0))
+        dr_r = collect(dr, cnt("TCC_EA0_RDREQ_DRAM_sum"))
+        dr_w = collect(dr, cnt("TCC_EA0_WRREQ_DRAM_sum"))
+        cr, cw = dr_r.get(("probe", "copy"), []), dr_w.get(("probe", "copy"), [])
+        if cr and cw and np.median(cr) > 0 and np.median(cw) > 0:
+            br, bw = known / float(np.median(cr)), known / float(np.median(cw))
+            lines.append("# cross-check: TCC_EA0_RDREQ_DRAM / TCC_EA0_WRREQ_DRAM (requests addressed to local "
+                         "memory) in bytes,")
+            lines.append(f"#   at the calibration copy's {br:.1f} read and {bw:.1f} written bytes per request")
+            for key in sorted(k for k in dr_r if k[0] != "probe"):
+                path, kern = key
+                rr = float(np.median(dr_r[key])) * br
+                ww = float(np.median(dr_w.get(key, [0.0]))) * bw
+                alg = kernel_launch_bytes(kern, g.nx, g.points, path == "mixed")
+                lines.append(f"dram.{path}.{kern}.bytes_per_launch: {rr + ww:.0f}   # read {rr:.0f}, "
+                             f"write {ww:.0f}, ratio to algorithmic {(rr + ww) / alg:.3f}")
     return "\n".join(lines) + "\n"
 
 
@@ -721,7 +743,7 @@ def main():
     ap.add_argument("--retune", action="store_true", help="autotune every grid, ignoring the tuning cache")
     ap.add_argument("--no-var", action="store_true", help="skip the variable-density solve")
     ap.add_argument("--pmc-run", action="store_true", help="the short run that the counter passes profile")
-    ap.add_argument("--summarize-counters", nargs=2, metavar=("RD_CSV", "WR_CSV"),
+    ap.add_argument("--summarize-counters", nargs="+", metavar="CSV",
                     help="print the per-kernel traffic summary of two counter passes over --pmc-run")
     ap.add_argument("--summarize-trace", nargs="+", metavar=("STATS_CSV", "BENCH_LOG"),
                     help="print the per-kernel summary of a rocprofv3 --kernel-trace --stats run")
@@ -732,7 +754,11 @@ def main():
               "MI355X (sharding across GPUs is described, not built). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     if args.summarize_counters:
-        sys.stdout.write(summarize_counters(*args.summarize_counters, args.workload, args.command))
+        sc = args.summarize_counters
+        if len(sc) not in (2, 3):
+            ap.error("--summarize-counters takes RD_CSV WR_CSV [DRAM_CSV]")
+        sys.stdout.write(summarize_counters(sc[0], sc[1], args.workload, args.command,
+                                            sc[2] if len(sc) == 3 else None))
         return
     if args.summarize_trace:
         sys.stdout.write(summarize_trace(args.summarize_trace[0], args.workload, args.command,

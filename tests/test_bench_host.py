@@ -71,3 +71,28 @@ def test_summary_calibrates_on_the_probe_copy(tmp_path):
     assert np.isclose(float(vals["mixed.grad_final.read_bytes_per_launch"]), 2 * A, rtol=1e-6)
     assert np.isclose(float(vals["mixed.grad_final.bytes_per_launch"]), 3 * A, rtol=1e-6)
     assert vals["kernels_sha256_16"] == bench.kernel_source_hash()
+
+
+def test_summary_dram_cross_check(tmp_path):
+    # third pass: requests addressed to local memory, scaled by the copy's
+    # bytes per request (64 here); the gradient's come to 2 A read, A written
+    known = bench.CALIB_MIB * (1 << 20)
+    copy = "(anonymous namespace)::k_probe_copy(float vector[4] const*, float vector[4]*, long long)"
+    grad = "void monc::k_grad<float, 4, false>(monc::LaunchArgs)"
+    A = 1 << 30
+    rd = [dict(Dispatch_Id=1, Kernel_Name=copy, Counter_Name="TCC_EA0_RDREQ_128B_sum", Counter_Value=known / 128),
+          dict(Dispatch_Id=2, Kernel_Name=grad, Counter_Name="TCC_EA0_RDREQ_128B_sum", Counter_Value=2 * A / 128)]
+    wr = [dict(Dispatch_Id=1, Kernel_Name=copy, Counter_Name="TCC_EA0_WRREQ_sum", Counter_Value=known / 64),
+          dict(Dispatch_Id=1, Kernel_Name=copy, Counter_Name="TCC_EA0_WRREQ_64B_sum", Counter_Value=known / 64),
+          dict(Dispatch_Id=2, Kernel_Name=grad, Counter_Name="TCC_EA0_WRREQ_sum", Counter_Value=A / 64),
+          dict(Dispatch_Id=2, Kernel_Name=grad, Counter_Name="TCC_EA0_WRREQ_64B_sum", Counter_Value=A / 64)]
+    dr = [dict(Dispatch_Id=1, Kernel_Name=copy, Counter_Name="TCC_EA0_RDREQ_DRAM_sum", Counter_Value=known / 64),
+          dict(Dispatch_Id=1, Kernel_Name=copy, Counter_Name="TCC_EA0_WRREQ_DRAM_sum", Counter_Value=known / 64),
+          dict(Dispatch_Id=2, Kernel_Name=grad, Counter_Name="TCC_EA0_RDREQ_DRAM_sum", Counter_Value=2 * A / 64),
+          dict(Dispatch_Id=2, Kernel_Name=grad, Counter_Name="TCC_EA0_WRREQ_DRAM_sum", Counter_Value=A / 64)]
+    for name, rows in (("rd", rd), ("wr", wr), ("dr", dr)):
+        _write_csv(tmp_path / f"{name}.csv", rows)
+    text = bench.summarize_counters(str(tmp_path / "rd.csv"), str(tmp_path / "wr.csv"), "256x256x128", "cmd",
+                                    str(tmp_path / "dr.csv"))
+    line = [ln for ln in text.splitlines() if ln.startswith("dram.mixed.grad_final.bytes_per_launch")][0]
+    assert np.isclose(float(line.split(":", 1)[1].split("#", 1)[0]), 3 * A, rtol=1e-6)
