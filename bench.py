@@ -208,7 +208,7 @@ class Runner:
             for pl in self.plans:
                 self.tuned.setdefault((pl.nx, pl.ny, pl.nz), pl.params)
                 self.tuning.setdefault((pl.nx, pl.ny, pl.nz), "cache")
-            self.schedule = dict(zip(("order", "budget_mb", "groups"), monc.batch_schedule(self.plans)))
+            self.schedule = dict(zip(("order", "budget_mb", "groups", "branches"), monc.batch_schedule(self.plans)))
         else:
             for pl in self.plans:
                 key = (pl.nx, pl.ny, pl.nz)

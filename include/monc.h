@@ -68,6 +68,8 @@ enum {
 #define MONC_MAX_N 8192
 #define MONC_MAX_NZ 1024
 #define MONC_MAX_BATCH 256
+/* Most independent graph branches a batch schedule deals its groups to. */
+#define MONC_MAX_BRANCHES 4
 
 /*
  * Create a plan on the current HIP device.
@@ -280,10 +282,11 @@ int monc_profile_read(monc_plan* plan, double* ms, int* launches);
  * grid's first plan, one parameter after the
  * other, and copied to its other plans. For count > 1 the batch schedule
  * of monc_project_batched over these plans is then tuned as a whole: each
- * member order (largest or smallest first) and grouping (all members per
- * phase, or groups of at most 1024, 512, 256, 128 or 64 MB of working set
- * run one after the other) is captured and its graph replayed on scratch
- * fields.
+ * member order (largest or smallest first), grouping (all members per
+ * phase, or groups of at most 1024, 512, 256, 128 or 64 MB of working set,
+ * each running its whole phase sequence) and number of graph branches the
+ * groups are dealt to (1, 2 or 4) is captured and its graph replayed on
+ * scratch fields.
  * Results are stored in the plans / the schedule table and in the JSON cache
  * named by the MONC_TUNE_CACHE environment variable (if set), which plans and
  * batches of the same grids read back. Allocates scratch fields, synchronises
@@ -294,11 +297,15 @@ int monc_autotune(monc_plan* const* plans, int count, void* stream);
 /* The batch schedule monc_project_batched uses for these plans (tuned, read
  * from the cache, or the default): out[0] = member order (0 largest first,
  * 1 smallest first), out[1] = working-set budget per group in MB (0 = one
- * group, every phase over all members), out[2] = number of groups. */
+ * group, every phase over all members), out[2] = number of groups, out[3] =
+ * graph branches (1..MONC_MAX_BRANCHES): with a budget, group g runs on
+ * branch g mod branches, and the branches are independent chains of the
+ * captured graph that the device runs concurrently. out holds 4 ints. */
 int monc_batch_schedule(monc_plan* const* plans, int count, int* out);
-/* Set that schedule by hand (order 0 or 1, budget_mb >= 0); the next
+/* Set that schedule by hand (order 0 or 1, budget_mb >= 0, branches in
+ * [1, MONC_MAX_BRANCHES]; branches only matter with budget_mb > 0); the next
  * monc_project_batched call over these plans captures it. */
-int monc_batch_set_schedule(monc_plan* const* plans, int count, int order, int budget_mb);
+int monc_batch_set_schedule(monc_plan* const* plans, int count, int order, int budget_mb, int branches);
 
 /* Streaming-bandwidth probes: one launch of the plainest kernel that moves
  * a known number of bytes, to measure the bandwidth a streaming kernel

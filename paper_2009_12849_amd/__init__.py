@@ -82,7 +82,7 @@ def lib() -> ctypes.CDLL:
     L.monc_batch_schedule.restype = ip
     L.monc_batch_schedule.argtypes = [ctypes.POINTER(vp), ip, ctypes.POINTER(ip)]
     L.monc_batch_set_schedule.restype = ip
-    L.monc_batch_set_schedule.argtypes = [ctypes.POINTER(vp), ip, ip, ip]
+    L.monc_batch_set_schedule.argtypes = [ctypes.POINTER(vp), ip, ip, ip, ip]
     L.monc_plan_params.restype = ip
     L.monc_plan_params.argtypes = [vp, ctypes.POINTER(ip)]
     L.monc_plan_set_params.restype = ip
@@ -289,17 +289,17 @@ def autotune_batched(plans: Sequence[Plan], stream=None):
 
 
 def batch_schedule(plans: Sequence[Plan]):
-    """(order, budget_mb, groups) of the batch schedule of these plans."""
+    """(order, budget_mb, groups, branches) of the batch schedule of these plans."""
     arr = (ctypes.c_void_p * len(plans))(*[pl.handle for pl in plans])
-    out = (ctypes.c_int * 3)()
+    out = (ctypes.c_int * 4)()
     _check(lib().monc_batch_schedule(arr, len(plans), out))
     return tuple(out)
 
 
-def set_batch_schedule(plans: Sequence[Plan], order: int, budget_mb: int):
+def set_batch_schedule(plans: Sequence[Plan], order: int, budget_mb: int, branches: int = 1):
     """Set the batch schedule of these plans by hand (monc_batch_set_schedule)."""
     arr = (ctypes.c_void_p * len(plans))(*[pl.handle for pl in plans])
-    _check(lib().monc_batch_set_schedule(arr, len(plans), int(order), int(budget_mb)))
+    _check(lib().monc_batch_set_schedule(arr, len(plans), int(order), int(budget_mb), int(branches)))
 
 
 PROBES = {"read": 0, "write": 1, "copy": 2, "update": 3}

@@ -1227,6 +1227,7 @@ static void drop_batch_cache_for(unsigned long long plan_id) {
 struct BatchSchedule {
   int order = 0;
   int budget_mb = 0;
+  int branches = 1;  // independent graph branches the groups are dealt to
 };
 
 static std::mutex g_sched_mu;
@@ -1266,9 +1267,13 @@ static BatchSchedule lookup_schedule(monc_plan* const* plans, int count) {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     auto m = read_cache(path);
     auto it = m.find(key);
-    if (it != m.end() && it->second.size() == 2 && (it->second[0] == 0 || it->second[0] == 1) && it->second[1] >= 0) {
+    // [order, budget_mb] or [order, budget_mb, branches]
+    if (it != m.end() && (it->second.size() == 2 || it->second.size() == 3) &&
+        (it->second[0] == 0 || it->second[0] == 1) && it->second[1] >= 0 &&
+        (it->second.size() == 2 || (it->second[2] >= 1 && it->second[2] <= MONC_MAX_BRANCHES))) {
       sc.order = it->second[0];
       sc.budget_mb = it->second[1];
+      sc.branches = it->second.size() == 3 ? it->second[2] : 1;
     }
   }
   std::lock_guard<std::mutex> lk(g_sched_mu);
@@ -1318,14 +1323,55 @@ static void build_groups(monc_plan* const* plans, int count, void* const* u, voi
 
 // Every phase over all groups (phase-major), or all phases of each group in
 // turn (group-major, the grouped schedules).
+// Group-major batches: every group runs its whole phase sequence before the
+// next. With side streams (a capture in progress on `stream`), group g goes
+// to branch g mod (1 + side.size()): the captured graph then holds that many
+// independent chains, which the device runs concurrently (the transform and
+// tridiagonal kernels are latency-bound at the occupancy their LDS allows,
+// so a second chain fills what one leaves idle).
 static int run_batch(const std::vector<Group>& groups, const std::vector<Phase>& seq, bool group_major,
-                     void* stream, Profiler* prof) {
+                     void* stream, Profiler* prof, const std::vector<hipStream_t>& side = {}) {
   if (!group_major) return run_phases(groups, seq, stream, prof);
-  for (const auto& g : groups)
-    for (Phase ph : seq) {
-      const int rc = launch_phase(g, ph, stream, prof);
-      if (rc != MONC_OK) return rc;
+  const size_t nb = 1 + std::min(side.size(), groups.size() ? groups.size() - 1 : 0);
+  std::vector<hipEvent_t> ev;
+  auto cleanup = [&]() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  };
+  if (nb > 1) {  // fork: the side streams start after what the main one holds
+    hipEvent_t fork = nullptr;
+    if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess)
+      return fail(MONC_EHIP, "batch: event creation failed");
+    ev.push_back(fork);
+    bool ok = hipEventRecord(fork, (hipStream_t)stream) == hipSuccess;
+    for (size_t b = 1; b < nb && ok; ++b) ok = hipStreamWaitEvent(side[b - 1], fork, 0) == hipSuccess;
+    if (!ok) {
+      cleanup();
+      return fail(MONC_EHIP, "batch: fork of the graph branches failed");
     }
+  }
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    void* st = (gi % nb) ? (void*)side[gi % nb - 1] : stream;
+    for (Phase ph : seq) {
+      const int rc = launch_phase(groups[gi], ph, st, prof);
+      if (rc != MONC_OK) {
+        cleanup();
+        return rc;
+      }
+    }
+  }
+  for (size_t b = 1; b < nb; ++b) {  // join
+    hipEvent_t join = nullptr;
+    if (hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) {
+      cleanup();
+      return fail(MONC_EHIP, "batch: event creation failed");
+    }
+    ev.push_back(join);
+    if (hipEventRecord(join, side[b - 1]) != hipSuccess || hipStreamWaitEvent((hipStream_t)stream, join, 0) != hipSuccess) {
+      cleanup();
+      return fail(MONC_EHIP, "batch: join of the graph branches failed");
+    }
+  }
+  cleanup();
   return MONC_OK;
 }
 
@@ -1367,6 +1413,7 @@ extern "C" int monc_project_batched(monc_plan* const* plans, int count, void* co
   key.reserve(6 * count + 2);
   key.push_back((unsigned long long)sc.order);
   key.push_back((unsigned long long)sc.budget_mb);
+  key.push_back((unsigned long long)sc.branches);
   for (int i = 0; i < count; ++i) {
     key.push_back(plans[i]->id);
     key.push_back(plans[i]->version);
@@ -1412,10 +1459,19 @@ extern "C" int monc_project_batched(monc_plan* const* plans, int count, void* co
       (void)hipStreamDestroy(cs);
       return fail(MONC_EHIP, "hipStreamBeginCapture failed: %s", hipGetErrorString(e));
     }
-    rc = run_batch(groups, seq, group_major, cs, nullptr);
+    // side streams of the capture: forked from cs and joined back into it,
+    // so they record into the same graph
+    std::vector<hipStream_t> side;
+    for (int b = 1; b < sc.branches && rc == MONC_OK; ++b) {
+      hipStream_t s2 = nullptr;
+      if (hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess) rc = fail(MONC_EHIP, "batch: stream creation failed");
+      else side.push_back(s2);
+    }
+    if (rc == MONC_OK) rc = run_batch(groups, seq, group_major, cs, nullptr, side);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(cs, &graph);
     (void)hipStreamDestroy(cs);
+    for (hipStream_t s2 : side) (void)hipStreamDestroy(s2);
     if (rc != MONC_OK) {
       if (graph) (void)hipGraphDestroy(graph);
       return rc;
@@ -1448,17 +1504,23 @@ extern "C" int monc_batch_schedule(monc_plan* const* plans, int count, int* out)
   out[0] = sc.order;
   out[1] = sc.budget_mb;
   out[2] = ngroups;
+  out[3] = sc.branches;
   return MONC_OK;
 }
 
-extern "C" int monc_batch_set_schedule(monc_plan* const* plans, int count, int order, int budget_mb) {
+extern "C" int monc_batch_set_schedule(monc_plan* const* plans, int count, int order, int budget_mb,
+                                       int branches) {
   int rc = check_batch(plans, count, "monc_batch_set_schedule");
   if (rc != MONC_OK) return rc;
   if (order != 0 && order != 1) return fail(MONC_EINVAL, "monc_batch_set_schedule: order must be 0 or 1 (got %d)", order);
   if (budget_mb < 0) return fail(MONC_EINVAL, "monc_batch_set_schedule: budget_mb must be >= 0 (got %d)", budget_mb);
+  if (branches < 1 || branches > MONC_MAX_BRANCHES)
+    return fail(MONC_EINVAL, "monc_batch_set_schedule: branches must be in [1, %d] (got %d)", MONC_MAX_BRANCHES,
+                branches);
   BatchSchedule sc;
   sc.order = order;
   sc.budget_mb = budget_mb;
+  sc.branches = branches;
   std::lock_guard<std::mutex> lk(g_sched_mu);
   g_sched[batch_key(plans, count)] = sc;
   return MONC_OK;
@@ -1669,13 +1731,17 @@ static int tune_schedule(monc_plan* const* plans, int count, void* stream) {
   size_t total = 0;
   for (int i = 0; i < count; ++i) total += member_bytes(plans[i]);
   const int budgets[] = {0, 1024, 512, 256, 128, 64};
+  const int branch_counts[] = {1, 2, 4};
   BatchSchedule best;
   double best_ms = 1e300;
   int rc = MONC_OK;
   for (int order = 0; order < 2 && rc == MONC_OK; ++order)
-    for (int budget : budgets) {
+    for (int budget : budgets)
+      for (int branches : branch_counts) {
       if (budget && ((size_t)budget << 20) >= total) continue;  // one group anyway
-      rc = monc_batch_set_schedule(plans, count, order, budget);
+      if (branches > 1 && !budget) continue;                     // one group: one chain
+      if (branches > 1 && ((size_t)budget << 20) * (size_t)(branches - 1) >= total) continue;  // fewer groups than branches
+      rc = monc_batch_set_schedule(plans, count, order, budget, branches);
       if (rc != MONC_OK) break;
       for (int r = 0; r < 2 && rc == MONC_OK; ++r)  // capture, then one warm replay
         rc = monc_project_batched(plans, count, f[0].data(), f[1].data(), f[2].data(), f[3].data(), stream);
@@ -1692,8 +1758,9 @@ static int tune_schedule(monc_plan* const* plans, int count, void* stream) {
         best_ms = ms;
         best.order = order;
         best.budget_mb = budget;
+        best.branches = branches;
       }
-    }
+      }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   // the candidates' graphs hold the scratch pointers: drop them with the fields
@@ -1701,12 +1768,12 @@ static int tune_schedule(monc_plan* const* plans, int count, void* stream) {
   for (int i = 0; i < count; ++i) drop_batch_cache_for(plans[i]->id);
   release();
   if (rc != MONC_OK) return rc;
-  rc = monc_batch_set_schedule(plans, count, best.order, best.budget_mb);
+  rc = monc_batch_set_schedule(plans, count, best.order, best.budget_mb, best.branches);
   if (rc != MONC_OK) return rc;
   if (const char* path = std::getenv("MONC_TUNE_CACHE")) {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     auto m = read_cache(path);
-    m[batch_key(plans, count)] = {best.order, best.budget_mb};
+    m[batch_key(plans, count)] = {best.order, best.budget_mb, best.branches};
     write_cache(path, m);
   }
   return MONC_OK;

@@ -116,8 +116,8 @@ def test_batch_schedule_argument_checks_run_before_the_device():
     L = monc.lib()
     VP = ctypes.c_void_p * 1
     z = VP(None)
-    out = (ctypes.c_int * 3)()
+    out = (ctypes.c_int * 4)()
     assert L.monc_batch_schedule(z, 0, out) == monc.EINVAL
-    assert L.monc_batch_set_schedule(z, 1, 0, 0) == monc.EINVAL
+    assert L.monc_batch_set_schedule(z, 1, 0, 0, 1) == monc.EINVAL
     assert L.monc_autotune(z, 0, None) == monc.EINVAL
     assert "count" in monc.last_error()

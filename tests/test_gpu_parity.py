@@ -327,28 +327,28 @@ def test_batched_equals_members_and_oracle(dtype):
 
 @pytest.mark.parametrize("dtype", ["f64", "mixed"])
 def test_batch_schedules_equal_member_projections(dtype):
-    # every member order and grouping (one group; groups of about 1 MB, i.e.
-    # one or two members each; 8 MB) gives each member its single projection
-    # bit for bit
+    # every member order, grouping (one group; groups of about 1 MB, i.e.
+    # one or two members each; 8 MB) and number of graph branches the groups
+    # run on gives each member its single projection bit for bit
     mem = _ensemble(7, [(32, 32, 16), (48, 48, 24), (64, 32, 20), (24, 36, 12), (96, 96, 9)], 41)
     plans = [monc.Plan.from_grid(g, dtype) for g, *_ in mem]
     tdt = plans[0].torch_dtype
     cast = np.float64 if dtype == "f64" else np.float32
     singles = [run_gpu(g, u.astype(cast), v.astype(cast), w.astype(cast), dtype) for g, u, v, w in mem]
-    for order in (0, 1):
-        for budget in (0, 1, 8):
-            monc.set_batch_schedule(plans, order, budget)
-            o, b, ngroups = monc.batch_schedule(plans)
-            assert (o, b) == (order, budget)
-            assert (ngroups == 1) if budget == 0 else (ngroups > 1), ngroups
-            fields = [[to_dev(a.astype(cast), tdt) for a in (u, v, w)] for _, u, v, w in mem]
-            ps = [torch.empty_like(f[0]) for f in fields]
-            monc.project_batched(plans, [f[0] for f in fields], [f[1] for f in fields], [f[2] for f in fields], ps)
-            torch.cuda.synchronize()
-            for i in range(len(mem)):
-                got = [t.cpu().numpy().astype(np.float64) for t in fields[i] + [ps[i]]]
-                for a, ref in zip(got, singles[i]):
-                    assert np.array_equal(a, ref), (order, budget, i)
+    for order, budget, branches in [(0, 0, 1), (0, 1, 1), (0, 8, 1), (1, 0, 1), (1, 1, 1), (1, 8, 1),
+                                    (0, 1, 2), (1, 1, 4), (0, 8, 2)]:
+        monc.set_batch_schedule(plans, order, budget, branches)
+        o, b, ngroups, nb = monc.batch_schedule(plans)
+        assert (o, b, nb) == (order, budget, branches)
+        assert (ngroups == 1) if budget == 0 else (ngroups > 1), ngroups
+        fields = [[to_dev(a.astype(cast), tdt) for a in (u, v, w)] for _, u, v, w in mem]
+        ps = [torch.empty_like(f[0]) for f in fields]
+        monc.project_batched(plans, [f[0] for f in fields], [f[1] for f in fields], [f[2] for f in fields], ps)
+        torch.cuda.synchronize()
+        for i in range(len(mem)):
+            got = [t.cpu().numpy().astype(np.float64) for t in fields[i] + [ps[i]]]
+            for a, ref in zip(got, singles[i]):
+                assert np.array_equal(a, ref), (order, budget, branches, i)
 
 
 def test_batch_autotune_picks_a_schedule_and_caches_it(tmp_path, monkeypatch):
@@ -358,10 +358,10 @@ def test_batch_autotune_picks_a_schedule_and_caches_it(tmp_path, monkeypatch):
     mem = _ensemble(6, [(32, 32, 16), (64, 64, 24), (48, 24, 12)], 42)
     plans = [monc.Plan.from_grid(g, "mixed") for g, *_ in mem]
     monc.autotune_batched(plans)
-    order, budget, ngroups = monc.batch_schedule(plans)
+    order, budget, ngroups, branches = monc.batch_schedule(plans)
     data = json.loads(cache.read_text())
     keys = [k for k in data if k.startswith("gfx950:batch:6:") and k.endswith(":mixed")]
-    assert len(keys) == 1 and data[keys[0]] == [order, budget], data
+    assert len(keys) == 1 and data[keys[0]] == [order, budget, branches], data
     # plans of the same grid share the tuned tile parameters
     for i in range(len(mem)):
         for j in range(i):
@@ -369,7 +369,7 @@ def test_batch_autotune_picks_a_schedule_and_caches_it(tmp_path, monkeypatch):
                 assert plans[i].params == plans[j].params
     # a fresh set of plans of the same grids reads the schedule back
     plans2 = [monc.Plan.from_grid(g, "mixed") for g, *_ in mem]
-    assert monc.batch_schedule(plans2)[:2] == (order, budget)
+    assert monc.batch_schedule(plans2)[:2] == (order, budget) and monc.batch_schedule(plans2)[3] == branches
     fields = [[to_dev(a.astype(np.float32), torch.float32) for a in (u, v, w)] for _, u, v, w in mem]
     ps = [torch.empty_like(f[0]) for f in fields]
     monc.project_batched(plans2, [f[0] for f in fields], [f[1] for f in fields], [f[2] for f in fields], ps)
