@@ -680,8 +680,8 @@ static int launch_one(const Group& g, const std::vector<int>& idx, Phase ph, con
   if (lds > 160 * 1024) return fail(MONC_EUNSUPPORTED, "phase needs %zu bytes of LDS", lds);
   if (blocks == 0) return MONC_OK;
   // a persistent kernel takes one workgroup per CU slot its LDS leaves
-  const int grid = sh.persistent ? (int)std::min<long long>(blocks, (long long)cu_count() * std::max<size_t>(1, (160 * 1024) / lds))
-                                 : (int)blocks;
+  const long long slots = (long long)cu_count() * (long long)std::max<size_t>(1, (160 * 1024) / std::max<size_t>(lds, 1));
+  const int grid = sh.persistent ? (int)std::min(blocks, slots) : (int)blocks;
   const int kid = phase_kernel_id(ph);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const bool timed = prof && (prof->mask >> kid & 1u);
@@ -1322,13 +1322,11 @@ static void build_groups(monc_plan* const* plans, int count, void* const* u, voi
 }
 
 // Every phase over all groups (phase-major), or all phases of each group in
-// turn (group-major, the grouped schedules).
-// Group-major batches: every group runs its whole phase sequence before the
-// next. With side streams (a capture in progress on `stream`), group g goes
-// to branch g mod (1 + side.size()): the captured graph then holds that many
-// independent chains, which the device runs concurrently (the transform and
-// tridiagonal kernels are latency-bound at the occupancy their LDS allows,
-// so a second chain fills what one leaves idle).
+// turn (group-major, the grouped schedules). With side streams (a capture in
+// progress on `stream`), group-major group g goes to branch
+// g mod (1 + side.size()): the captured graph then holds that many
+// independent chains, which the device runs concurrently, so that one
+// chain's small launches fill the tails and gaps another leaves.
 static int run_batch(const std::vector<Group>& groups, const std::vector<Phase>& seq, bool group_major,
                      void* stream, Profiler* prof, const std::vector<hipStream_t>& side = {}) {
   if (!group_major) return run_phases(groups, seq, stream, prof);
@@ -1738,28 +1736,29 @@ static int tune_schedule(monc_plan* const* plans, int count, void* stream) {
   for (int order = 0; order < 2 && rc == MONC_OK; ++order)
     for (int budget : budgets)
       for (int branches : branch_counts) {
-      if (budget && ((size_t)budget << 20) >= total) continue;  // one group anyway
-      if (branches > 1 && !budget) continue;                     // one group: one chain
-      if (branches > 1 && ((size_t)budget << 20) * (size_t)(branches - 1) >= total) continue;  // fewer groups than branches
-      rc = monc_batch_set_schedule(plans, count, order, budget, branches);
-      if (rc != MONC_OK) break;
-      for (int r = 0; r < 2 && rc == MONC_OK; ++r)  // capture, then one warm replay
-        rc = monc_project_batched(plans, count, f[0].data(), f[1].data(), f[2].data(), f[3].data(), stream);
-      if (rc != MONC_OK) break;
-      const int reps = 5;
-      (void)hipEventRecord(e0, st);
-      for (int r = 0; r < reps && rc == MONC_OK; ++r)
-        rc = monc_project_batched(plans, count, f[0].data(), f[1].data(), f[2].data(), f[3].data(), stream);
-      (void)hipEventRecord(e1, st);
-      float ms = 0.0f;
-      if (rc == MONC_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-        rc = fail(MONC_EHIP, "autotune: event timing failed");
-      if (rc == MONC_OK && ms < best_ms) {
-        best_ms = ms;
-        best.order = order;
-        best.budget_mb = budget;
-        best.branches = branches;
-      }
+        if (rc != MONC_OK) break;
+        if (budget && ((size_t)budget << 20) >= total) continue;  // one group anyway
+        if (branches > 1 && !budget) continue;                     // one group: one chain
+        if (branches > 1 && ((size_t)budget << 20) * (size_t)(branches - 1) >= total)
+          continue;  // fewer groups than branches
+        rc = monc_batch_set_schedule(plans, count, order, budget, branches);
+        for (int r = 0; r < 2 && rc == MONC_OK; ++r)  // capture, then one warm replay
+          rc = monc_project_batched(plans, count, f[0].data(), f[1].data(), f[2].data(), f[3].data(), stream);
+        if (rc != MONC_OK) break;
+        const int reps = 5;
+        (void)hipEventRecord(e0, st);
+        for (int r = 0; r < reps && rc == MONC_OK; ++r)
+          rc = monc_project_batched(plans, count, f[0].data(), f[1].data(), f[2].data(), f[3].data(), stream);
+        (void)hipEventRecord(e1, st);
+        float ms = 0.0f;
+        if (rc == MONC_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+          rc = fail(MONC_EHIP, "autotune: event timing failed");
+        if (rc == MONC_OK && ms < best_ms) {
+          best_ms = ms;
+          best.order = order;
+          best.budget_mb = budget;
+          best.branches = branches;
+        }
       }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

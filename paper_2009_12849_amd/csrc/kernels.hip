@@ -743,7 +743,6 @@ __global__ void __launch_bounds__(1024) k_ffty_ct(LaunchArgs a) {
 // tile's loads (a workgroup holds a CU's LDS alone, so nothing else would
 // cover them). Twiddles come from an LDS copy of the table: a global load
 // issued during the transform would wait behind the prefetched tile.
-// Columns past nxh load column 0 and are transformed but never stored.
 template <bool INV, int N>
 __global__ void __launch_bounds__(512) k_ffty_pp(LaunchArgs a) {
   using T = float;
