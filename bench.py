@@ -385,16 +385,15 @@ def max_errors(out, ref, members_in):
 def var_iteration_bytes_per_point(nx, mixed):
     """Algorithmic HBM bytes per grid point of one conjugate-gradient
     iteration of the variable-density projection: the operator (read d and
-    rho, write q), the update (read p, d, r, q and the FP32 scaling s; write
-    p, r), the spectral preconditioner (read r, the spectrum's four round
-    trips, write z in the plan's storage type), the inner products (read r
-    and z; with the FP32 preconditioner's flexible update also q and s) and
-    the direction update (read z, d, s; write d). FP64 136 + 64f, mixed
-    136 + 32f."""
+    rho, write q), the update (read p, d, r, q; write p, r), the spectral
+    preconditioner (read r, the spectrum's four round trips, write z in the
+    plan's storage type), the inner products (read r and z; with the FP32
+    preconditioner's flexible update also q) and the direction update (read
+    z, d; write d). FP64 128 + 64f, mixed 124 + 32f."""
     f = spectral_words(nx)
     wb = 4.0 if mixed else 8.0
-    dots = (8 + wb + 8 + 4) if mixed else (8 + wb)
-    return 24 + (48 + 4) + (8 + 8 * f * wb + wb) + dots + (16 + wb + 4)
+    dots = (8 + wb + 8) if mixed else (8 + wb)
+    return 24 + 48 + (8 + 8 * f * wb + wb) + dots + (16 + wb)
 
 
 def variable_density(monc, torch, member, reps=3, tol=1e-10, amp=0.2, strong=0.5):

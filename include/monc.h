@@ -188,7 +188,7 @@ int monc_project_reduce(monc_plan* plan, void* u, void* v, void* w, void* p, dou
  * the residual r = D_rho(u*) - D_rho(G p)); maxit in [1, 10000]: the most
  * iterations. *iters and *relres (either may be NULL) receive the iterations
  * taken and the final ||r||/||D_rho(u*)||; reaching maxit is not an error,
- * the caller compares *relres with tol. Work vectors (five fields) are
+ * the caller compares *relres with tol. Work vectors (four fields) are
  * allocated on the plan by the first call and freed with it.
  * Unlike the other entry points this one synchronises the stream: the
  * residual-norm reduction decides convergence on the device (later kernels

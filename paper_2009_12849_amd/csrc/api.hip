@@ -903,7 +903,6 @@ static constexpr int kVarMaxIt = 10000;
 // the preconditioner's device descriptor and its scaling field s (FP32).
 struct VarWs {
   double *r, *d, *q, *part0, *part1, *scal, *za, *zb;
-  float* s;
   void* z;
   MemberDesc* desc;
 };
@@ -913,10 +912,10 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 static int var_workspace(monc_plan* pl, VarWs* ws) {
   const size_t n = (size_t)pl->nx * pl->ny * pl->nz;
   const size_t nparts = (size_t)var_point_parts(pl->nx, pl->ny, pl->nz);  // the larger count
-  constexpr int kParts = 11;
+  constexpr int kParts = 10;
   const size_t sizes[kParts] = {n * 8, n * 8, n * 8, n * elem_bytes(pl->dtype), nparts * 8, nparts * 8,
                                 (size_t)(kVarMaxIt + 2) * kVarSlots * 8, (size_t)pl->nz * 8, (size_t)pl->nz * 8,
-                                sizeof(MemberDesc), n * 4};
+                                sizeof(MemberDesc)};
   size_t off[kParts], total = 0;
   for (int i = 0; i < kParts; ++i) {
     off[i] = total;
@@ -949,7 +948,6 @@ static int var_workspace(monc_plan* pl, VarWs* ws) {
   ws->za = reinterpret_cast<double*>(b + off[7]);
   ws->zb = reinterpret_cast<double*>(b + off[8]);
   ws->desc = reinterpret_cast<MemberDesc*>(b + off[9]);
-  ws->s = reinterpret_cast<float*>(b + off[10]);
   return MONC_OK;
 }
 
@@ -1007,8 +1005,6 @@ extern "C" int monc_project_var(monc_plan* pl, const double* rho, double* u, dou
   g.rdzc = h.rdzc;
   g.za = ws.za;
   g.zb = ws.zb;
-  g.rho0 = h.rho0;
-  g.s = ws.s;
   const long long np_st = var_stencil_parts(pl->nx, pl->ny, pl->nz);  // partials of the stencil kernels
   const long long np_pt = var_point_parts(pl->nx, pl->ny, pl->nz);    // partials of the pointwise kernels
   const bool z64 = pl->dtype == MONC_FP64;

@@ -46,11 +46,6 @@ struct VarGrid {
   const double* rdzc;       // [nz] 1/dzc_k (0 at nz-1)
   const double* za;         // [nz] dz_{k+1}/(dz_k + dz_{k+1}) (0 at nz-1)
   const double* zb;         // [nz] dz_k/(dz_k + dz_{k+1}) (0 at nz-1)
-  const double* rho0;       // [nz] the preconditioner's (the plan's) density
-  // (nz, ny, nx) preconditioner scaling sqrt(rho0_k / rho), rounded to FP32
-  // (4 bytes a point); written by the divergence, and every use takes the
-  // same rounded value, so the preconditioner stays exactly symmetric
-  float* s;
 };
 
 // part: one partial sum per workgroup: var_stencil_parts entries after the

@@ -5,16 +5,17 @@
 // Sec. 5 proposes a preconditioner built from the problem's structure and a
 // mixed-precision solver with a double-precision restart).
 //
-// Preconditioner: M^-1 = S Lbar^-1 S, Lbar the separable operator with the
-// plan's rho0(z) (solved spectrally) and S = diag(sqrt(rho0_k / rho)), the
-// symmetric scaling that carries the local density (self-adjoint in the dz
-// inner product like Lbar^-1; 8 instead of 10 iterations at +-20 % density,
-// 12 instead of 17 at +-50 %). The solver keeps the scaled residual
-// rt = S r, which is what the spectral solve reads (z' = Lbar^-1 rt, z = S z'),
-// so <r, z> = <rt, z'>; S enters the residual update, <z, q> and the
-// direction update, and the residual norm is taken of r = rt / S. S is
-// stored in FP32 and every use takes that same rounded value, so the
-// preconditioner stays exactly symmetric.
+// Preconditioner: M^-1 = Lbar^-1, Lbar the separable operator with the
+// plan's rho0(z), solved spectrally. Both D_rho G and Lbar are
+// -D (face density) G, so their energies p^T A p differ only in the face
+// density that weighs each face's |G p|^2: the preconditioned operator's
+// condition is at most max(rho_face / rho0) / min(rho_face / rho0) on every
+// grid (12 iterations at +-30 % density to a relative residual of 1e-10,
+// from 16 x 32 to 256^2 points a level). A symmetric density scaling
+// S Lbar^-1 S, S = diag(sqrt(rho0 / rho)), saved a few iterations on square
+// domains but loses that bound: G(S p) carries p G(S), which dominates for
+// the lowest modes of a long domain (16 x 1024 x 6, dy = 57 m: no
+// convergence in 200 iterations), so it is not used.
 //
 // All vectors are FP64 (nz, ny, nx) fields; the preconditioned residual z is
 // in the plan's storage type (ZT). Face densities come from rho on the fly:
@@ -132,8 +133,7 @@ __device__ __forceinline__ Lev level(const VarGrid& g, int k) {
 
 }  // namespace
 
-// r = D_rho(u*); writes s = sqrt(rho0_k / rho), the scaled residual rt = s r
-// and p = 0; partial sums of dz r^2. Each thread walks up its group of
+// r = D_rho(u*) and p = 0; partial sums of dz r^2. Each thread walks up its group of
 // levels keeping rho and w of the level below in registers.
 __global__ void __launch_bounds__(kVarBlock) k_var_div(VarGrid g, const double* __restrict__ u,
                                                      const double* __restrict__ v, const double* __restrict__ w,
@@ -156,7 +156,6 @@ __global__ void __launch_bounds__(kVarBlock) k_var_div(VarGrid g, const double* 
   double acc = 0.0;
   for (int k = k0; k < k1; ++k) {
     const Lev L = level(g, k);
-    const double r0 = g.rho0[k];
     const long long b = (long long)k * nh, bu = L.top ? b + nh : b;
 #pragma unroll
     for (int t = 0; t < kVarPts; ++t) {
@@ -169,10 +168,7 @@ __global__ void __launch_bounds__(kVarBlock) k_var_div(VarGrid g, const double* 
       const double div = (rxe * u[b + c.h[t]] - rxw * u[b + c.hw[t]]) * g.rdx +
                          (ryn * v[b + c.h[t]] - rys * v[b + c.hs[t]]) * g.rdy + (ft - fb) * L.rdz;
       if (c.live[t]) {
-        const float sf = (float)sqrt(r0 / rc[t]);
-        const double sc = (double)sf;
-        g.s[b + c.h[t]] = sf;
-        r[b + c.h[t]] = sc * div;
+        r[b + c.h[t]] = div;
         p[b + c.h[t]] = 0.0;
         acc += L.dz * div * div;
       }
@@ -317,7 +313,7 @@ __global__ void __launch_bounds__(kVarBlock) k_var_apply2(VarGrid g, const doubl
   if (threadIdx.x == 0) part[part_index()] = sm;
 }
 
-// alpha = rz/dq; p += alpha d; rt -= alpha s q; partial sums of dz (rt/s)^2
+// alpha = rz/dq; p += alpha d; r -= alpha q; partial sums of dz r^2
 __global__ void __launch_bounds__(kVarBlock) k_var_update(VarGrid g, const double* __restrict__ scal, int it,
                                                         double* __restrict__ p, double* __restrict__ r,
                                                         const double* __restrict__ d, const double* __restrict__ q,
@@ -335,14 +331,12 @@ __global__ void __launch_bounds__(kVarBlock) k_var_update(VarGrid g, const doubl
 #pragma unroll
     for (int t = 0; t < kVarPts; ++t) {
       const long long o = b + c.h[t];
-      const double sc = (double)g.s[o];
       const double pn = p[o] + alpha * d[o];
-      const double rn = r[o] - alpha * sc * q[o];
-      const double ru = rn / sc;   // the unscaled residual
+      const double rn = r[o] - alpha * q[o];
       if (c.live[t]) {
         p[o] = pn;
         r[o] = rn;
-        acc += dz * ru * ru;
+        acc += dz * rn * rn;
       }
     }
   }
@@ -350,8 +344,8 @@ __global__ void __launch_bounds__(kVarBlock) k_var_update(VarGrid g, const doubl
   if (threadIdx.x == 0) part[part_index()] = s;
 }
 
-// partial sums of dz rt z' (= <r, z>) and, for the flexible update (FLEX),
-// dz s z' q (= <z, q>)
+// partial sums of dz r z (<r, z>) and, for the flexible update (FLEX),
+// dz z q (<z, q>)
 template <typename ZT, bool FLEX>
 __global__ void __launch_bounds__(kVarBlock) k_var_dots(VarGrid g, const double* __restrict__ scal,
                                                       const double* __restrict__ r, const ZT* __restrict__ z,
@@ -371,8 +365,8 @@ __global__ void __launch_bounds__(kVarBlock) k_var_dots(VarGrid g, const double*
       const double zc = (double)z[o], rc = r[o];
       if (c.live[t]) a0 += dz * rc * zc;
       if constexpr (FLEX) {
-        const double qc = q[o], sc = (double)g.s[o];
-        if (c.live[t]) a1 += dz * sc * zc * qc;
+        const double qc = q[o];
+        if (c.live[t]) a1 += dz * zc * qc;
       }
     }
   }
@@ -385,7 +379,7 @@ __global__ void __launch_bounds__(kVarBlock) k_var_dots(VarGrid g, const double*
   }
 }
 
-// d = s z' + beta d (beta = 0 at it = 0); flexible (Polak-Ribiere):
+// d = z + beta d (beta = 0 at it = 0); flexible (Polak-Ribiere):
 // beta = <z_it, r_it - r_{it-1}> / rz_{it-1} = -alpha_{it-1} <z_it, q_{it-1}> / rz_{it-1};
 // otherwise (Fletcher-Reeves) beta = rz_it / rz_{it-1}
 template <typename ZT, bool FLEX>
@@ -411,7 +405,7 @@ __global__ void __launch_bounds__(kVarBlock) k_var_dir(VarGrid g, const double* 
 #pragma unroll
     for (int t = 0; t < kVarPts; ++t) {
       const long long o = b + c.h[t];
-      const double zc = (double)g.s[o] * (double)z[o];
+      const double zc = (double)z[o];
       // d is not yet defined at it = 0
       const double dn = it > 0 ? zc + beta * d[o] : zc;
       if (c.live[t]) d[o] = dn;
