@@ -94,14 +94,40 @@ def kernel_path_bytes_per_point(nx, mixed):
     return (18 + 16 * f) * 4.0 if mixed else (11 + 8 * f) * 8.0
 
 
+def strip_comments(src):
+    """C++ source without its comments, runs of whitespace collapsed to one
+    space (string and character literals kept as written)."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def kernel_source_hash():
-    """Hash of every kernel source (a counter summary taken on other sources
-    is stale)."""
+    """Hash of every kernel source, comments and layout aside (a counter
+    summary taken on other code is stale; one taken before a comment changed
+    is not)."""
     h = hashlib.sha256()
     for name in sorted(os.listdir(KERNEL_DIR)):
         if name.endswith((".hip", ".h")):
-            with open(os.path.join(KERNEL_DIR, name), "rb") as fh:
-                h.update(name.encode() + b"\0" + fh.read())
+            with open(os.path.join(KERNEL_DIR, name), encoding="utf-8") as fh:
+                h.update(name.encode() + b"\0" + strip_comments(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -533,8 +533,14 @@ __device__ __forceinline__ long long tiled_pair(const MemberDesc& d, long long p
 // x-direction forward real FFT, compile-time length N (NT = N/8 threads per
 // transform, blockDim = transforms per workgroup * NT)
 // ---------------------------------------------------------------------------
+// The residual variant at lengths whose transforms share a wave (no scalar
+// row contexts, below) needs about 172 registers: 2 waves per SIMD. A budget
+// for 3 spills 2-6 registers and gains about 1 % on grids of 64^2 to 256^2; a
+// budget for 5 waves at the longer lengths spills 16 and loses 6 %.
 template <typename T, int MODE, int N>
-__global__ void __launch_bounds__(512) k_xfwd_ct(LaunchArgs a) {
+__global__ void __launch_bounds__(512)
+    __attribute__((amdgpu_waves_per_eu(MODE == 1 && ct_threads(N) % 64 != 0 ? 3 : 1, 8)))
+    k_xfwd_ct(LaunchArgs a) {
   constexpr int NT = ct_threads(N);
   using F = CtFft<T, N, NT, false>;
   extern __shared__ unsigned char smem_raw[];
@@ -546,8 +552,9 @@ __global__ void __launch_bounds__(512) k_xfwd_ct(LaunchArgs a) {
   const int ipw = blockDim.x / NT;
   // scalar row contexts for the residual only, and only where a transform
   // spans whole waves (NT a multiple of 64: then no wave holds lanes of two
-  // transforms): its occupancy rises from 3 to 5 waves per SIMD and it gains;
-  // the divergence variants measure slower at the higher occupancy
+  // transforms): its registers fall from 174 to 126 and its occupancy rises
+  // from 2 to 4 waves per SIMD, and it gains; the divergence variants measure
+  // slower with scalar contexts
   constexpr bool UNI = NT % 64 == 0 && MODE == 1;
   const int inst = UNI ? wuni((int)(threadIdx.x / NT)) : (int)(threadIdx.x / NT);
   const int q = threadIdx.x - inst * NT;

@@ -96,3 +96,16 @@ def test_summary_dram_cross_check(tmp_path):
                                     str(tmp_path / "dr.csv"))
     line = [ln for ln in text.splitlines() if ln.startswith("dram.mixed.grad_final.bytes_per_launch")][0]
     assert np.isclose(float(line.split(":", 1)[1].split("#", 1)[0]), 3 * A, rtol=1e-6)
+
+
+def test_kernel_hash_ignores_comments_not_code():
+    # a counter summary stays valid across comment edits and goes stale on
+    # any change of the code, string literals included
+    base = 'int f(int a) { return a + 1; } // one\nconst char* s = "x // y";\n'
+    same = '/* doc */\nint f(int a)  {\n  return a + 1;  // two\n}\nconst char* s = "x // y";'
+    code = 'int f(int a) { return a + 2; }\nconst char* s = "x // y";\n'
+    lit = 'int f(int a) { return a + 1; }\nconst char* s = "x // z";\n'
+    assert bench.strip_comments(base) == bench.strip_comments(same)
+    assert bench.strip_comments(base) != bench.strip_comments(code)
+    assert bench.strip_comments(base) != bench.strip_comments(lit)
+    assert bench.strip_comments("char c = '\"'; /* a */ int b;") == "char c = '\"'; int b;"
