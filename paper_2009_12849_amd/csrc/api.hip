@@ -605,7 +605,16 @@ static Shape member_shape(const MemberDesc& d, Phase ph, bool fp64) {
     const long long pairs = (d.nrow + 1) / 2;
     if (ct_supported(d.nx)) {
       const int nt = ct_threads_host(d.nx);
-      const int ipw = d.xpw > 0 ? d.xpw : std::max(1, 256 / nt);
+      int ipw = d.xpw > 0 ? d.xpw : std::max(1, 256 / nt);
+      // the residual kernel at these lengths walks whole rows per wave: its
+      // workgroups hold whole waves, the nearest multiple of m transforms
+      // (up, unless that passes 512 threads; m nt <= 512, and at most 16
+      // transforms of 256 to 1536 points stay within the LDS limit)
+      if (ph == PH_RESID && xres_wave_rows(d.nx)) {
+        const int m = wave_transforms(nt);
+        ipw = (ipw + m - 1) / m * m;
+        if (ipw * nt > 512) ipw -= m;
+      }
       s.variant = d.nx;
       s.block = ipw * nt;
       s.lds = (size_t)ipw * xlds_len(d.nx, (int)cb) * cb;

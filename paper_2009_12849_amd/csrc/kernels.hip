@@ -533,13 +533,15 @@ __device__ __forceinline__ long long tiled_pair(const MemberDesc& d, long long p
 // x-direction forward real FFT, compile-time length N (NT = N/8 threads per
 // transform, blockDim = transforms per workgroup * NT)
 // ---------------------------------------------------------------------------
-// The residual variant at lengths whose transforms share a wave (no scalar
-// row contexts, below) needs about 172 registers: 2 waves per SIMD. A budget
-// for 3 spills 2-6 registers and gains about 1 % on grids of 64^2 to 256^2; a
-// budget for 5 waves at the longer lengths spills 16 and loses 6 %.
+// The residual variant at lengths whose transforms share a wave and whose
+// stencil cannot walk whole rows per wave (below 256 points, or not a
+// multiple of 256) keeps its row contexts in vector registers: about 172
+// registers, 2 waves per SIMD. A budget for 3 spills 2-6 registers and gains
+// about 1 % on grids of 64^2 to 192^2; a budget for 5 waves at the longer
+// lengths spills 16 and loses 6 %.
 template <typename T, int MODE, int N>
 __global__ void __launch_bounds__(512)
-    __attribute__((amdgpu_waves_per_eu(MODE == 1 && ct_threads(N) % 64 != 0 ? 3 : 1, 8)))
+    __attribute__((amdgpu_waves_per_eu(MODE == 1 && ct_threads(N) % 64 != 0 && !xres_wave_rows(N) ? 3 : 1, 8)))
     k_xfwd_ct(LaunchArgs a) {
   constexpr int NT = ct_threads(N);
   using F = CtFft<T, N, NT, false>;
@@ -568,10 +570,10 @@ __global__ void __launch_bounds__(512)
     c1 = wuni(c1);
   }
   // 1. vector phase: the stencil on 16-byte chunks of both rows, packed as
-  //    z = row0 + i row1 into LDS in natural order
+  //    z = row0 + i row1 into LDS in natural order: chunk i0 of the rows with
+  //    contexts (c0, c1) and validity (v0, v1) into transform slot L
   constexpr int V = Vec<T>::n;
-  auto stencil = [&](int t) {
-    const int i0 = (q + t * NT) * V;
+  auto stencil = [&](const RowCtx& c0, const RowCtx& c1, bool v0, bool v1, int i0, cx<T>* L) {
     T s0[V], s1[V];
     // a full pair within one level (even ny): the two rows share loads
     const bool pair = !(d.ny & 1) && v1;
@@ -604,10 +606,27 @@ __global__ void __launch_bounds__(512)
       }
     }
 #pragma unroll
-    for (int e = 0; e < V; ++e) lds[xpad<T, N>(i0 + e)] = cx<T>{s0[e], s1[e]};
+    for (int e = 0; e < V; ++e) L[xpad<T, N>(i0 + e)] = cx<T>{s0[e], s1[e]};
   };
+  if constexpr (MODE == 1 && xres_wave_rows(N)) {
+    // residual with transforms narrower than a wave: each wave takes one
+    // transform's 64-lane run of chunks at a time (the host launches whole
+    // waves), so the row contexts are wave-uniform, in scalar registers, as
+    // in the case above; this halves the registers and doubles the waves
+    constexpr int C = N / (64 * V);  // wave runs per transform
+    const int nw = blockDim.x / 64, wv = wuni((int)(threadIdx.x / 64)), ln = threadIdx.x & 63;
+    cx<T>* lds0 = reinterpret_cast<cx<T>*>(smem_raw);
+    for (int it = wv; it < ipw * C; it += nw) {
+      const int ins = it / C, ch = it - ins * C;
+      const long long pr = tiled_pair(d, (long long)lb * ipw + ins);
+      const bool w0 = 2 * pr < d.nrow, w1 = 2 * pr + 1 < d.nrow;
+      const RowCtx e0 = wuni(make_row(d, 2 * pr, w0)), e1 = wuni(make_row(d, 2 * pr + 1, w1));
+      stencil(e0, e1, w0, w1, (ch * 64 + ln) * V, lds0 + ins * xlds_len(N, 2 * sizeof(T)));
+    }
+  } else {
 #pragma unroll
-  for (int t = 0; t < N / (V * NT); ++t) stencil(t);
+    for (int t = 0; t < N / (V * NT); ++t) stencil(c0, c1, v0, v1, (q + t * NT) * V, lds);
+  }
   __syncthreads();
   cx<T> v[F::VMAX];
 #pragma unroll

@@ -33,6 +33,20 @@ constexpr int tri_lane_slots(int s, bool f32) {
 // along y sixteen from length 2048 on, so that a 1024-thread workgroup still
 // holds several columns of the longest transforms, eight below.
 constexpr int ct_threads_x_n(int n) { return n >= 512 ? n / 16 : (n >= 8 ? n / 8 : 1); }
+// Fewest transforms of nt threads that fill whole waves (64 lanes).
+constexpr int wave_transforms(int nt) {
+  int m = 1;
+  while (m * nt % 64 != 0) m *= 2;
+  return m;
+}
+// The residual's stencil phase at lengths whose transforms do not fill whole
+// waves, are a multiple of 256 points and fit whole waves in 512 threads
+// (256, 512, 768, 1536) walks whole rows per wave (64 lanes x 4 points), so
+// that each wave handles one transform's rows at a time and its row contexts
+// are wave-uniform; its workgroups then hold whole waves.
+constexpr bool xres_wave_rows(int n) {
+  return ct_threads_x_n(n) % 64 != 0 && n % 256 == 0 && wave_transforms(ct_threads_x_n(n)) * ct_threads_x_n(n) <= 512;
+}
 // Along y the elements per thread (8: radix-8 passes, 16: radix-16 passes)
 // are a tile parameter: default sixteen from length 2048 on, eight below.
 constexpr int ct_yept_default(int n) { return n >= 2048 ? 16 : 8; }

@@ -268,6 +268,35 @@ def test_mixed_small(shape):
     assert np.all(out[2][-1] == 0.0)
 
 
+@pytest.mark.parametrize("nx,xpws", [(256, [1, 2, 3, 8]), (512, [1, 4]), (768, [1, 4, 9]), (1536, [1, 3])])
+@pytest.mark.parametrize("ny", [6, 9])
+def test_mixed_residual_whole_rows_per_wave(nx, xpws, ny):
+    # at these lengths the residual's stencil walks whole rows per wave and
+    # the host rounds its transforms per workgroup to whole waves (up, or
+    # down where up passes 512 threads: 9 x 48 -> 8 x 48); each transform's
+    # arithmetic does not depend on the grouping, so every value gives the
+    # same bits, within the oracle's bound. ny = 9: rows pair across levels
+    # (single-row stencils) and the last pair has one row
+    g, u, v, w = _case((nx, ny, 5), 23)
+    u32, v32, w32 = (a.astype(np.float32) for a in (u, v, w))
+    ref = oracle.project(u32.astype(np.float64), v32.astype(np.float64), w32.astype(np.float64),
+                         g.dx, g.dy, g.dz, g.rho0)
+    outs = []
+    for xpw in xpws:
+        print(f"case residual whole rows nx={nx} ny={ny} xpw={xpw}", flush=True)
+        plan = monc.Plan.from_grid(g, "mixed")
+        plan.params = [0, 0, 0, 0, 0, xpw, 0]
+        assert plan.params[5] == xpw
+        out = run_gpu(g, u32, v32, w32, "mixed", plan=plan)
+        errs = field_errors(out, ref, u32, v32, w32)
+        assert max(errs) <= TOL_MIXED, (xpw, errs)
+        outs.append(out)
+        plan.close()
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
+
+
 def test_mixed_256x256x128_with_ir_gain():
     m = synth.make_workload("256x256x128").members[0]
     g = m.grid
@@ -349,6 +378,34 @@ def test_batch_schedules_equal_member_projections(dtype):
             got = [t.cpu().numpy().astype(np.float64) for t in fields[i] + [ps[i]]]
             for a, ref in zip(got, singles[i]):
                 assert np.array_equal(a, ref), (order, budget, branches, i)
+
+
+def test_batch_with_whole_row_residual_equals_member_projections():
+    # members whose residual walks whole rows per wave (nx = 256, 768), with
+    # transforms per workgroup that the host rounds to whole waves (3 -> 4,
+    # 1 -> 2 and 1 -> 4), beside one that takes the per-thread mapping (96),
+    # in one grouped batch: each member's projection bit for bit
+    mem = _ensemble(1, [(256, 6, 5)], 50) + _ensemble(1, [(256, 9, 4)], 51) + _ensemble(1, [(768, 4, 3)], 52) \
+        + _ensemble(1, [(96, 8, 6)], 53)
+    xpws = [3, 1, 1, 0]
+    plans = []
+    for (g, *_), xpw in zip(mem, xpws):
+        pl = monc.Plan.from_grid(g, "mixed")
+        pl.params = [0, 0, 0, 0, 0, xpw, 0]
+        plans.append(pl)
+    print("case batch with whole-row residual", flush=True)
+    singles = [run_gpu(g, u.astype(np.float32), v.astype(np.float32), w.astype(np.float32), "mixed", plan=pl)
+               for (g, u, v, w), pl in zip(mem, plans)]
+    fields = [[to_dev(a.astype(np.float32), torch.float32) for a in (u, v, w)] for _, u, v, w in mem]
+    ps = [torch.empty_like(f[0]) for f in fields]
+    monc.project_batched(plans, [f[0] for f in fields], [f[1] for f in fields], [f[2] for f in fields], ps)
+    torch.cuda.synchronize()
+    for i in range(len(mem)):
+        got = [t.cpu().numpy().astype(np.float64) for t in fields[i] + [ps[i]]]
+        for a, ref in zip(got, singles[i]):
+            assert np.array_equal(a, ref), i
+    for pl in plans:
+        pl.close()
 
 
 def test_batch_autotune_picks_a_schedule_and_caches_it(tmp_path, monkeypatch):
