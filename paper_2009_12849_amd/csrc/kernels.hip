@@ -343,8 +343,14 @@ __device__ __forceinline__ void div_pair_vec(const MemberDesc& d, const RowCtx& 
 }
 
 typedef float f4v __attribute__((ext_vector_type(4)));
+template <int W> using fwv = float __attribute__((ext_vector_type(W)));
 
-// FP64 residual D(u*) - L p1 at points i0 .. i0+3 of a row from the loaded
+template <int W>
+__device__ __forceinline__ fwv<W> ldw(const float* p) {
+  return *reinterpret_cast<const fwv<W>*>(p);
+}
+
+// FP64 residual D(u*) - L p1 at points i0 .. i0+W-1 of a row from the loaded
 // neighbourhood (float data; pc: p1 of the row, pn/ps: rows j +- 1, pu/pd:
 // levels k +- 1, pe/pw: x-neighbours outside the vector, um: u west of the
 // vector; pu/pd, wc/wb ignored on the lid and bottom rows).
@@ -352,20 +358,22 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 // out once (rho0/dx, rho0/dx^2, ...) and every pressure difference taken
 // before it is scaled: one FP64 fused multiply-add per term. The callers pass
 // wc = 0 and pu = pc on the lid row, wb = 0 and pd = pc on the bottom row,
-// where the row's rhow (lid) and rhowm (bottom) are 0 as well.
-__device__ __forceinline__ void resid_core(const MemberDesc& d, const RowCtx& c, f4v pc, f4v pn, f4v ps, f4v pu,
-                                           f4v pd, float pw, float pe, f4v uc, float um, f4v vc, f4v vs, f4v wc,
-                                           f4v wb, float* out) {
+// where the row's rhow (lid) and rhowm (bottom) are 0 as well. A point's
+// value does not depend on W.
+template <int W>
+__device__ __forceinline__ void resid_core(const MemberDesc& d, const RowCtx& c, fwv<W> pc, fwv<W> pn, fwv<W> ps,
+                                           fwv<W> pu, fwv<W> pd, float pw, float pe, fwv<W> uc, float um,
+                                           fwv<W> vc, fwv<W> vs, fwv<W> wc, fwv<W> wb, float* out) {
   const double bx = c.rho0 * d.rdx, by = c.rho0 * d.rdy;      // D(u*) horizontal
   const double wt = c.rdz * c.rhow, wm = c.rdz * c.rhowm;     // D(u*) vertical
   const double ax = bx * d.rdx, ay = by * d.rdy;              // L p1 horizontal
   const double cu = wt * c.rdzc, cd = wm * c.rdzcm;           // L p1 vertical
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const double uW = (e > 0) ? (double)uc[(e + 3) & 3] : (double)um;
+  for (int e = 0; e < W; ++e) {
+    const double uW = (e > 0) ? (double)uc[e > 0 ? e - 1 : 0] : (double)um;
     const double p0 = pc[e];
-    const double pE = (e < 3) ? (double)pc[(e + 1) & 3] : (double)pe;
-    const double pW = (e > 0) ? (double)pc[(e + 3) & 3] : (double)pw;
+    const double pE = (e < W - 1) ? (double)pc[e < W - 1 ? e + 1 : 0] : (double)pe;
+    const double pW = (e > 0) ? (double)pc[e > 0 ? e - 1 : 0] : (double)pw;
     const double dxx = (pE - p0) - (p0 - pW), dyy = ((double)pn[e] - p0) - (p0 - (double)ps[e]);
     double r = bx * ((double)uc[e] - uW);
     r = fma(by, (double)vc[e] - (double)vs[e], r);
@@ -379,6 +387,7 @@ __device__ __forceinline__ void resid_core(const MemberDesc& d, const RowCtx& c,
   }
 }
 
+template <int W>
 __device__ __forceinline__ void resid_vec(const MemberDesc& d, const RowCtx& c, const IoPtrs& io, int i0,
                                           float* out) {
   const float* __restrict__ u = reinterpret_cast<const float*>(io.u);
@@ -386,27 +395,28 @@ __device__ __forceinline__ void resid_vec(const MemberDesc& d, const RowCtx& c, 
   const float* __restrict__ w = reinterpret_cast<const float*>(io.w);
   const float* __restrict__ p = io.s2;
   const int nx = d.nx;
-  const int iw = (i0 == 0) ? nx - 1 : i0 - 1, ie = (i0 + 4 == nx) ? 0 : i0 + 4;
-  const f4v pc = ldv(p + c.off + i0);
+  const int iw = (i0 == 0) ? nx - 1 : i0 - 1, ie = (i0 + W == nx) ? 0 : i0 + W;
+  const fwv<W> pc = ldw<W>(p + c.off + i0);
   const float pw = p[c.off + iw], pe = p[c.off + ie];
-  const f4v pn = ldv(p + c.noff + i0), ps = ldv(p + c.soff + i0);
-  const f4v uc = ldv(u + c.off + i0);
+  const fwv<W> pn = ldw<W>(p + c.noff + i0), ps = ldw<W>(p + c.soff + i0);
+  const fwv<W> uc = ldw<W>(u + c.off + i0);
   const float um = u[c.off + iw];
-  const f4v vc = ldv(v + c.off + i0), vs = ldv(v + c.soff + i0);
-  f4v pu = pc, pd = pc, wc = (f4v)0.0f, wb = (f4v)0.0f;
+  const fwv<W> vc = ldw<W>(v + c.off + i0), vs = ldw<W>(v + c.soff + i0);
+  fwv<W> pu = pc, pd = pc, wc = (fwv<W>)0.0f, wb = (fwv<W>)0.0f;
   if (c.top) {
-    pu = ldv(p + c.off + c.plane + i0);
-    wc = ldv(w + c.off + i0);
+    pu = ldw<W>(p + c.off + c.plane + i0);
+    wc = ldw<W>(w + c.off + i0);
   }
   if (c.bot) {
-    pd = ldv(p + c.off - c.plane + i0);
-    wb = ldv(w + c.off - c.plane + i0);
+    pd = ldw<W>(p + c.off - c.plane + i0);
+    wb = ldw<W>(w + c.off - c.plane + i0);
   }
-  resid_core(d, c, pc, pn, ps, pu, pd, pw, pe, uc, um, vc, vs, wc, wb, out);
+  resid_core<W>(d, c, pc, pn, ps, pu, pd, pw, pe, uc, um, vc, vs, wc, wb, out);
 }
 
 // Both rows of a pair (k, j) and (k, j+1) of one level: they share p1 rows j
 // and j+1 and v row j, so 17 vector loads serve the two rows instead of 20.
+template <int W>
 __device__ __forceinline__ void resid_pair_vec(const MemberDesc& d, const RowCtx& c0, const RowCtx& c1,
                                                const IoPtrs& io, int i0, float* out0, float* out1) {
   const float* __restrict__ u = reinterpret_cast<const float*>(io.u);
@@ -414,28 +424,29 @@ __device__ __forceinline__ void resid_pair_vec(const MemberDesc& d, const RowCtx
   const float* __restrict__ w = reinterpret_cast<const float*>(io.w);
   const float* __restrict__ p = io.s2;
   const int nx = d.nx;
-  const int iw = (i0 == 0) ? nx - 1 : i0 - 1, ie = (i0 + 4 == nx) ? 0 : i0 + 4;
-  const f4v ps = ldv(p + c0.soff + i0), p0 = ldv(p + c0.off + i0), p1 = ldv(p + c1.off + i0);
-  const f4v p2 = ldv(p + c1.noff + i0);
+  const int iw = (i0 == 0) ? nx - 1 : i0 - 1, ie = (i0 + W == nx) ? 0 : i0 + W;
+  const fwv<W> ps = ldw<W>(p + c0.soff + i0), p0 = ldw<W>(p + c0.off + i0), p1 = ldw<W>(p + c1.off + i0);
+  const fwv<W> p2 = ldw<W>(p + c1.noff + i0);
   const float pw0 = p[c0.off + iw], pe0 = p[c0.off + ie], pw1 = p[c1.off + iw], pe1 = p[c1.off + ie];
-  const f4v u0 = ldv(u + c0.off + i0), u1 = ldv(u + c1.off + i0);
+  const fwv<W> u0 = ldw<W>(u + c0.off + i0), u1 = ldw<W>(u + c1.off + i0);
   const float um0 = u[c0.off + iw], um1 = u[c1.off + iw];
-  const f4v vs = ldv(v + c0.soff + i0), v0 = ldv(v + c0.off + i0), v1 = ldv(v + c1.off + i0);
-  f4v pu0 = p0, pd0 = p0, pu1 = p1, pd1 = p1, wc0 = (f4v)0.0f, wb0 = (f4v)0.0f, wc1 = (f4v)0.0f, wb1 = (f4v)0.0f;
+  const fwv<W> vs = ldw<W>(v + c0.soff + i0), v0 = ldw<W>(v + c0.off + i0), v1 = ldw<W>(v + c1.off + i0);
+  fwv<W> pu0 = p0, pd0 = p0, pu1 = p1, pd1 = p1;
+  fwv<W> wc0 = (fwv<W>)0.0f, wb0 = (fwv<W>)0.0f, wc1 = (fwv<W>)0.0f, wb1 = (fwv<W>)0.0f;
   if (c0.top) {  // one level: c0.top == c1.top, c0.bot == c1.bot
-    pu0 = ldv(p + c0.off + c0.plane + i0);
-    pu1 = ldv(p + c1.off + c1.plane + i0);
-    wc0 = ldv(w + c0.off + i0);
-    wc1 = ldv(w + c1.off + i0);
+    pu0 = ldw<W>(p + c0.off + c0.plane + i0);
+    pu1 = ldw<W>(p + c1.off + c1.plane + i0);
+    wc0 = ldw<W>(w + c0.off + i0);
+    wc1 = ldw<W>(w + c1.off + i0);
   }
   if (c0.bot) {
-    pd0 = ldv(p + c0.off - c0.plane + i0);
-    pd1 = ldv(p + c1.off - c1.plane + i0);
-    wb0 = ldv(w + c0.off - c0.plane + i0);
-    wb1 = ldv(w + c1.off - c1.plane + i0);
+    pd0 = ldw<W>(p + c0.off - c0.plane + i0);
+    pd1 = ldw<W>(p + c1.off - c1.plane + i0);
+    wb0 = ldw<W>(w + c0.off - c0.plane + i0);
+    wb1 = ldw<W>(w + c1.off - c1.plane + i0);
   }
-  resid_core(d, c0, p0, p1, ps, pu0, pd0, pw0, pe0, u0, um0, v0, vs, wc0, wb0, out0);
-  resid_core(d, c1, p1, p2, p0, pu1, pd1, pw1, pe1, u1, um1, v1, v0, wc1, wb1, out1);
+  resid_core<W>(d, c0, p0, p1, ps, pu0, pd0, pw0, pe0, u0, um0, v0, vs, wc0, wb0, out0);
+  resid_core<W>(d, c1, p1, p2, p0, pu1, pd1, pw1, pe1, u1, um1, v1, v0, wc1, wb1, out1);
 }
 
 template <typename T, int MODE>
@@ -451,7 +462,7 @@ __device__ __forceinline__ void source_vec(const MemberDesc& d, const RowCtx& c,
       out[e + 1] = (T)x[1];
     }
   } else {
-    resid_vec(d, c, io, i0, reinterpret_cast<float*>(out));
+    resid_vec<4>(d, c, io, i0, reinterpret_cast<float*>(out));
   }
 }
 
@@ -534,10 +545,10 @@ __device__ __forceinline__ long long tiled_pair(const MemberDesc& d, long long p
 // transform, blockDim = transforms per workgroup * NT)
 // ---------------------------------------------------------------------------
 // The residual variant at lengths whose transforms share a wave and whose
-// stencil cannot walk whole rows per wave (below 256 points, or not a
-// multiple of 256) keeps its row contexts in vector registers: about 172
-// registers, 2 waves per SIMD. A budget for 3 spills 2-6 registers and gains
-// about 1 % on grids of 64^2 to 192^2; a budget for 5 waves at the longer
+// stencil cannot walk whole rows per wave (16 to 48 and 96 points) keeps its
+// row contexts in vector registers: about 172 registers, 2 waves per SIMD. A
+// budget for 3 spills 2-6 registers and measured about 1 % faster where it
+// applied before the whole-row stencil; a budget for 5 waves at the longer
 // lengths spills 16 and loses 6 %.
 template <typename T, int MODE, int N>
 __global__ void __launch_bounds__(512)
@@ -595,7 +606,7 @@ __global__ void __launch_bounds__(512)
       if (pair && MODE == 0) {
         div_pair_vec<T>(d, c0, c1, io, i0, s0, s1);
       } else if (pair && MODE == 1) {
-        resid_pair_vec(d, c0, c1, io, i0, s0, s1);
+        resid_pair_vec<4>(d, c0, c1, io, i0, s0, s1);
       } else {
         if (v0) source_vec<T, MODE>(d, c0, io, i0, s0);
         else
@@ -610,10 +621,12 @@ __global__ void __launch_bounds__(512)
   };
   if constexpr (MODE == 1 && xres_wave_rows(N)) {
     // residual with transforms narrower than a wave: each wave takes one
-    // transform's 64-lane run of chunks at a time (the host launches whole
-    // waves), so the row contexts are wave-uniform, in scalar registers, as
-    // in the case above; this halves the registers and doubles the waves
-    constexpr int C = N / (64 * V);  // wave runs per transform
+    // transform's run of 64 chunks of W points at a time (the host launches
+    // whole waves), so the row contexts are wave-uniform, in scalar
+    // registers, as in the case above; this halves the registers and doubles
+    // the waves. Every point's value is the per-thread mapping's.
+    constexpr int W = xres_chunk(N);
+    constexpr int C = N / (64 * W);  // wave runs per transform
     const int nw = blockDim.x / 64, wv = wuni((int)(threadIdx.x / 64)), ln = threadIdx.x & 63;
     cx<T>* lds0 = reinterpret_cast<cx<T>*>(smem_raw);
     for (int it = wv; it < ipw * C; it += nw) {
@@ -621,7 +634,21 @@ __global__ void __launch_bounds__(512)
       const long long pr = tiled_pair(d, (long long)lb * ipw + ins);
       const bool w0 = 2 * pr < d.nrow, w1 = 2 * pr + 1 < d.nrow;
       const RowCtx e0 = wuni(make_row(d, 2 * pr, w0)), e1 = wuni(make_row(d, 2 * pr + 1, w1));
-      stencil(e0, e1, w0, w1, (ch * 64 + ln) * V, lds0 + ins * xlds_len(N, 2 * sizeof(T)));
+      const int i0 = (ch * 64 + ln) * W;
+      float s0[W], s1[W];
+      if (!(d.ny & 1) && w1) {
+        resid_pair_vec<W>(d, e0, e1, io, i0, s0, s1);
+      } else {
+        if (w0) resid_vec<W>(d, e0, io, i0, s0);
+        else
+          for (int e = 0; e < W; ++e) s0[e] = 0.0f;
+        if (w1) resid_vec<W>(d, e1, io, i0, s1);
+        else
+          for (int e = 0; e < W; ++e) s1[e] = 0.0f;
+      }
+      cx<T>* L = lds0 + ins * xlds_len(N, 2 * sizeof(T));
+#pragma unroll
+      for (int e = 0; e < W; ++e) L[xpad<T, N>(i0 + e)] = cx<T>{s0[e], s1[e]};
     }
   } else {
 #pragma unroll

@@ -40,13 +40,15 @@ constexpr int wave_transforms(int nt) {
   return m;
 }
 // The residual's stencil phase at lengths whose transforms do not fill whole
-// waves, are a multiple of 256 points and fit whole waves in 512 threads
-// (256, 512, 768, 1536) walks whole rows per wave (64 lanes x 4 points), so
-// that each wave handles one transform's rows at a time and its row contexts
-// are wave-uniform; its workgroups then hold whole waves.
+// waves, are a multiple of 64 points and fit whole waves in 512 threads (64,
+// 128, 192, 256, 384, 512, 768, 1536) walks whole rows per wave (64 lanes x
+// xres_chunk points: 4 where the length allows, else 2, else 1), so that each
+// wave handles one transform's rows at a time and its row contexts are
+// wave-uniform; its workgroups then hold whole waves.
 constexpr bool xres_wave_rows(int n) {
-  return ct_threads_x_n(n) % 64 != 0 && n % 256 == 0 && wave_transforms(ct_threads_x_n(n)) * ct_threads_x_n(n) <= 512;
+  return ct_threads_x_n(n) % 64 != 0 && n % 64 == 0 && wave_transforms(ct_threads_x_n(n)) * ct_threads_x_n(n) <= 512;
 }
+constexpr int xres_chunk(int n) { return n % 256 == 0 ? 4 : (n % 128 == 0 ? 2 : 1); }
 // Along y the elements per thread (8: radix-8 passes, 16: radix-16 passes)
 // are a tile parameter: default sixteen from length 2048 on, eight below.
 constexpr int ct_yept_default(int n) { return n >= 2048 ? 16 : 8; }

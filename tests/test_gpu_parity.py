@@ -268,15 +268,17 @@ def test_mixed_small(shape):
     assert np.all(out[2][-1] == 0.0)
 
 
-@pytest.mark.parametrize("nx,xpws", [(256, [1, 2, 3, 8]), (512, [1, 4]), (768, [1, 4, 9]), (1536, [1, 3])])
+@pytest.mark.parametrize("nx,xpws", [(64, [1, 3, 12]), (128, [1, 5]), (192, [1, 9, 21]), (256, [1, 2, 3, 8]),
+                                     (384, [1, 10]), (512, [1, 4]), (768, [1, 4, 9]), (1536, [1, 3])])
 @pytest.mark.parametrize("ny", [6, 9])
 def test_mixed_residual_whole_rows_per_wave(nx, xpws, ny):
-    # at these lengths the residual's stencil walks whole rows per wave and
-    # the host rounds its transforms per workgroup to whole waves (up, or
-    # down where up passes 512 threads: 9 x 48 -> 8 x 48); each transform's
-    # arithmetic does not depend on the grouping, so every value gives the
-    # same bits, within the oracle's bound. ny = 9: rows pair across levels
-    # (single-row stencils) and the last pair has one row
+    # at these lengths the residual's stencil walks whole rows per wave (in
+    # runs of 64 chunks of 1, 2 or 4 points) and the host rounds its
+    # transforms per workgroup to whole waves (up, or down where up passes
+    # 512 threads: 21 x 24 -> 16 x 24, 10 x 48 -> 8 x 48, 9 x 48 -> 8 x 48);
+    # each transform's arithmetic does not depend on the grouping, so every
+    # value gives the same bits, within the oracle's bound. ny = 9: rows pair
+    # across levels (single-row stencils) and the last pair has one row
     g, u, v, w = _case((nx, ny, 5), 23)
     u32, v32, w32 = (a.astype(np.float32) for a in (u, v, w))
     ref = oracle.project(u32.astype(np.float64), v32.astype(np.float64), w32.astype(np.float64),
@@ -381,13 +383,13 @@ def test_batch_schedules_equal_member_projections(dtype):
 
 
 def test_batch_with_whole_row_residual_equals_member_projections():
-    # members whose residual walks whole rows per wave (nx = 256, 768), with
-    # transforms per workgroup that the host rounds to whole waves (3 -> 4,
-    # 1 -> 2 and 1 -> 4), beside one that takes the per-thread mapping (96),
-    # in one grouped batch: each member's projection bit for bit
+    # members whose residual walks whole rows per wave (nx = 256, 768, 192),
+    # with transforms per workgroup that the host rounds to whole waves (3 ->
+    # 4, 1 -> 2, 1 -> 4, 5 -> 8), beside one that takes the per-thread
+    # mapping (96), in one grouped batch: each member's projection bit for bit
     mem = _ensemble(1, [(256, 6, 5)], 50) + _ensemble(1, [(256, 9, 4)], 51) + _ensemble(1, [(768, 4, 3)], 52) \
-        + _ensemble(1, [(96, 8, 6)], 53)
-    xpws = [3, 1, 1, 0]
+        + _ensemble(1, [(192, 6, 5)], 54) + _ensemble(1, [(96, 8, 6)], 53)
+    xpws = [3, 1, 1, 5, 0]
     plans = []
     for (g, *_), xpw in zip(mem, xpws):
         pl = monc.Plan.from_grid(g, "mixed")
