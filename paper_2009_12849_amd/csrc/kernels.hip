@@ -541,15 +541,18 @@ __device__ __forceinline__ long long tiled_pair(const MemberDesc& d, long long p
 }
 
 // ---------------------------------------------------------------------------
-// x-direction forward real FFT, compile-time length N (NT = N/8 threads per
-// transform, blockDim = transforms per workgroup * NT)
+// x-direction forward real FFT, compile-time length N (NT = ct_threads(N)
+// threads per transform: N/16 from 512 points, N/8 below; blockDim =
+// transforms per workgroup * NT)
 // ---------------------------------------------------------------------------
 // The residual variant at lengths whose transforms share a wave and whose
-// stencil cannot walk whole rows per wave (16 to 48 and 96 points) keeps its
-// row contexts in vector registers: about 172 registers, 2 waves per SIMD. A
-// budget for 3 spills 2-6 registers and measured about 1 % faster where it
-// applied before the whole-row stencil; a budget for 5 waves at the longer
-// lengths spills 16 and loses 6 %.
+// stencil does not walk whole rows per wave (lengths that are not a multiple
+// of 64, such as 16-48, 96, 144, 288, or whose whole-wave workgroups would
+// pass 512 threads: 576, 1152, 2304) keeps its row contexts in vector
+// registers: about 172 registers, 2 waves per SIMD. A budget for 3 spills 2-6
+// registers and measured about 1 % faster where it applied before the
+// whole-row stencil; a budget for 5 waves at the longer lengths spills 16 and
+// loses 6 %.
 template <typename T, int MODE, int N>
 __global__ void __launch_bounds__(512)
     __attribute__((amdgpu_waves_per_eu(MODE == 1 && ct_threads(N) % 64 != 0 && !xres_wave_rows(N) ? 3 : 1, 8)))
