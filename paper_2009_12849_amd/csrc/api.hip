@@ -578,6 +578,7 @@ static bool is_yphase(Phase ph) { return ph == PH_YFWD || ph == PH_YINV; }
 // the runtime-length kernel) and `block` its workgroup size.
 struct Shape {
   int variant = 0;   // compile-time length, or 0 for the runtime-length kernel
+  int sub = 0;       // kernel instance within the variant (tridiagonal: column pairs)
   int block = 256;
   size_t lds = 0;
   long long blocks = 0;       // tiles of the phase
@@ -650,6 +651,7 @@ static Shape member_shape(const MemberDesc& d, Phase ph, bool fp64) {
     }
   } else if (ph == PH_TRI) {
     s.variant = d.tris;
+    s.sub = tri_pairs(d.tris, d.tricw, !fp64) ? 1 : 0;
     s.block = d.tricw * d.triP;
     s.lds = (size_t)d.tricw * (d.triP * tri_lane_slots(d.tris, !fp64) + 1) * 16;  // matches the kernel's column stride
     s.blocks = ((long long)d.ny * d.nxp + d.tricw - 1) / d.tricw;  // over the padded plane
@@ -707,7 +709,7 @@ static int launch_one(const Group& g, const std::vector<int>& idx, Phase ph, con
     case PH_RESID: launch_xfwd(a, grid, block, lds, false, 1, v, stream); break;
     case PH_YFWD: launch_ffty(a, grid, block, lds, g.fp64, false, v, g.mem[idx[0]].h->yept, stream); break;
     case PH_YINV: launch_ffty(a, grid, block, lds, g.fp64, true, v, g.mem[idx[0]].h->yept, stream); break;
-    case PH_TRI: launch_tridiag(a, grid, block, lds, g.fp64, v, stream); break;
+    case PH_TRI: launch_tridiag(a, grid, block, lds, g.fp64, v, sh.sub != 0, stream); break;
     case PH_XINV: launch_xinv(a, grid, block, lds, g.fp64, 0, v, stream); break;
     case PH_XINV_P1: launch_xinv(a, grid, block, lds, false, 2, v, stream); break;
     case PH_XINV_CORR: launch_xinv(a, grid, block, lds, false, 1, v, stream); break;
@@ -745,7 +747,7 @@ static int launch_phase(const Group& g, Phase ph, void* stream, Profiler* prof) 
     // the compile-time kernels need blockDim to match each member exactly,
     // and the y kernels the member's elements per thread
     const std::array<int, 3> key{s.variant, s.variant ? s.block : 0,
-                                 (s.variant && is_yphase(ph)) ? g.mem[i].h->yept : 0};
+                                 !s.variant ? 0 : is_yphase(ph) ? g.mem[i].h->yept : s.sub};
     size_t pi = 0;
     while (pi < parts.size() && (parts[pi].first != key || parts[pi].second.size() >= (size_t)kMaxLaunchMembers)) ++pi;
     if (pi == parts.size()) {

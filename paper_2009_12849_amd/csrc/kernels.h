@@ -29,7 +29,7 @@ void launch_xfwd(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64
 void launch_ffty(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, bool inverse, int ct_n, int ept,
                  void* stream);
 // rows: rows per lane, one of kTriRows (the member's tris)
-void launch_tridiag(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, int rows, void* stream);
+void launch_tridiag(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, int rows, bool pairs, void* stream);
 // the result goes to io.p (mode 0), io.s1 (mode 1, float only: the
 // correction delta) or io.s2 (mode 2, float only: the first-pass pressure)
 void launch_xinv(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, int mode, int ct_n, void* stream);

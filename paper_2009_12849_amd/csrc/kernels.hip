@@ -1176,7 +1176,7 @@ __device__ __forceinline__ double2 column_sum(double2 v, int P) {
 
 // One tile of columns; SING: the tile holds the (0,0) column (tile 0), so
 // the mean removal, the pinned top row and the gauge are compiled in.
-template <typename TS, int S, bool SING>
+template <typename TS, int S, bool SING, bool PAIRS>
 __device__ __forceinline__ void tri_tile(const MemberDesc& d, const IoPtrs& io, int lb, double2* stage) {
   const int P = d.triP, CW = d.tricw, nz = d.nz, nxh = d.nxh, nxp = d.nxp;
   const int lp = __builtin_ctz(P), lcw = __builtin_ctz(CW);  // both powers of two
@@ -1202,6 +1202,12 @@ __device__ __forceinline__ void tri_tile(const MemberDesc& d, const IoPtrs& io, 
   //    eliminate; a wave's load touches CW consecutive columns of each of its
   //    levels. The loads are unconditional (clamped address, zero selected
   //    afterwards) so that all of them are in flight before the first wait.
+  //    The PAIRS instance (FP32 storage, even S, tiles of at least 8
+  //    columns): thread (cp, kr) = (tid mod CW/2, tid / (CW/2)) stages levels
+  //    kr S/2 .. kr S/2 + S/2-1 of the column pair 2cp, 2cp+1 instead, with
+  //    16-byte accesses: the same runs in half the memory instructions. A pair
+  //    never straddles the end of the plane (col0, ncolp and the plane are
+  //    even), so its address is in bounds whenever either column is valid.
   const int tid = threadIdx.x;
   const int cc = tid & (CW - 1), kq = tid >> lcw;
   const int ks = kq * S;
@@ -1210,8 +1216,31 @@ __device__ __forceinline__ void tri_tile(const MemberDesc& d, const IoPtrs& io, 
   int sn, sm;
   spec_nm(d, scol_g, sn, sm);
   const bool sok = scol_g < ncolp && sm < nxh;
+  static_assert(!PAIRS || (F32 && S % 2 == 0), "column pairs need FP32 storage and an even row count");
+  constexpr int S2 = PAIRS ? S / 2 : 1;
+  constexpr bool pairs = PAIRS;
+  const int cp = pairs ? tid & ((CW >> 1) - 1) : 0, kr = pairs ? tid >> (lcw - 1) : 0;
+  const int gA = col0 + 2 * cp, ks2 = kr * S2;
+  int nA, mA, nB, mB;
+  spec_nm(d, gA, nA, mA);
+  spec_nm(d, gA + 1, nB, mB);
+  const bool okA = pairs && gA < ncolp && mA < nxh, okB = pairs && gA + 1 < ncolp && mB < nxh;
+  const long long plane4 = plane / 2;  // a level in 16-byte units (FP32 pairs)
+  // the pair's chunk slots: column 2cp + h, lane chunk kr / 2, rows (kr mod 2) S/2 ..
+  auto pslot = [&](int h) {
+    return reinterpret_cast<float2*>(stage + (2 * cp + h) * lrow + (kr >> 1) * SP) + (kr & 1) * S2;
+  };
   CS ld[S];
-  {
+  float4 ld4[S2];
+  if constexpr (pairs) {
+    // levels ks2 .. ks2+S2-1, clamped to nz-1 (those rows are zeroed below)
+    const float4* src = reinterpret_cast<const float4*>(Sg + ((okA || okB) ? gA : 0) + (long long)min(ks2, nz - 1) * plane);
+#pragma unroll
+    for (int j = 0; j < S2; ++j) {
+      ld4[j] = src[0];
+      if (j + 1 < S2) src += (ks2 + j + 1 < nz) ? plane4 : 0;
+    }
+  } else {
     // levels ks .. ks+S-1, clamped to nz-1 (those rows are zeroed below)
     const CS* src = Sg + (sok ? scol_g : 0) + (long long)min(ks, nz - 1) * plane;
 #pragma unroll
@@ -1242,13 +1271,24 @@ __device__ __forceinline__ void tri_tile(const MemberDesc& d, const IoPtrs& io, 
     R0[r] = ldg(d.trr + k0 + r);
   }
   // column data into LDS (zero outside the grid)
+  if constexpr (pairs) {
+    float2* la = pslot(0);
+    float2* lb = pslot(1);
 #pragma unroll
-  for (int j = 0; j < S; ++j) {
-    const bool in = sok && ks + j < nz;  // every slot exists; rows >= nz are never read
-    if constexpr (F32)
-      reinterpret_cast<float2*>(sst)[j] = in ? make_float2(ld[j].x, ld[j].y) : make_float2(0.0f, 0.0f);
-    else
-      sst[j] = make_double2(in ? (double)ld[j].x : 0.0, in ? (double)ld[j].y : 0.0);
+    for (int j = 0; j < S2; ++j) {
+      const bool in = ks2 + j < nz;  // every slot exists; rows >= nz are never read
+      la[j] = okA && in ? make_float2(ld4[j].x, ld4[j].y) : make_float2(0.0f, 0.0f);
+      lb[j] = okB && in ? make_float2(ld4[j].z, ld4[j].w) : make_float2(0.0f, 0.0f);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      const bool in = sok && ks + j < nz;  // every slot exists; rows >= nz are never read
+      if constexpr (F32)
+        reinterpret_cast<float2*>(sst)[j] = in ? make_float2(ld[j].x, ld[j].y) : make_float2(0.0f, 0.0f);
+      else
+        sst[j] = make_double2(in ? (double)ld[j].x : 0.0, in ? (double)ld[j].y : 0.0);
+    }
   }
   // padding columns (m >= nxh) solve a well-conditioned dummy system with a
   // zero right-hand side and are never stored
@@ -1485,7 +1525,26 @@ __device__ __forceinline__ void tri_tile(const MemberDesc& d, const IoPtrs& io, 
   __syncthreads();
 
   // coalesced store (the staging thread's rows), scaled by 1/(nx ny)
-  if (sok) {
+  if constexpr (pairs) {
+    const float2* la = pslot(0);
+    const float2* lb = pslot(1);
+    float2 xa[S2], xb[S2];
+#pragma unroll
+    for (int j = 0; j < S2; ++j) {
+      xa[j] = la[j];
+      xb[j] = lb[j];
+    }
+    CS* dA = Sg + gA + (long long)ks2 * plane;
+    float4* d4 = reinterpret_cast<float4*>(dA);
+#pragma unroll
+    for (int j = 0; j < S2; ++j) {
+      if (ks2 + j < nz) {
+        if (okA && okB) d4[j * plane4] = make_float4(xa[j].x, xa[j].y, xb[j].x, xb[j].y);
+        else if (okA) dA[j * plane] = CS{xa[j].x, xa[j].y};
+        else if (okB) dA[j * plane + 1] = CS{xb[j].x, xb[j].y};
+      }
+    }
+  } else if (sok) {
     CS* dst = Sg + scol_g + (long long)ks * plane;
     if constexpr (F32) {
       float2 x[S];
@@ -1510,7 +1569,7 @@ __device__ __forceinline__ void tri_tile(const MemberDesc& d, const IoPtrs& io, 
 // SIMD (the LDS chunks then fit 4 such workgroups per CU); the solve is
 // latency-bound and gains more from the extra wave than it loses to a
 // 16-byte spill at 10 rows
-template <typename TS, int S, int MAXT>
+template <typename TS, int S, int MAXT, bool PAIRS>
 __global__ void __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(S <= 10 && sizeof(TS) == 4 ? 4 : 1, 8)))
 k_tridiag(LaunchArgs a) {
   extern __shared__ unsigned char smem_raw[];
@@ -1521,9 +1580,9 @@ k_tridiag(LaunchArgs a) {
   const IoPtrs io = a.io[mi];
   const int lb = xcd_local_block(a, mi);
   if (lb == 0)
-    tri_tile<TS, S, true>(d, io, lb, stage);
+    tri_tile<TS, S, true, PAIRS>(d, io, lb, stage);
   else
-    tri_tile<TS, S, false>(d, io, lb, stage);
+    tri_tile<TS, S, false, PAIRS>(d, io, lb, stage);
 }
 
 // ---------------------------------------------------------------------------
@@ -1770,10 +1829,14 @@ void init_kernel_attributes() {
   set_lds_limit(k_xinv_gen<float, 1>);
   set_lds_limit(k_xinv_gen<float, 2>);
 #define MONC_TRI_ATTR(S)                   \
-  set_lds_limit(k_tridiag<double, S, 256>); \
-  set_lds_limit(k_tridiag<float, S, 256>);  \
-  set_lds_limit(k_tridiag<double, S, 512>); \
-  set_lds_limit(k_tridiag<float, S, 512>);
+  set_lds_limit(k_tridiag<double, S, 256, false>); \
+  set_lds_limit(k_tridiag<float, S, 256, false>);  \
+  set_lds_limit(k_tridiag<double, S, 512, false>); \
+  set_lds_limit(k_tridiag<float, S, 512, false>);  \
+  if constexpr (S % 2 == 0) {                      \
+    set_lds_limit(k_tridiag<float, S, 256, S % 2 == 0>); \
+    set_lds_limit(k_tridiag<float, S, 512, S % 2 == 0>); \
+  }
   MONC_TRI_ROWS(MONC_TRI_ATTR)
 #undef MONC_TRI_ATTR
 #define MONC_ATTR(N)                          \
@@ -1894,17 +1957,30 @@ void launch_xinv(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64
   }
 }
 
-void launch_tridiag(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, int rows, void* stream) {
+// FP32 tridiagonal instance: column pairs (even S only) or single columns
+template <int S, int MAXT>
+static void launch_tri_f32(const LaunchArgs& a, int grid, int block, size_t lds, bool pairs, void* stream) {
+  if constexpr (S % 2 == 0) {
+    if (pairs) {
+      MONC_GO((k_tridiag<float, S, MAXT, S % 2 == 0>));
+      return;
+    }
+  }
+  MONC_GO((k_tridiag<float, S, MAXT, false>));
+}
+
+void launch_tridiag(const LaunchArgs& a, int grid, int block, size_t lds, bool fp64, int rows, bool pairs,
+                    void* stream) {
   switch (rows) {
-#define MONC_CASE(S)                                  \
-  case S:                                             \
-    if (block <= 256) {                               \
-      if (fp64) MONC_GO((k_tridiag<double, S, 256>)); \
-      else MONC_GO((k_tridiag<float, S, 256>));       \
-    } else {                                          \
-      if (fp64) MONC_GO((k_tridiag<double, S, 512>)); \
-      else MONC_GO((k_tridiag<float, S, 512>));       \
-    }                                                 \
+#define MONC_CASE(S)                                         \
+  case S:                                                    \
+    if (block <= 256) {                                      \
+      if (fp64) MONC_GO((k_tridiag<double, S, 256, false>)); \
+      else launch_tri_f32<S, 256>(a, grid, block, lds, pairs, stream); \
+    } else {                                                 \
+      if (fp64) MONC_GO((k_tridiag<double, S, 512, false>)); \
+      else launch_tri_f32<S, 512>(a, grid, block, lds, pairs, stream); \
+    }                                                        \
     return;
     MONC_TRI_ROWS(MONC_CASE)
 #undef MONC_CASE

@@ -27,6 +27,12 @@ constexpr int kSpecBlockMax = 8;        // widest spectral column block (nxp is 
 constexpr int tri_lane_slots(int s, bool f32) {
   return f32 ? ((s + 1) / 2 > s - 2 ? (s + 1) / 2 : (s - 2 > 1 ? s - 2 : 1)) | 1 : s | 1;
 }
+
+// The tridiagonal kernel with FP32 storage, an even row count and tiles of at
+// least 8 columns moves column pairs with 16-byte accesses (its own kernel
+// instance): half the memory instructions for the same runs; narrower tiles
+// measured slower that way.
+constexpr bool tri_pairs(int s, int cw, bool f32) { return f32 && s % 2 == 0 && cw >= 8; }
 // Threads per compile-time transform (shared by the kernels and the host's
 // launch shapes), and so the radix plan (16 elements per thread take radix-16
 // passes): along x sixteen elements each from length 512 on, eight below;

@@ -532,6 +532,37 @@ def test_tile_parameters_mixed(params):
     assert max(errs) <= TOL_MIXED, (errs, errs_default)
 
 
+@pytest.mark.parametrize("nz,lanes", [(12, 4), (16, 4), (20, 4), (24, 4), (28, 4), (32, 4), (40, 4), (48, 4),
+                                      (64, 4), (130, 16)])
+def test_mixed_tridiagonal_tiles_give_identical_bits(nz, lanes):
+    # rows per lane 3, 4, 5, 6, 7, 8, 10, 12, 16 and 10 (130 levels on 16
+    # lanes: 9 rounded up, the last lane's rows partly past the top). FP32
+    # storage with an even number and tiles of 8 or more columns takes the
+    # kernel instance that moves column pairs with 16-byte accesses, other
+    # tiles the single-column one; each column's solve does not depend on
+    # how columns are grouped into tiles or staged, so every tile width
+    # gives the same bits. nx = 48: 25 spectral columns per row, so one pair
+    # holds a padding column; ny = 9 leaves the last tile ragged.
+    g, u, v, w = _case((48, 9, nz), 29)
+    u32, v32, w32 = (a.astype(np.float32) for a in (u, v, w))
+    ref = oracle.project(u32.astype(np.float64), v32.astype(np.float64), w32.astype(np.float64),
+                         g.dx, g.dy, g.dz, g.rho0)
+    outs = []
+    for cw in (1, 4, 8, 16):
+        print(f"case tridiagonal tiles nz={nz} lanes={lanes} cw={cw}", flush=True)
+        plan = monc.Plan.from_grid(g, "mixed")
+        plan.params = [0, 0, 0, lanes, cw, 0, 0]
+        assert plan.params[3:5] == [lanes, cw], plan.params
+        out = run_gpu(g, u32, v32, w32, "mixed", plan=plan)
+        errs = field_errors(out, ref, u32, v32, w32)
+        assert max(errs) <= TOL_MIXED, (cw, errs)
+        outs.append(out)
+        plan.close()
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
+
+
 @pytest.mark.parametrize("params", [[8, 8, 8, 16, 3], [8, 8, 8, 32, 32], [8, 8, 8, 64, 16], [8, 8, 8, 3, 0]])
 def test_plan_rejects_bad_tridiagonal_tiles(params):
     g, u, v, w = _case((32, 16, 130), 19)
