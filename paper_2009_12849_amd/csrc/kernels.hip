@@ -512,7 +512,7 @@ __device__ __forceinline__ void spec_nm(const MemberDesc& d, int x, int& n, int&
 }
 
 // Row pairs of the stencil kernels in (level, pair) tiles: consecutive
-// pair slots walk 8 pairs of d.ptk consecutive levels before moving on, so
+// pair slots walk d.ptj pairs of d.ptk consecutive levels before moving on, so
 // the rows a stencil re-reads (levels k +- 1, rows j +- 1) are read by
 // workgroups that run at about the same time on the same XCD and meet in its
 // L2. ptk = 1 or odd ny (pairs straddle levels) keeps the linear order.
@@ -537,7 +537,7 @@ __device__ __forceinline__ long long tiled_index(long long p, long long per, int
 
 __device__ __forceinline__ long long tiled_pair(const MemberDesc& d, long long p) {
   if (d.ny & 1) return p;
-  return tiled_index(p, d.ny / 2, d.nz, d.ptk, 8);
+  return tiled_index(p, d.ny / 2, d.nz, d.ptk, d.ptj);
 }
 
 // ---------------------------------------------------------------------------
@@ -682,12 +682,40 @@ __global__ void __launch_bounds__(512)
   cx<T>* S = reinterpret_cast<cx<T>*>(io.spec);
   const long long so0 = spec_row(d, v0 ? r0 : 0), so1 = spec_row(d, v1 ? r1 : 0);
   const int ns = pair_slots(d);
-  for (int s = q; s < ns; s += NT) {
-    const PairSlot ps = pair_slot(d, s);
-    if (ps.m < d.nxh && (ps.row ? v1 : v0)) {
-      const cx<T> z = lds[xpad<T, N>(ps.m)];
-      const cx<T> zr = lds[xpad<T, N>(ps.m == 0 ? 0 : N - ps.m)];
-      S[(ps.row ? so1 : so0) + ps.off] = split_bin<T>(z, zr, ps.row);
+  if (sizeof(T) == 4 && d.sbw >= 2) {
+    // FP32 with column blocks at least 2 wide: a lane takes two adjacent
+    // slots (bins m, m+1 of one row, adjacent in memory, 16-byte aligned:
+    // m, the block and row offsets and the plane are even) and stores them
+    // with one 16-byte access; a block's last valid bin may be alone. Half
+    // the store instructions of one slot per lane, which measured as the
+    // costliest phase of these kernels.
+    for (int s2 = q; s2 < ns / 2; s2 += NT) {
+      const PairSlot ps = pair_slot(d, 2 * s2);
+      if (ps.m < d.nxh && (ps.row ? v1 : v0)) {
+        const cx<T> b0 = split_bin<T>(lds[xpad<T, N>(ps.m)], lds[xpad<T, N>(ps.m == 0 ? 0 : N - ps.m)], ps.row);
+        cx<T>* dst = S + (ps.row ? so1 : so0) + ps.off;
+        if (ps.m + 1 < d.nxh) {
+          const cx<T> b1 = split_bin<T>(lds[xpad<T, N>(ps.m + 1)], lds[xpad<T, N>(N - ps.m - 1)], ps.row);
+          typedef T t4 __attribute__((ext_vector_type(4)));
+          t4 v;
+          v[0] = b0.x;
+          v[1] = b0.y;
+          v[2] = b1.x;
+          v[3] = b1.y;
+          *reinterpret_cast<t4*>(dst) = v;
+        } else {
+          *dst = b0;
+        }
+      }
+    }
+  } else {
+    for (int s = q; s < ns; s += NT) {
+      const PairSlot ps = pair_slot(d, s);
+      if (ps.m < d.nxh && (ps.row ? v1 : v0)) {
+        const cx<T> z = lds[xpad<T, N>(ps.m)];
+        const cx<T> zr = lds[xpad<T, N>(ps.m == 0 ? 0 : N - ps.m)];
+        S[(ps.row ? so1 : so0) + ps.off] = split_bin<T>(z, zr, ps.row);
+      }
     }
   }
 }

@@ -138,6 +138,7 @@ struct MemberDesc {
   int tris;               // rows per lane (>= 2)
   int tricw;              // columns per workgroup (blockDim / triP)
   int ptk;                // levels per (level, row pair) tile of the stencil kernels (1 = row order)
+  int ptj;                // row pairs per such tile of the x-forward kernels (8 to 64)
   int xpw;                // x-direction transforms (row pairs) per workgroup of the compile-time kernels
   int yept;               // elements per thread of the compile-time y-FFT kernels (8 or 16)
   // Spectral layout: a level's half spectrum sits in column blocks of sbw
