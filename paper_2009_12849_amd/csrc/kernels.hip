@@ -1035,7 +1035,36 @@ __global__ void __launch_bounds__(512) k_xinv_ct(LaunchArgs a) {
   const bool v0 = r0 < d.nrow, v1 = r1 < d.nrow;
   const cx<T>* S = reinterpret_cast<const cx<T>*>(io.spec);
   auto li = [](int i) { return xpad<T, N>(i); };
-  {
+  if (sizeof(T) == 4 && d.sbw >= 2) {
+    // FP32 with column blocks at least 2 wide: bins m, m+1 (m even) of a row
+    // are adjacent and 16-byte aligned in memory, so a lane loads both with
+    // one access (half the load instructions). Pairs m = 0, 2, .. up to nx/2
+    // over NT threads; the slot after bin nx/2 (a padding slot of the row's
+    // last block: nx/2 + 1 is odd, the padded row length a multiple of 8) is
+    // read and dropped. Loads first and unconditional, as below.
+    typedef T t4 __attribute__((ext_vector_type(4)));
+    constexpr int NP = N / 4 + 1;  // pairs (m even, m <= N/2)
+    constexpr int RND2 = (NP + NT - 1) / NT;
+    const long long so0 = spec_row(d, v0 ? r0 : 0), so1 = spec_row(d, v1 ? r1 : 0);
+    t4 ya[RND2], yb[RND2];
+#pragma unroll
+    for (int t = 0; t < RND2; ++t) {
+      const int m = 2 * (q + t * NT);
+      const bool in = m <= N / 2;
+      const long long cm = spec_col(d, in ? m : 0);
+      const t4 a = *reinterpret_cast<const t4*>(S + so0 + cm), b = *reinterpret_cast<const t4*>(S + so1 + cm);
+      ya[t] = (in && v0) ? a : (t4)(T)0;
+      yb[t] = (in && v1) ? b : (t4)(T)0;
+    }
+#pragma unroll
+    for (int t = 0; t < RND2; ++t) {
+      const int m = 2 * (q + t * NT);
+      if (m <= N / 2) {
+        pack_bins<T>(lds, li, cx<T>{ya[t][0], ya[t][1]}, cx<T>{yb[t][0], yb[t][1]}, N, m);
+        if (m + 1 <= N / 2) pack_bins<T>(lds, li, cx<T>{ya[t][2], ya[t][3]}, cx<T>{yb[t][2], yb[t][3]}, N, m + 1);
+      }
+    }
+  } else {
     // nx/2 + 1 bins over NT threads: N/(2 NT) + 1 rounds, loads issued first
     // and unconditional (clamped bin; a missing row reads row 0), selected after
     constexpr int RND = N / (2 * NT) + 1;
