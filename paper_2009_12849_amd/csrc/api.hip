@@ -351,19 +351,21 @@ extern "C" monc_plan* monc_plan_create(int nx, int ny, int nz, double dx, double
   h.inv_nxny = 1.0 / ((double)nx * (double)ny);
   // stencil kernels walk (8 level x J row pair) tiles once a level of one
   // field outgrows an XCD's L2 share (4 MB); smaller grids stay in row order.
-  // The x-forward kernels take J row pairs of about 1 MB per level and field
-  // (8 to 64 pairs: 64 at 2048 FP32 points a row, 32 at 2048 FP64 or 4096
-  // FP32, 16 at 4096 FP64), the gradient J = 8 rows: each workgroup writes
-  // its spectral bins as short runs spread over the level, which a tile
-  // whose J pairs run at about the same time turns into longer runs, while
-  // the neighbour rows its stencil re-reads must still meet in L2. Measured
-  // at 2048^2 x 160 / 1024^2 x 256 (mixed divergence and residual 6-8 %
-  // faster with 64 than with 8); wider than 1 MB lost at 4096^2 x 64 FP64.
+  // The x-forward kernels take J row pairs of about 512 KB per level and
+  // field (8 to 64 pairs: 64 at 1024 FP32 points a row, 32 at 2048 FP32 or
+  // 1024 FP64, 16 at 2048 FP64 or 4096 FP32, 8 at 4096 FP64), the gradient
+  // J = 8 rows: each workgroup writes its spectral bins as short runs spread
+  // over the level, which a tile whose J pairs run at about the same time
+  // turns into longer runs, while the neighbour rows its stencil re-reads
+  // must still meet in L2. At 2048^2 x 160 (mixed) 32 pairs against 8: the
+  // divergence 2.47 -> 2.31 ms and the residual 3.45 -> 3.30 ms; 64 pairs
+  // were as fast but re-read 15-20 % more from HBM (traffic over
+  // algorithmic bytes 1.21 / 1.60 against 1.07 / 1.34).
   h.ptk = ((double)nx * ny * elem_bytes(dtype) >= 4.0 * (1 << 20)) ? 8 : 1;
   {
     const double pair_bytes = 2.0 * nx * elem_bytes(dtype);
     int j = 8;
-    while (j < 64 && 2 * j * pair_bytes <= (double)(1 << 20)) j *= 2;
+    while (j < 64 && 2 * j * pair_bytes <= (double)(1 << 19)) j *= 2;
     h.ptj = j;
   }
   h.rdxf = (float)h.rdx;

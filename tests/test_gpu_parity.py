@@ -206,8 +206,8 @@ def test_fp64_256x256x128_full_size():
                                          ((2048, 648, 6), "mixed")])
 def test_large_levels_tiled_stencil_order(shape, dtype):
     # a level of one field above 4 MB switches the stencil kernels to
-    # (8 level x 64 row pair) tiles (about 1 MB of rows: 64 pairs at these
-    # widths), and the gradient kernels to (8 level x 8 row) tiles where a
+    # (8 level x J row pair) tiles (about 512 KB of rows: J = 16 to 64 at
+    # these widths), and the gradient kernels to (8 level x 8 row) tiles where a
     # row is a whole number of blocks (nx = 1024 FP64, 2048 mixed); ragged in
     # both (324 or 432 pairs per level, 5..11 levels), compile-time (1024,
     # 1536, 2048) and runtime (864) x FFTs
