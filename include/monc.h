@@ -335,7 +335,9 @@ int monc_stream_probe(int kind, void* a, void* b, void* c, void* d, size_t bytes
  *            at most 1024 threads),
  *   out[5] = x-direction transforms (row pairs) per workgroup of the
  *            compile-time x-FFT kernels (at most 512 threads and 160 KB of
- *            LDS per workgroup; default 256 threads' worth),
+ *            LDS per workgroup; default 256 threads' worth; the mixed
+ *            path's residual kernel, at lengths whose transforms are
+ *            narrower than a wave, rounds it to whole waves),
  *   out[6] = elements per thread of the compile-time y-FFT kernels, i.e.
  *            their radix plan: 8 (radix-8 passes) or 16 (radix-16 passes);
  *            default 16 from ny = 2048 on, else 8. On MONC_MIXED plans with
