@@ -519,7 +519,11 @@ def test_tile_parameters_do_not_change_results(params):
     assert max(errs[:3]) <= TOL64 and errs[3] <= p_tolerance(g), errs
 
 
-@pytest.mark.parametrize("params", [[8, 8, 8, 16, 32], [8, 8, 8, 32, 8], [8, 8, 8, 64, 4]])
+# y tile widths 1 and 2 set spectral column blocks of 1 and 2 bins: with 1
+# the FP32 x kernels move one bin per lane, from 2 on two bins per 16-byte
+# access
+@pytest.mark.parametrize("params", [[8, 8, 8, 16, 32], [8, 8, 8, 32, 8], [8, 8, 8, 64, 4], [8, 8, 1, 0, 0],
+                                    [8, 8, 2, 0, 0]])
 def test_tile_parameters_mixed(params):
     g, u, v, w = _case((96, 48, 130), 18)
     errs_default, _, _ = mixed_case(g, u, v, w)
