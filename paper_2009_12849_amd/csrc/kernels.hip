@@ -564,7 +564,12 @@ __global__ void __launch_bounds__(512)
   const MemberDesc& d = *a.mem[mi];
   if (skipped(d)) return;
   const IoPtrs io = a.io[mi];
-  const int lb = xcd_local_block(a, mi);
+  // workgroups in launch order for the residual (1-7 % faster than grouped
+  // by XCD: 2048^2 x 160, 1024^2 x 256, 4096^2 x 64 and the ensemble), by XCD
+  // for the divergence (FP32 2 % faster that way at 2048^2 x 160; FP64 4 %
+  // slower there but 7 % faster at 4096^2 x 64) and the given-field mode
+  constexpr bool PLAIN = MODE == 1;
+  const int lb = PLAIN ? (int)blockIdx.x - a.block_start[mi] : xcd_local_block(a, mi);
   const int ipw = blockDim.x / NT;
   // scalar row contexts for the residual only, and only where a transform
   // spans whole waves (NT a multiple of 64: then no wave holds lanes of two
